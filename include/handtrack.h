@@ -1,0 +1,230 @@
+/*
+ * handtrack.h -- C ABI of libhandtrack.so, the MI355X (gfx950) hot path of model-based
+ * 26-DOF hand tracking: score particle-swarm particles (hand poses) against an RGB-D
+ * observation and move the swarm.
+ *
+ * What is computed (paper: "Recognition of 26 Degrees of Freedom of Hands Using Model-based
+ * approach and Depth-Color Images", arXiv:2005.07068):
+ *   - a pose h is the 26-vector of Eq. 1-3 (five fingers x (MP flexion, MP abduction, PIP,
+ *     DIP), then wrist x, y, z, theta_x, theta_y, theta_z); a two-hand particle is 52-D;
+ *   - the model depth image r_d(h, C) of section III.A is the exact nearest entry depth of a
+ *     sphere / closed cylinder / ellipsoid hand (section II.A) along each pixel ray;
+ *   - the cost is E(h, O) = D(O, h, C) + lambda_k kc(h) of Eq. 4-5 with d_m = 10 mm,
+ *     d_M = 40 mm, lambda = 20, lambda_k = 10, sums over every ROI pixel;
+ *   - the swarm moves by Eq. 6-7 with bounds (Tables 1-2) and the mutation of section III.B.
+ *
+ * Conventions shared by every call:
+ *   - Status: every entry point returns HT_OK or a negative ht_status and never throws;
+ *     ht_last_error() gives a thread-local message for the last failure.  Arguments are
+ *     validated on the host before anything is enqueued; on an error nothing is enqueued.
+ *   - Asynchrony: eval / grad / pso calls only enqueue work on the given HIP stream (NULL =
+ *     the legacy default stream) and never synchronise, so they can be captured in a HIP
+ *     graph once the context's workspace is reserved (ht_reserve); without a reservation a
+ *     call may grow the workspace with hipMalloc, which is refused during capture.
+ *   - Memory: "device" pointers are HIP device memory owned by the caller and must stay alive
+ *     until the enqueued work completes; the library deep-copies the model and observations
+ *     into memory owned by the context.
+ *   - Layout: poses are float32 [n_frames][n_particles][n_dof] row-major; costs are
+ *     float32 [n_frames][n_particles]; images are row-major [H][W].
+ *   - Non-finite pose components give cost = +inf and a zero gradient (not an error).
+ *   - A context is bound to one HIP device and is not thread-safe.
+ */
+#ifndef HANDTRACK_H
+#define HANDTRACK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ht_ctx ht_ctx;
+
+typedef enum {
+  HT_OK = 0,
+  HT_ERR_ARG = -1,          /* NULL pointer, size out of range, inconsistent shapes        */
+  HT_ERR_STATE = -2,        /* call before set_model / set_observation, unset frame slot   */
+  HT_ERR_OOM = -3,          /* device allocation failed                                    */
+  HT_ERR_HIP = -4,          /* a HIP runtime call failed (message names it)                */
+  HT_ERR_UNSUPPORTED = -5   /* valid request outside what this build supports              */
+} ht_status;
+
+enum { HT_SPHERE = 0, HT_CYLINDER = 1, HT_ELLIPSOID = 2 };
+enum { HT_PTR_HOST = 0, HT_PTR_DEVICE = 1 };
+
+/* Limits of this build. */
+#define HT_MAX_DOF 64
+#define HT_MAX_SEG 32
+#define HT_MAX_PRIM 128
+#define HT_MAX_KC 16
+#define HT_MAX_SLOTS 1024
+#define HT_MAX_ROI 4096
+
+/* Message of the last failed call on this thread ("" if none).  Valid until the next call. */
+const char* ht_last_error(void);
+
+/* Library version string. */
+const char* ht_version(void);
+
+/* Create a context on HIP device `hip_device`.  *out is set on success. */
+ht_status ht_create(ht_ctx** out, int hip_device);
+
+/* Destroy a context and free everything it owns.  NULL is a no-op.  The caller must make
+ * sure no enqueued work of this context is still running. */
+void ht_destroy(ht_ctx* ctx);
+
+/* Hand model (section II.A), read from host memory and deep-copied to the device.
+ * Kinematics: segment s is placed by parent * offset_s * Rot(axis_s0, h[dof_s0]) *
+ * Rot(axis_s1, h[dof_s1]); a root segment (parent -1) is placed by the six wrist parameters
+ * h[root_dof .. root_dof + 5] = (x, y, z, theta_x, theta_y, theta_z) as
+ * Trans(x, y, z) Rz(theta_z) Ry(theta_y) Rx(theta_x) * offset_s (Eq. 2; the rotation order is
+ * this library's reading).  Parents must precede their children.
+ * Primitives: type, segment, local frame (3x4 in the segment frame) and sizes:
+ *   HT_SPHERE     centre = frame origin, radius = size[0]
+ *   HT_CYLINDER   closed, flat caps; first cap centre = frame origin, axis = frame z,
+ *                 radius = size[0], length = size[1]
+ *   HT_ELLIPSOID  centre = frame origin, semi-axes size[0..2] along frame x, y, z
+ * kc (Eq. 5): sum over pairs of max(-(h[a] - h[b]), 0).
+ * Errors: HT_ERR_ARG for counts beyond the limits, a bad parent order, a non-unit axis, a
+ * dof index out of range, non-positive sizes or lo > hi. */
+typedef struct {
+  int32_t n_dof, n_seg, n_prim, n_kc;
+  const int32_t* seg_parent;     /* [n_seg], -1 = root                                      */
+  const int32_t* seg_root_dof;   /* [n_seg], first wrist dof of a root, else ignored         */
+  const double* seg_offset;      /* [n_seg][3][4] rotation | translation, mm                 */
+  const double* seg_joint_axis;  /* [n_seg][2][3] unit axes in the segment frame             */
+  const int32_t* seg_joint_dof;  /* [n_seg][2], -1 = no joint                                */
+  const int32_t* prim_type;      /* [n_prim] HT_SPHERE / HT_CYLINDER / HT_ELLIPSOID          */
+  const int32_t* prim_seg;       /* [n_prim]                                                 */
+  const double* prim_frame;      /* [n_prim][3][4]                                           */
+  const double* prim_size;       /* [n_prim][3], mm                                          */
+  const double* bounds_lo;       /* [n_dof] joint limits (Tables 1-2), rad / mm              */
+  const double* bounds_hi;       /* [n_dof]                                                  */
+  const uint8_t* mutate_mask;    /* [n_dof] 1 = re-drawn by the mutation step                */
+  const int32_t* kc_pairs;       /* [n_kc][2] (a, b): a is the finger nearer the thumb       */
+} ht_model;
+
+ht_status ht_set_model(ht_ctx* ctx, const ht_model* model);
+
+/* The checks of ht_set_model without a context or a device: HT_OK or HT_ERR_ARG. */
+ht_status ht_check_model(const ht_model* model);
+
+/* Pinhole camera C of section III.A (pixels); depth is camera z in mm.  The ray of pixel
+ * (u, v) has direction ((u - cx)/fx, (v - cy)/fy, 1). */
+typedef struct {
+  float fx, fy, cx, cy;
+} ht_camera;
+
+/* Observation O = (O_s, O_d) of section II.B for frame slot `frame_slot` (0..HT_MAX_SLOTS-1):
+ * depth_mm [H][W] (0 = undefined), skin [H][W] (nonzero = skin), camera and the background
+ * plane depth B (model misses render B; B <= 0 means no plane and misses render 0).
+ * `ptr_kind` says whether depth_mm / skin are host or device pointers.  The data are copied
+ * (stream-ordered on hip_stream); the caller may free them once the stream has passed this
+ * call.  May allocate (set-up call: not for graph capture).
+ * Errors: HT_ERR_ARG for W or H outside 1..HT_MAX_ROI, a bad slot, NULL data, fx or fy <= 0. */
+ht_status ht_set_observation(ht_ctx* ctx, int frame_slot, int W, int H, const uint16_t* depth_mm,
+                             const uint8_t* skin, ht_camera cam, float bg_depth_mm,
+                             int ptr_kind, void* hip_stream);
+
+/* Pre-allocate the workspace for up to `max_particles` particles in total (all frames of one
+ * call) over observations of up to `max_pixels` pixels each, so that later calls allocate
+ * nothing (required for graph capture).  HT_ERR_OOM on failure. */
+ht_status ht_reserve(ht_ctx* ctx, int max_particles, int max_pixels);
+
+/* Optional per-pixel outputs of ht_eval_particles for a single frame (n_frames == 1); each
+ * pointer may be NULL.  Device memory, [n_particles][H][W].  `slot` must repeat, on the host,
+ * the observation slot held in frame_slots[0] (it gives W, H and B for the images). */
+typedef struct {
+  int32_t slot;
+  float* depth;      /* r_d                                         */
+  uint8_t* hit;      /* model hit (nearest entry in front of B)      */
+  uint8_t* rm;       /* r_m of Eq. 4                                 */
+  int32_t* winner;   /* index of the nearest primitive, -1 on a miss */
+} ht_debug;
+
+/* E(h, O) (Eq. 5) for n_frames x n_particles poses.  frame_slots: device int32 [n_frames],
+ * the observation slot of each frame.  poses: device float32 [n_frames][n_particles][n_dof];
+ * cost: device float32 [n_frames][n_particles].  dbg may be NULL.
+ * Errors: HT_ERR_STATE before set_model, HT_ERR_ARG for NULL pointers or counts < 0,
+ * HT_ERR_UNSUPPORTED for dbg with n_frames != 1.  n_frames * n_particles == 0 is a no-op.
+ * The frame slots are read on the device: every slot used must have been set. */
+ht_status ht_eval_particles(ht_ctx* ctx, int n_frames, const int32_t* frame_slots,
+                            int n_particles, const float* poses, float* cost,
+                            const ht_debug* dbg, void* hip_stream);
+
+/* E and dE/dh.  The gradient is that of the clamped depth sum of Eq. 4 over the hit pixels
+ * (with sum(o_s or r_m) held fixed; it and the Dice term are piecewise constant) plus
+ * lambda_k dkc/dh.  grad: device float32 [n_frames][n_particles][n_dof].  pixel_mask: NULL for
+ * every pixel, else device uint8 [H][W] (n_frames must be 1): pixels with 0 are left out of
+ * the gradient (not of the cost).  Errors as ht_eval_particles. */
+ht_status ht_eval_particles_grad(ht_ctx* ctx, int n_frames, const int32_t* frame_slots,
+                                 int n_particles, const float* poses, float* cost, float* grad,
+                                 const uint8_t* pixel_mask, void* hip_stream);
+
+/* Swarm state, all device memory owned by the caller, float32 unless noted:
+ *   x, v, pbest_x [F][P][n_dof]; pbest_cost, cost [F][P]; gbest_x [F][n_dof];
+ *   gbest_cost [F]; gen: int32 [F] generation counters; frame_slots: int32 [F];
+ *   init_lo, init_hi [F][n_dof]: box of the initial positions (ht_pso_init). */
+typedef struct {
+  int32_t n_frames, n_particles;
+  const int32_t* frame_slots;
+  float *x, *v, *pbest_x, *pbest_cost, *gbest_x, *gbest_cost, *cost;
+  int32_t* gen;
+  const float *init_lo, *init_hi;
+  uint64_t seed;
+} ht_swarm;
+
+/* Swarm constants.  Plain PSO of the paper: c1 = 2.8, c2 = 1.3, w = 2/|2 - psi -
+ * sqrt(psi^2 - 4 psi)| (psi = c1 + c2), mutate_every = 3, mutate_frac = 0.5.  refine_topk > 0
+ * adds gradient refinement (not in the paper) of the refine_topk lowest-cost particles:
+ * refine_steps normalised steepest-descent steps in the eta-scaled space (eta_rot rad for
+ * angles, eta_trans mm for translations), halving the step up to 3 times until E drops. */
+typedef struct {
+  float w, c1, c2;
+  int32_t mutate_every;
+  float mutate_frac;
+  int32_t refine_topk, refine_steps;
+  float eta_rot, eta_trans;
+} ht_pso_params;
+
+/* Initialise: x ~ U[init_lo, init_hi] clamped to the joint limits (Philox4x32-10, stream 1),
+ * v = 0, best costs = +inf, gen = 0.  Enqueue-only.  HT_ERR_STATE before set_model. */
+ht_status ht_pso_init(ht_ctx* ctx, const ht_swarm* swarm, void* hip_stream);
+
+/* One generation (section III.B): evaluate E at x (into cost), refine the top-K if asked,
+ * update personal / global bests, then mutation (every mutate_every-th generation, the worst
+ * floor(P * mutate_frac) by current cost re-draw their mutate-mask dimensions) or Eq. 6-7 with
+ * clamping to the joint limits.  Random numbers: Philox4x32-10 keyed by the seed with counter
+ * (dim, frame * P + particle, generation, stream).  Enqueue-only; generation counters live on
+ * the device, so a captured sequence of calls can be replayed.
+ * Errors: HT_ERR_STATE before set_model, HT_ERR_ARG for bad pointers / counts / params. */
+ht_status ht_pso_step(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_params* params,
+                      void* hip_stream);
+
+/* A whole run: ht_pso_init followed by n_generations x ht_pso_step, captured once into a HIP
+ * graph (cached in the context per swarm / params / n_generations) and launched on
+ * hip_stream.  Requires ht_reserve to cover the swarm.  HT_ERR_HIP if capture fails. */
+ht_status ht_pso_run_graph(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_params* params,
+                           int n_generations, void* hip_stream);
+
+/* Launch shape of the batched persistent ray-cast kernel. */
+typedef struct {
+  int32_t tiles_per_item;   /* 8x8-pixel tiles per work item (one work item per workgroup) */
+  int32_t groups_per_cu;    /* persistent workgroups per compute unit                       */
+} ht_launch_config;
+
+ht_status ht_get_launch_config(ht_ctx* ctx, ht_launch_config* out);
+ht_status ht_set_launch_config(ht_ctx* ctx, const ht_launch_config* cfg);
+
+/* Autotune the launch shape on the given workload (timed with HIP events on hip_stream,
+ * synchronising it), keep the fastest in the context and return it in *out.
+ * The candidate list is tiles_per_item x groups_per_cu over small powers of two. */
+ht_status ht_autotune(ht_ctx* ctx, int n_frames, const int32_t* frame_slots, int n_particles,
+                      const float* poses, float* cost, int repeats, ht_launch_config* out,
+                      void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HANDTRACK_H */

@@ -1,0 +1,314 @@
+"""ctypes binding of libhandtrack.so (argument marshalling only).
+
+Device memory and streams come from PyTorch (ROCm): tensors are passed by ``data_ptr()`` and
+the current stream by ``torch.cuda.current_stream().cuda_stream``.  Every compute step runs in
+the library's HIP kernels; if the library is missing or fails, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhandtrack.so")
+
+HT_OK, HT_ERR_ARG, HT_ERR_STATE, HT_ERR_OOM, HT_ERR_HIP, HT_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+HT_PTR_HOST, HT_PTR_DEVICE = 0, 1
+_NAMES = {0: "HT_OK", -1: "HT_ERR_ARG", -2: "HT_ERR_STATE", -3: "HT_ERR_OOM", -4: "HT_ERR_HIP",
+          -5: "HT_ERR_UNSUPPORTED"}
+
+
+class HandtrackError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Model(C.Structure):
+    _fields_ = [
+        ("n_dof", C.c_int32), ("n_seg", C.c_int32), ("n_prim", C.c_int32), ("n_kc", C.c_int32),
+        ("seg_parent", C.c_void_p), ("seg_root_dof", C.c_void_p), ("seg_offset", C.c_void_p),
+        ("seg_joint_axis", C.c_void_p), ("seg_joint_dof", C.c_void_p),
+        ("prim_type", C.c_void_p), ("prim_seg", C.c_void_p), ("prim_frame", C.c_void_p),
+        ("prim_size", C.c_void_p), ("bounds_lo", C.c_void_p), ("bounds_hi", C.c_void_p),
+        ("mutate_mask", C.c_void_p), ("kc_pairs", C.c_void_p),
+    ]
+
+
+class Camera(C.Structure):
+    _fields_ = [("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class Debug(C.Structure):
+    _fields_ = [("slot", C.c_int32), ("depth", C.c_void_p), ("hit", C.c_void_p),
+                ("rm", C.c_void_p), ("winner", C.c_void_p)]
+
+
+class Swarm(C.Structure):
+    _fields_ = [
+        ("n_frames", C.c_int32), ("n_particles", C.c_int32), ("frame_slots", C.c_void_p),
+        ("x", C.c_void_p), ("v", C.c_void_p), ("pbest_x", C.c_void_p), ("pbest_cost", C.c_void_p),
+        ("gbest_x", C.c_void_p), ("gbest_cost", C.c_void_p), ("cost", C.c_void_p),
+        ("gen", C.c_void_p), ("init_lo", C.c_void_p), ("init_hi", C.c_void_p),
+        ("seed", C.c_uint64),
+    ]
+
+
+class PsoParams(C.Structure):
+    _fields_ = [("w", C.c_float), ("c1", C.c_float), ("c2", C.c_float),
+                ("mutate_every", C.c_int32), ("mutate_frac", C.c_float),
+                ("refine_topk", C.c_int32), ("refine_steps", C.c_int32),
+                ("eta_rot", C.c_float), ("eta_trans", C.c_float)]
+
+
+class LaunchConfig(C.Structure):
+    _fields_ = [("tiles_per_item", C.c_int32), ("groups_per_cu", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhandtrack.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2005_07068_amd.build.build()")
+    lib = C.CDLL(path)
+    P, I, F, S = C.c_void_p, C.c_int, C.c_float, C.c_int
+    lib.ht_last_error.restype = C.c_char_p
+    lib.ht_version.restype = C.c_char_p
+    lib.ht_create.argtypes = [C.POINTER(C.c_void_p), I]
+    lib.ht_destroy.argtypes = [P]
+    lib.ht_destroy.restype = None
+    lib.ht_set_model.argtypes = [P, C.POINTER(Model)]
+    lib.ht_check_model.argtypes = [C.POINTER(Model)]
+    lib.ht_check_model.restype = S
+    lib.ht_set_observation.argtypes = [P, I, I, I, P, P, Camera, F, I, P]
+    lib.ht_reserve.argtypes = [P, I, I]
+    lib.ht_eval_particles.argtypes = [P, I, P, I, P, P, C.POINTER(Debug), P]
+    lib.ht_eval_particles_grad.argtypes = [P, I, P, I, P, P, P, P, P]
+    lib.ht_pso_init.argtypes = [P, C.POINTER(Swarm), P]
+    lib.ht_pso_step.argtypes = [P, C.POINTER(Swarm), C.POINTER(PsoParams), P]
+    lib.ht_pso_run_graph.argtypes = [P, C.POINTER(Swarm), C.POINTER(PsoParams), I, P]
+    lib.ht_get_launch_config.argtypes = [P, C.POINTER(LaunchConfig)]
+    lib.ht_set_launch_config.argtypes = [P, C.POINTER(LaunchConfig)]
+    lib.ht_autotune.argtypes = [P, I, P, I, P, P, I, C.POINTER(LaunchConfig), P]
+    for name in ("ht_create", "ht_set_model", "ht_set_observation", "ht_reserve",
+                 "ht_eval_particles", "ht_eval_particles_grad", "ht_pso_init", "ht_pso_step",
+                 "ht_pso_run_graph", "ht_get_launch_config", "ht_set_launch_config",
+                 "ht_autotune"):
+        getattr(lib, name).restype = S
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != HT_OK:
+        raise HandtrackError(status, load_library().ht_last_error().decode())
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def pso_params(w=0.72, c1=2.05, c2=2.05, mutate_every=3, mutate_frac=0.5, refine_topk=0,
+               refine_steps=0, eta_rot=0.02, eta_trans=2.0) -> PsoParams:
+    return PsoParams(w, c1, c2, mutate_every, mutate_frac, refine_topk, refine_steps, eta_rot,
+                     eta_trans)
+
+
+def model_struct(m: dict):
+    """ctypes ht_model over contiguous copies of the tables; returns (struct, arrays to keep)."""
+    arrs = {
+        "seg_parent": np.ascontiguousarray(m["seg_parent"], np.int32),
+        "seg_root_dof": np.ascontiguousarray(m["seg_root_dof"], np.int32),
+        "seg_offset": np.ascontiguousarray(m["seg_offset"], np.float64),
+        "seg_joint_axis": np.ascontiguousarray(m["seg_joint_axis"], np.float64),
+        "seg_joint_dof": np.ascontiguousarray(m["seg_joint_dof"], np.int32),
+        "prim_type": np.ascontiguousarray(m["prim_type"], np.int32),
+        "prim_seg": np.ascontiguousarray(m["prim_seg"], np.int32),
+        "prim_frame": np.ascontiguousarray(m["prim_frame"], np.float64),
+        "prim_size": np.ascontiguousarray(m["prim_size"], np.float64),
+        "bounds_lo": np.ascontiguousarray(m["bounds_lo"], np.float64),
+        "bounds_hi": np.ascontiguousarray(m["bounds_hi"], np.float64),
+        "mutate_mask": np.ascontiguousarray(m["mutate_mask"], np.uint8),
+        "kc_pairs": np.ascontiguousarray(m["kc_pairs"], np.int32).reshape(-1, 2),
+    }
+    mm = Model(int(m["n_dof"]), int(m["n_seg"]), int(m["n_prim"]), len(arrs["kc_pairs"]),
+               *[a.ctypes.data for a in arrs.values()])
+    return mm, arrs
+
+
+def check_model(m: dict) -> None:
+    """Validate model tables with the library's checks (no device needed)."""
+    mm, keep = model_struct(m)
+    _check(load_library().ht_check_model(C.byref(mm)))
+    del keep
+
+
+class Context:
+    """One library context on a HIP device (see include/handtrack.h for every call)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.handle = C.c_void_p()
+        _check(self.lib.ht_create(C.byref(self.handle), device))
+        self.device = device
+        self._keep = []
+        self.n_dof = 0
+        self.slots = {}
+
+    def close(self):
+        if self.handle:
+            self.lib.ht_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up -------------------------------------------------------------------------
+    def set_model(self, m: dict):
+        mm, keep = model_struct(m)
+        _check(self.lib.ht_set_model(self.handle, C.byref(mm)))
+        del keep
+        self.n_dof = int(m["n_dof"])
+
+    def set_observation(self, slot: int, depth, skin, cam, bg: float):
+        """depth: uint16 [H, W], skin: uint8 [H, W] as numpy arrays (host) or torch tensors
+        (host or device)."""
+        import torch
+        if isinstance(depth, torch.Tensor):
+            kind = HT_PTR_DEVICE if depth.is_cuda else HT_PTR_HOST
+            depth_t = depth.contiguous()
+            skin_t = skin.to(torch.uint8).contiguous()
+            H, W = depth_t.shape
+            dp, sp = depth_t.data_ptr(), skin_t.data_ptr()
+            self._keep = [depth_t, skin_t]
+        else:
+            kind = HT_PTR_HOST
+            d = np.ascontiguousarray(depth, np.uint16)
+            s = np.ascontiguousarray(skin, np.uint8)
+            H, W = d.shape
+            dp, sp = d.ctypes.data, s.ctypes.data
+            self._keep = [d, s]
+        fx, fy, cx, cy = (float(c) for c in cam)
+        _check(self.lib.ht_set_observation(self.handle, slot, W, H, C.c_void_p(dp),
+                                           C.c_void_p(sp), Camera(fx, fy, cx, cy), float(bg),
+                                           kind, _stream()))
+        self.slots[slot] = (W, H, float(bg))
+
+    def reserve(self, max_particles: int, max_pixels: int):
+        _check(self.lib.ht_reserve(self.handle, max_particles, max_pixels))
+
+    # -- evaluation ---------------------------------------------------------------------
+    def eval(self, poses, frame_slots, cost=None, debug=None):
+        """poses: float32 cuda tensor [F, P, D] (or [P, D] for one frame); frame_slots: int32
+        cuda tensor [F].  Returns cost [F, P] (or [P])."""
+        import torch
+        squeeze = poses.dim() == 2
+        p3 = poses.unsqueeze(0) if squeeze else poses
+        F, P, D = p3.shape
+        if D != self.n_dof:
+            raise ValueError(f"poses have {D} parameters, model has {self.n_dof}")
+        p3 = p3.contiguous()
+        if cost is None:
+            cost = torch.empty((F, P), device=poses.device, dtype=torch.float32)
+        dbg = None
+        if debug is not None:
+            dbg = Debug(int(debug["slot"]), *[_ptr(debug.get(k)) for k in
+                                               ("depth", "hit", "rm", "winner")])
+        _check(self.lib.ht_eval_particles(self.handle, F, _ptr(frame_slots), P, _ptr(p3),
+                                          _ptr(cost), C.byref(dbg) if dbg else None, _stream()))
+        return cost[0] if squeeze else cost
+
+    def eval_grad(self, poses, frame_slots, pixel_mask=None):
+        import torch
+        squeeze = poses.dim() == 2
+        p3 = (poses.unsqueeze(0) if squeeze else poses).contiguous()
+        F, P, D = p3.shape
+        cost = torch.empty((F, P), device=poses.device, dtype=torch.float32)
+        grad = torch.empty((F, P, D), device=poses.device, dtype=torch.float32)
+        _check(self.lib.ht_eval_particles_grad(self.handle, F, _ptr(frame_slots), P, _ptr(p3),
+                                               _ptr(cost), _ptr(grad), _ptr(pixel_mask),
+                                               _stream()))
+        if squeeze:
+            return cost[0], grad[0]
+        return cost, grad
+
+    # -- swarm --------------------------------------------------------------------------
+    def swarm(self, frame_slots, n_particles: int, init_lo, init_hi, seed: int):
+        """Allocate swarm state tensors; returns a dict (tensors) and its ctypes struct."""
+        import torch
+        dev = frame_slots.device
+        F, D = int(frame_slots.numel()), self.n_dof
+        t = {
+            "frame_slots": frame_slots,
+            "x": torch.zeros((F, n_particles, D), device=dev),
+            "v": torch.zeros((F, n_particles, D), device=dev),
+            "pbest_x": torch.zeros((F, n_particles, D), device=dev),
+            "pbest_cost": torch.zeros((F, n_particles), device=dev),
+            "gbest_x": torch.zeros((F, D), device=dev),
+            "gbest_cost": torch.zeros((F,), device=dev),
+            "cost": torch.zeros((F, n_particles), device=dev),
+            "gen": torch.zeros((F,), device=dev, dtype=torch.int32),
+            "init_lo": init_lo.to(dev, torch.float32).reshape(F, D).contiguous(),
+            "init_hi": init_hi.to(dev, torch.float32).reshape(F, D).contiguous(),
+        }
+        s = Swarm(F, n_particles, _ptr(t["frame_slots"]), _ptr(t["x"]), _ptr(t["v"]),
+                  _ptr(t["pbest_x"]), _ptr(t["pbest_cost"]), _ptr(t["gbest_x"]),
+                  _ptr(t["gbest_cost"]), _ptr(t["cost"]), _ptr(t["gen"]), _ptr(t["init_lo"]),
+                  _ptr(t["init_hi"]), C.c_uint64(seed))
+        t["_struct"] = s
+        return t
+
+    def pso_init(self, sw):
+        _check(self.lib.ht_pso_init(self.handle, C.byref(sw["_struct"]), _stream()))
+
+    def pso_step(self, sw, params: PsoParams):
+        _check(self.lib.ht_pso_step(self.handle, C.byref(sw["_struct"]), C.byref(params),
+                                    _stream()))
+
+    def pso_run_graph(self, sw, params: PsoParams, n_generations: int):
+        _check(self.lib.ht_pso_run_graph(self.handle, C.byref(sw["_struct"]), C.byref(params),
+                                         n_generations, _stream()))
+
+    # -- launch shape -------------------------------------------------------------------
+    def launch_config(self):
+        lc = LaunchConfig()
+        _check(self.lib.ht_get_launch_config(self.handle, C.byref(lc)))
+        return lc.tiles_per_item, lc.groups_per_cu
+
+    def set_launch_config(self, tiles_per_item: int, groups_per_cu: int):
+        lc = LaunchConfig(tiles_per_item, groups_per_cu)
+        _check(self.lib.ht_set_launch_config(self.handle, C.byref(lc)))
+
+    def autotune(self, poses, frame_slots, repeats: int = 5):
+        import torch
+        F, P, D = poses.shape
+        cost = torch.empty((F, P), device=poses.device, dtype=torch.float32)
+        lc = LaunchConfig()
+        _check(self.lib.ht_autotune(self.handle, F, _ptr(frame_slots), P, _ptr(poses.contiguous()),
+                                    _ptr(cost), repeats, C.byref(lc), _stream()))
+        return lc.tiles_per_item, lc.groups_per_cu
+
+
+def header_functions(header_path: str | None = None) -> list[str]:
+    """Names of the functions declared in include/handtrack.h."""
+    import re
+    if header_path is None:
+        header_path = os.path.join(os.path.dirname(HERE), "include", "handtrack.h")
+    text = open(header_path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ht_[a-z_]+)\s*\(", text)))

@@ -1,0 +1,794 @@
+// Host side of the C ABI: context, validation, device copies of the model and observations,
+// workspace management and kernel launches.  Every entry point validates its arguments before
+// enqueuing anything and reports failures through ht_status + ht_last_error().
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "handtrack.h"
+#include "ht_device.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+ht_status fail(ht_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HT_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? HT_ERR_OOM : HT_ERR_HIP, "%s: %s", #call,  \
+                  hipGetErrorString(e_));                                                  \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+struct SlotHost {
+  bool set = false;
+  int W = 0, H = 0, TW = 0, TH = 0;
+  size_t cap_tiles = 0, cap_px = 0;
+  uint32_t* words = nullptr;
+  float* tile_td = nullptr;
+  int* tile_skin = nullptr;
+  double* totals = nullptr;
+  uint16_t* stage_depth = nullptr;
+  uint8_t* stage_skin = nullptr;
+  ht::FrameSlot entry{};
+};
+
+struct GraphKey {
+  ht_swarm sw;
+  ht_pso_params p;
+  int gens;
+  bool operator<(const GraphKey& o) const { return std::memcmp(this, &o, sizeof *this) < 0; }
+};
+
+}  // namespace
+
+struct ht_ctx {
+  int device = 0;
+  int n_cu = 256;
+  bool has_model = false;
+  int n_dof = 0, n_seg = 0, n_prim = 0;
+  ht::TypeMasks tmask{};
+  ht::DevModel* d_model = nullptr;
+  ht::DevModel h_model{};
+  ht::FrameSlot* d_slots = nullptr;
+  SlotHost slots[HT_MAX_SLOTS];
+  // evaluation workspace
+  ht::Workspace ws{};
+  int cap_particles = 0;
+  int cap_items = 0;
+  int cap_tiles = 0;
+  bool cap_wrench = false;
+  ht_launch_config lc{16, 4};
+  // swarm refinement scratch
+  float* r_x = nullptr;       // [cap_ref][n_dof] current positions of the refined particles
+  float* r_cost = nullptr;    // [cap_ref]
+  float* r_grad = nullptr;    // [cap_ref][n_dof]
+  float* r_cand = nullptr;    // [4 * cap_ref][n_dof]
+  float* r_ccost = nullptr;   // [4 * cap_ref]
+  int* r_sel = nullptr;       // [cap_ref]
+  int* r_active = nullptr;    // [cap_ref]
+  int* r_slots = nullptr;     // [4 * cap_ref] frame slot of each refined particle
+  int cap_ref = 0;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+
+  int max_tiles() const {
+    int m = 0;
+    for (const auto& s : slots)
+      if (s.set) m = std::max(m, s.TW * s.TH);
+    return m;
+  }
+};
+
+namespace {
+
+constexpr int kMinTilesPerItem = 4;
+
+void invalidate_graphs(ht_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+void free_workspace(ht_ctx* c) {
+  invalidate_graphs(c);
+  dfree(c->ws.recs);
+  dfree(c->ws.boxes);
+  dfree(c->ws.pinfo);
+  dfree(c->ws.dof_frame);
+  dfree(c->ws.seg_org);
+  dfree(c->ws.item_off);
+  dfree(c->ws.item_map);
+  dfree(c->ws.partial);
+  dfree(c->ws.wrench);
+  dfree(c->ws.counters);
+  c->cap_particles = c->cap_items = c->cap_tiles = 0;
+  c->cap_wrench = false;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Make sure the workspace holds n_total particles over observations of max_tiles tiles.
+ht_status ensure_workspace(ht_ctx* c, int n_total, int max_tiles, bool grad, hipStream_t s) {
+  const long long items_ll =
+      (long long)n_total * ((max_tiles + kMinTilesPerItem - 1) / kMinTilesPerItem);
+  if (items_ll > (1ll << 30)) return fail(HT_ERR_ARG, "workload too large: %lld work items", items_ll);
+  const int items = (int)std::max<long long>(items_ll, 1);
+  const bool ok = n_total <= c->cap_particles && items <= c->cap_items &&
+                  max_tiles <= c->cap_tiles && (!grad || c->cap_wrench);
+  if (ok) return HT_OK;
+  if (capturing(s))
+    return fail(HT_ERR_STATE, "workspace too small during graph capture; call ht_reserve first");
+  HT_HIP(hipDeviceSynchronize());
+  const int np = std::max(n_total, c->cap_particles);
+  const int nt = std::max(max_tiles, c->cap_tiles);
+  const int ni = std::max<long long>(items, (long long)np * ((nt + kMinTilesPerItem - 1) / kMinTilesPerItem));
+  const bool wr = grad || c->cap_wrench;
+  free_workspace(c);
+  auto& w = c->ws;
+  HT_HIP(hipMalloc(&w.recs, (size_t)np * c->n_prim * ht::kRec * sizeof(float)));
+  HT_HIP(hipMalloc(&w.boxes, (size_t)np * c->n_prim * sizeof(int4)));
+  HT_HIP(hipMalloc(&w.pinfo, (size_t)np * sizeof(ht::PInfo)));
+  HT_HIP(hipMalloc(&w.dof_frame, (size_t)np * c->n_dof * 8 * sizeof(float)));
+  HT_HIP(hipMalloc(&w.seg_org, (size_t)np * c->n_seg * 4 * sizeof(float)));
+  HT_HIP(hipMalloc(&w.item_off, (size_t)(np + 1) * sizeof(int)));
+  HT_HIP(hipMalloc(&w.item_map, (size_t)ni * sizeof(int)));
+  HT_HIP(hipMalloc(&w.partial, (size_t)ni * sizeof(ht::Partial)));
+  if (wr) HT_HIP(hipMalloc(&w.wrench, (size_t)ni * c->n_seg * 6 * sizeof(float)));
+  HT_HIP(hipMalloc(&w.counters, 4 * sizeof(int)));
+  HT_HIP(hipMemset(w.counters, 0, 4 * sizeof(int)));
+  w.max_items = ni;
+  c->cap_tiles = nt;
+  c->cap_particles = np;
+  c->cap_items = ni;
+  c->cap_wrench = wr;
+  return HT_OK;
+}
+
+ht_status check_ctx(ht_ctx* c, bool need_model = true) {
+  if (!c) return fail(HT_ERR_ARG, "context is NULL");
+  if (need_model && !c->has_model) return fail(HT_ERR_STATE, "no model: call ht_set_model first");
+  return HT_OK;
+}
+
+ht_status check_slots_set(ht_ctx* c) {
+  for (const auto& s : c->slots)
+    if (s.set) return HT_OK;
+  return fail(HT_ERR_STATE, "no observation: call ht_set_observation first");
+}
+
+}  // namespace
+
+namespace ht {
+
+// Evaluation shared by ht_eval_particles, ht_eval_particles_grad and the swarm step.
+ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_particles,
+                    const float* poses, float* cost, float* grad, const uint8_t* pixel_mask,
+                    const ht_debug* dbg, hipStream_t s) {
+  const int n_total = n_frames * n_particles;
+  if (n_total == 0) return HT_OK;
+  ht_status st = ensure_workspace(c, n_total, c->max_tiles(), grad != nullptr, s);
+  if (st != HT_OK) return st;
+  EvalArgs a{};
+  a.model = c->d_model;
+  a.slots = c->d_slots;
+  a.frame_slots = frame_slots;
+  a.n_frames = n_frames;
+  a.n_particles = n_particles;
+  a.poses = poses;
+  a.cost = cost;
+  a.grad = grad;
+  a.pixel_mask = pixel_mask;
+  if (dbg) {
+    a.dbg = *dbg;
+    const SlotHost& sh = c->slots[dbg->slot];
+    a.dbg_W = sh.W;
+    a.dbg_H = sh.H;
+    a.dbg_bg = sh.entry.bg;
+  }
+  a.type_masks = c->tmask;
+  a.tiles_per_item = c->lc.tiles_per_item;
+  const long long bound = (long long)n_total *
+                          ((c->max_tiles() + a.tiles_per_item - 1) / a.tiles_per_item);
+  a.grid = (int)std::max<long long>(1, std::min<long long>((long long)c->n_cu * c->lc.groups_per_cu,
+                                                           bound));
+  a.n_prim = c->n_prim;
+  a.n_seg = c->n_seg;
+  a.n_dof = c->n_dof;
+  HT_HIP(launch_eval(a, c->ws, s));
+  return HT_OK;
+}
+
+}  // namespace ht
+
+extern "C" {
+
+const char* ht_last_error(void) { return g_err.c_str(); }
+
+const char* ht_version(void) { return "handtrack 0.1 (gfx950)"; }
+
+ht_status ht_create(ht_ctx** out, int hip_device) {
+  g_err.clear();
+  if (!out) return fail(HT_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HT_HIP(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n)
+    return fail(HT_ERR_ARG, "device %d out of range (%d devices)", hip_device, n);
+  DeviceGuard g(hip_device);
+  hipDeviceProp_t prop;
+  HT_HIP(hipGetDeviceProperties(&prop, hip_device));
+  ht_ctx* c = new ht_ctx();
+  c->device = hip_device;
+  c->n_cu = prop.multiProcessorCount;
+  hipError_t e = hipMalloc(&c->d_slots, HT_MAX_SLOTS * sizeof(ht::FrameSlot));
+  if (e == hipSuccess) e = hipMemset(c->d_slots, 0, HT_MAX_SLOTS * sizeof(ht::FrameSlot));
+  if (e == hipSuccess) e = hipMalloc(&c->d_model, sizeof(ht::DevModel));
+  if (e != hipSuccess) {
+    ht_destroy(c);
+    return fail(HT_ERR_OOM, "context allocation failed: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return HT_OK;
+}
+
+void ht_destroy(ht_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  free_workspace(c);
+  for (auto& s : c->slots) {
+    dfree(s.words);
+    dfree(s.tile_td);
+    dfree(s.tile_skin);
+    dfree(s.totals);
+    dfree(s.stage_depth);
+    dfree(s.stage_skin);
+  }
+  dfree(c->r_x);
+  dfree(c->r_cost);
+  dfree(c->r_grad);
+  dfree(c->r_cand);
+  dfree(c->r_ccost);
+  dfree(c->r_sel);
+  dfree(c->r_active);
+  dfree(c->r_slots);
+  dfree(c->d_slots);
+  dfree(c->d_model);
+  delete c;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validate the host model tables and lay them out for the device.
+ht_status build_model(const ht_model* m, ht::DevModel& d, ht::TypeMasks& tm) {
+  if (!m) return fail(HT_ERR_ARG, "model is NULL");
+  if (m->n_dof <= 0 || m->n_dof > HT_MAX_DOF) return fail(HT_ERR_ARG, "n_dof %d out of 1..%d", m->n_dof, HT_MAX_DOF);
+  if (m->n_seg <= 0 || m->n_seg > HT_MAX_SEG) return fail(HT_ERR_ARG, "n_seg %d out of 1..%d", m->n_seg, HT_MAX_SEG);
+  if (m->n_prim <= 0 || m->n_prim > HT_MAX_PRIM) return fail(HT_ERR_ARG, "n_prim %d out of 1..%d", m->n_prim, HT_MAX_PRIM);
+  if (m->n_kc < 0 || m->n_kc > HT_MAX_KC) return fail(HT_ERR_ARG, "n_kc %d out of 0..%d", m->n_kc, HT_MAX_KC);
+  if (!m->seg_parent || !m->seg_root_dof || !m->seg_offset || !m->seg_joint_axis ||
+      !m->seg_joint_dof || !m->prim_type || !m->prim_seg || !m->prim_frame || !m->prim_size ||
+      !m->bounds_lo || !m->bounds_hi || !m->mutate_mask || (m->n_kc && !m->kc_pairs))
+    return fail(HT_ERR_ARG, "model table pointer is NULL");
+  std::memset(&d, 0, sizeof d);
+  d.n_dof = m->n_dof;
+  d.n_seg = m->n_seg;
+  d.n_prim = m->n_prim;
+  d.n_kc = m->n_kc;
+  std::vector<int> used(m->n_dof, 0);
+  for (int s = 0; s < m->n_seg; ++s) {
+    const int par = m->seg_parent[s];
+    if (par >= s || par < -1) return fail(HT_ERR_ARG, "segment %d: parent %d must precede it", s, par);
+    d.seg_parent[s] = par;
+    d.seg_depth[s] = par < 0 ? 0 : d.seg_depth[par] + 1;
+    d.max_depth = std::max(d.max_depth, d.seg_depth[s]);
+    if (par < 0) {
+      const int b = m->seg_root_dof[s];
+      if (b < 0 || b + 6 > m->n_dof) return fail(HT_ERR_ARG, "segment %d: root dof %d out of range", s, b);
+      d.seg_root_dof[s] = b;
+      for (int i = 0; i < 6; ++i) used[b + i]++;
+      for (int i = 0; i < 3; ++i) d.dof_trans[b + i] = 1;
+    } else {
+      d.seg_root_dof[s] = -1;
+    }
+    for (int i = 0; i < 12; ++i) d.seg_off[s][i] = m->seg_offset[s * 12 + i];
+    for (int j = 0; j < 2; ++j) {
+      const int dof = m->seg_joint_dof[s * 2 + j];
+      if (dof < -1 || dof >= m->n_dof) return fail(HT_ERR_ARG, "segment %d: joint dof %d out of range", s, dof);
+      d.seg_dof[s][j] = dof;
+      double n2 = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        d.seg_axis[s][j][i] = m->seg_joint_axis[(s * 2 + j) * 3 + i];
+        n2 += d.seg_axis[s][j][i] * d.seg_axis[s][j][i];
+      }
+      if (dof >= 0) {
+        if (std::fabs(n2 - 1.0) > 1e-9) return fail(HT_ERR_ARG, "segment %d: joint axis %d is not a unit vector", s, j);
+        used[dof]++;
+      }
+    }
+  }
+  for (int j = 0; j < m->n_dof; ++j)
+    if (used[j] > 1) return fail(HT_ERR_ARG, "pose parameter %d drives more than one joint", j);
+  // segments moved by each pose parameter: the driven segment and its descendants
+  for (int s = 0; s < m->n_seg; ++s) {
+    for (int q = s; q >= 0; q = d.seg_parent[q]) {
+      for (int j = 0; j < 2; ++j)
+        if (d.seg_dof[q][j] >= 0) d.dof_desc[d.seg_dof[q][j]] |= 1u << s;
+      if (d.seg_parent[q] < 0)
+        for (int i = 0; i < 6; ++i) d.dof_desc[d.seg_root_dof[q] + i] |= 1u << s;
+    }
+  }
+  tm = ht::TypeMasks{};
+  for (int k = 0; k < m->n_prim; ++k) {
+    const int t = m->prim_type[k], s = m->prim_seg[k];
+    if (t < HT_SPHERE || t > HT_ELLIPSOID) return fail(HT_ERR_ARG, "primitive %d: bad type %d", k, t);
+    if (s < 0 || s >= m->n_seg) return fail(HT_ERR_ARG, "primitive %d: segment %d out of range", k, s);
+    d.prim_type[k] = t;
+    d.prim_seg[k] = s;
+    for (int i = 0; i < 12; ++i) d.prim_frame[k][i] = m->prim_frame[k * 12 + i];
+    const int need = t == HT_SPHERE ? 1 : (t == HT_CYLINDER ? 2 : 3);
+    for (int i = 0; i < 3; ++i) {
+      d.prim_size[k][i] = m->prim_size[k * 3 + i];
+      if (i < need && !(d.prim_size[k][i] > 0.0)) return fail(HT_ERR_ARG, "primitive %d: size %d must be > 0", k, i);
+    }
+    tm.m[t][k / 64] |= 1ull << (k % 64);
+  }
+  for (int j = 0; j < m->n_dof; ++j) {
+    if (!(m->bounds_lo[j] <= m->bounds_hi[j])) return fail(HT_ERR_ARG, "bounds of dof %d: lo > hi", j);
+    d.lo[j] = (float)m->bounds_lo[j];
+    d.hi[j] = (float)m->bounds_hi[j];
+    d.mutate[j] = m->mutate_mask[j] ? 1 : 0;
+  }
+  for (int i = 0; i < m->n_kc; ++i) {
+    const int a = m->kc_pairs[2 * i], b = m->kc_pairs[2 * i + 1];
+    if (a < 0 || a >= m->n_dof || b < 0 || b >= m->n_dof) return fail(HT_ERR_ARG, "kc pair %d out of range", i);
+    d.kc_a[i] = a;
+    d.kc_b[i] = b;
+  }
+  return HT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ht_status ht_check_model(const ht_model* m) {
+  g_err.clear();
+  ht::DevModel d;
+  ht::TypeMasks tm;
+  return build_model(m, d, tm);
+}
+
+ht_status ht_set_model(ht_ctx* c, const ht_model* m) {
+  g_err.clear();
+  ht_status st = check_ctx(c, false);
+  if (st != HT_OK) return st;
+  ht::DevModel d;
+  ht::TypeMasks tm;
+  if ((st = build_model(m, d, tm)) != HT_OK) return st;
+  DeviceGuard g(c->device);
+  HT_HIP(hipDeviceSynchronize());
+  invalidate_graphs(c);
+  HT_HIP(hipMemcpy(c->d_model, &d, sizeof d, hipMemcpyHostToDevice));
+  c->h_model = d;
+  c->tmask = tm;
+  if (c->has_model && (c->n_dof != m->n_dof || c->n_seg != m->n_seg || c->n_prim != m->n_prim)) {
+    free_workspace(c);
+    c->cap_ref = 0;
+  }
+  c->n_dof = m->n_dof;
+  c->n_seg = m->n_seg;
+  c->n_prim = m->n_prim;
+  c->has_model = true;
+  return HT_OK;
+}
+
+
+ht_status ht_set_observation(ht_ctx* c, int slot, int W, int H, const uint16_t* depth_mm,
+                             const uint8_t* skin, ht_camera cam, float bg, int ptr_kind,
+                             void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c, false);
+  if (st != HT_OK) return st;
+  if (slot < 0 || slot >= HT_MAX_SLOTS) return fail(HT_ERR_ARG, "frame slot %d out of 0..%d", slot, HT_MAX_SLOTS - 1);
+  if (W < 1 || H < 1 || W > HT_MAX_ROI || H > HT_MAX_ROI) return fail(HT_ERR_ARG, "ROI %dx%d out of 1..%d", W, H, HT_MAX_ROI);
+  if (!depth_mm || !skin) return fail(HT_ERR_ARG, "observation pointer is NULL");
+  if (!(cam.fx > 0.0f) || !(cam.fy > 0.0f) || !std::isfinite(cam.cx) || !std::isfinite(cam.cy))
+    return fail(HT_ERR_ARG, "camera needs fx, fy > 0 and finite cx, cy");
+  if (!std::isfinite(bg)) return fail(HT_ERR_ARG, "background depth must be finite");
+  if (ptr_kind != HT_PTR_HOST && ptr_kind != HT_PTR_DEVICE) return fail(HT_ERR_ARG, "bad ptr_kind %d", ptr_kind);
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  SlotHost& sh = c->slots[slot];
+  const int TW = (W + ht::kTile - 1) / ht::kTile, TH = (H + ht::kTile - 1) / ht::kTile;
+  const size_t n_tiles = (size_t)TW * TH, n_px = (size_t)W * H;
+  // graphs captured for smaller observations would overrun their work lists
+  if ((int)n_tiles > c->cap_tiles) invalidate_graphs(c);
+  if (n_tiles > sh.cap_tiles) {
+    HT_HIP(hipDeviceSynchronize());
+    dfree(sh.words);
+    dfree(sh.tile_td);
+    dfree(sh.tile_skin);
+    HT_HIP(hipMalloc(&sh.words, n_tiles * ht::kTilePx * sizeof(uint32_t)));
+    HT_HIP(hipMalloc(&sh.tile_td, n_tiles * sizeof(float)));
+    HT_HIP(hipMalloc(&sh.tile_skin, n_tiles * sizeof(int)));
+    if (!sh.totals) HT_HIP(hipMalloc(&sh.totals, 2 * sizeof(double)));
+    sh.cap_tiles = n_tiles;
+  }
+  const uint16_t* dsrc = depth_mm;
+  const uint8_t* ssrc = skin;
+  if (ptr_kind == HT_PTR_HOST) {
+    if (n_px > sh.cap_px) {
+      HT_HIP(hipDeviceSynchronize());
+      dfree(sh.stage_depth);
+      dfree(sh.stage_skin);
+      HT_HIP(hipMalloc(&sh.stage_depth, n_px * sizeof(uint16_t)));
+      HT_HIP(hipMalloc(&sh.stage_skin, n_px));
+      sh.cap_px = n_px;
+    }
+    HT_HIP(hipMemcpyAsync(sh.stage_depth, depth_mm, n_px * sizeof(uint16_t), hipMemcpyHostToDevice, s));
+    HT_HIP(hipMemcpyAsync(sh.stage_skin, skin, n_px, hipMemcpyHostToDevice, s));
+    dsrc = sh.stage_depth;
+    ssrc = sh.stage_skin;
+  }
+  HT_HIP(ht::launch_pack_observation(dsrc, ssrc, W, H, TW, TH, sh.words, sh.tile_td,
+                                     sh.tile_skin, sh.totals, bg, s));
+  ht::FrameSlot& e = sh.entry;
+  e.W = W;
+  e.H = H;
+  e.TW = TW;
+  e.TH = TH;
+  if (cam.fx == cam.fy) {
+    e.sx = 1.0f;
+    e.sy = 1.0f;
+    e.sz = cam.fx;
+  } else {
+    e.sx = cam.fy;
+    e.sy = cam.fx;
+    e.sz = cam.fx * cam.fy;
+  }
+  e.cx = cam.cx;
+  e.cy = cam.cy;
+  e.fx = cam.fx;
+  e.fy = cam.fy;
+  e.bg = bg;
+  e.set = 1;
+  e.words = sh.words;
+  e.tile_td = sh.tile_td;
+  e.tile_skin = sh.tile_skin;
+  e.totals = sh.totals;
+  HT_HIP(hipMemcpyAsync(&c->d_slots[slot], &e, sizeof e, hipMemcpyHostToDevice, s));
+  HT_HIP(hipStreamSynchronize(s));
+  sh.set = true;
+  sh.W = W;
+  sh.H = H;
+  sh.TW = TW;
+  sh.TH = TH;
+  return HT_OK;
+}
+
+ht_status ht_reserve(ht_ctx* c, int max_particles, int max_pixels) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if (max_particles < 0 || max_pixels < 0) return fail(HT_ERR_ARG, "negative reservation");
+  const int side = (int)std::ceil(std::sqrt((double)max_pixels)) + ht::kTile;
+  const int tiles = std::max(c->max_tiles(), (side / ht::kTile + 1) * (side / ht::kTile + 1));
+  DeviceGuard g(c->device);
+  return ensure_workspace(c, std::max(max_particles, 1), tiles, true, nullptr);
+}
+
+ht_status ht_eval_particles(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_particles,
+                            const float* poses, float* cost, const ht_debug* dbg, void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if (n_frames < 0 || n_particles < 0) return fail(HT_ERR_ARG, "negative counts");
+  if ((long long)n_frames * n_particles > (1 << 24)) return fail(HT_ERR_ARG, "too many particles");
+  if (n_frames * n_particles == 0) return HT_OK;
+  if (!frame_slots || !poses || !cost) return fail(HT_ERR_ARG, "NULL device pointer");
+  if ((st = check_slots_set(c)) != HT_OK) return st;
+  if (dbg && (dbg->depth || dbg->hit || dbg->rm || dbg->winner)) {
+    if (n_frames != 1) return fail(HT_ERR_UNSUPPORTED, "debug images need n_frames == 1");
+    if (dbg->slot < 0 || dbg->slot >= HT_MAX_SLOTS || !c->slots[dbg->slot].set)
+      return fail(HT_ERR_STATE, "debug slot %d is not set", dbg->slot);
+  } else {
+    dbg = nullptr;
+  }
+  DeviceGuard g(c->device);
+  return ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, nullptr, nullptr, dbg,
+                       (hipStream_t)stream);
+}
+
+ht_status ht_eval_particles_grad(ht_ctx* c, int n_frames, const int32_t* frame_slots,
+                                 int n_particles, const float* poses, float* cost, float* grad,
+                                 const uint8_t* pixel_mask, void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if (n_frames < 0 || n_particles < 0) return fail(HT_ERR_ARG, "negative counts");
+  if ((long long)n_frames * n_particles > (1 << 24)) return fail(HT_ERR_ARG, "too many particles");
+  if (n_frames * n_particles == 0) return HT_OK;
+  if (!frame_slots || !poses || !cost || !grad) return fail(HT_ERR_ARG, "NULL device pointer");
+  if (pixel_mask && n_frames != 1) return fail(HT_ERR_UNSUPPORTED, "pixel_mask needs n_frames == 1");
+  if ((st = check_slots_set(c)) != HT_OK) return st;
+  DeviceGuard g(c->device);
+  return ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, grad, pixel_mask,
+                       nullptr, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+ht_status check_swarm(ht_ctx* c, const ht_swarm* sw) {
+  if (!sw) return fail(HT_ERR_ARG, "swarm is NULL");
+  if (sw->n_frames < 0 || sw->n_particles < 0) return fail(HT_ERR_ARG, "negative swarm counts");
+  if (sw->n_frames > HT_MAX_SLOTS) return fail(HT_ERR_ARG, "too many frames");
+  if ((long long)sw->n_frames * sw->n_particles > (1 << 22)) return fail(HT_ERR_ARG, "swarm too large");
+  if (sw->n_frames * sw->n_particles == 0) return HT_OK;
+  if (!sw->frame_slots || !sw->x || !sw->v || !sw->pbest_x || !sw->pbest_cost || !sw->gbest_x ||
+      !sw->gbest_cost || !sw->cost || !sw->gen || !sw->init_lo || !sw->init_hi)
+    return fail(HT_ERR_ARG, "swarm buffer is NULL");
+  (void)c;
+  return HT_OK;
+}
+
+ht_status check_params(const ht_swarm* sw, const ht_pso_params* p) {
+  if (!p) return fail(HT_ERR_ARG, "params is NULL");
+  if (!std::isfinite(p->w) || !std::isfinite(p->c1) || !std::isfinite(p->c2))
+    return fail(HT_ERR_ARG, "w, c1, c2 must be finite");
+  if (p->mutate_every < 0) return fail(HT_ERR_ARG, "mutate_every must be >= 0");
+  if (!(p->mutate_frac >= 0.0f && p->mutate_frac <= 1.0f)) return fail(HT_ERR_ARG, "mutate_frac out of [0, 1]");
+  if (p->refine_topk < 0 || p->refine_steps < 0) return fail(HT_ERR_ARG, "negative refinement counts");
+  if (p->refine_topk > sw->n_particles) return fail(HT_ERR_ARG, "refine_topk exceeds n_particles");
+  if (p->refine_topk > 0 && p->refine_steps > 0 &&
+      !(p->eta_rot > 0.0f && p->eta_trans > 0.0f && std::isfinite(p->eta_rot) && std::isfinite(p->eta_trans)))
+    return fail(HT_ERR_ARG, "eta_rot and eta_trans must be positive");
+  return HT_OK;
+}
+
+ht_status ensure_refine(ht_ctx* c, int n_ref, hipStream_t s) {
+  if (n_ref <= c->cap_ref) return HT_OK;
+  if (capturing(s)) return fail(HT_ERR_STATE, "refinement buffers too small during capture");
+  HT_HIP(hipDeviceSynchronize());
+  dfree(c->r_x);
+  dfree(c->r_cost);
+  dfree(c->r_grad);
+  dfree(c->r_cand);
+  dfree(c->r_ccost);
+  dfree(c->r_sel);
+  dfree(c->r_active);
+  const size_t D = c->n_dof;
+  HT_HIP(hipMalloc(&c->r_x, (size_t)n_ref * D * sizeof(float)));
+  HT_HIP(hipMalloc(&c->r_cost, (size_t)n_ref * sizeof(float)));
+  HT_HIP(hipMalloc(&c->r_grad, (size_t)n_ref * D * sizeof(float)));
+  HT_HIP(hipMalloc(&c->r_cand, (size_t)4 * n_ref * D * sizeof(float)));
+  HT_HIP(hipMalloc(&c->r_ccost, (size_t)4 * n_ref * sizeof(float)));
+  HT_HIP(hipMalloc(&c->r_sel, (size_t)n_ref * sizeof(int)));
+  HT_HIP(hipMalloc(&c->r_active, (size_t)n_ref * sizeof(int)));
+  c->cap_ref = n_ref;
+  return HT_OK;
+}
+
+// One generation on stream s (arguments already validated).
+ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, hipStream_t s) {
+  const int F = sw.n_frames, P = sw.n_particles, D = c->n_dof;
+  if (F * P == 0) return HT_OK;
+  ht_status st = ht::eval_impl(c, F, sw.frame_slots, P, sw.x, sw.cost, nullptr, nullptr, nullptr, s);
+  if (st != HT_OK) return st;
+  const int K = p.refine_topk;
+  if (K > 0 && p.refine_steps > 0) {
+    const int n_ref = F * K;
+    if ((st = ensure_refine(c, n_ref, s)) != HT_OK) return st;
+    HT_HIP(ht::launch_refine_select(sw, K, D, c->r_sel, c->r_x, c->r_cost, c->r_active, s));
+    for (int step = 0; step < p.refine_steps; ++step) {
+      st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s);
+      if (st != HT_OK) return st;
+      HT_HIP(ht::launch_refine_propose(c->d_model, n_ref, D, p.eta_rot, p.eta_trans, c->r_x,
+                                       c->r_grad, c->r_active, c->r_cand, s));
+      st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, nullptr, nullptr,
+                         nullptr, s);
+      if (st != HT_OK) return st;
+      HT_HIP(ht::launch_refine_accept(n_ref, D, c->r_x, c->r_cost, c->r_cand, c->r_ccost,
+                                      c->r_active, s));
+    }
+    HT_HIP(ht::launch_refine_gather(sw, K, D, c->r_sel, c->r_x, c->r_cost, s));
+  }
+  HT_HIP(ht::launch_pso_update(c->d_model, sw, p, D, s));
+  return HT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ht_status ht_pso_init(ht_ctx* c, const ht_swarm* sw, void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if ((st = check_swarm(c, sw)) != HT_OK) return st;
+  DeviceGuard g(c->device);
+  HT_HIP(ht::launch_pso_init(c->d_model, *sw, c->n_dof, (hipStream_t)stream));
+  return HT_OK;
+}
+
+ht_status ht_pso_step(ht_ctx* c, const ht_swarm* sw, const ht_pso_params* p, void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if ((st = check_swarm(c, sw)) != HT_OK) return st;
+  if ((st = check_params(sw, p)) != HT_OK) return st;
+  if (sw->n_frames * sw->n_particles == 0) return HT_OK;
+  if ((st = check_slots_set(c)) != HT_OK) return st;
+  DeviceGuard g(c->device);
+  return pso_step_impl(c, *sw, *p, (hipStream_t)stream);
+}
+
+ht_status ht_pso_run_graph(ht_ctx* c, const ht_swarm* sw, const ht_pso_params* p, int n_gen,
+                           void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if ((st = check_swarm(c, sw)) != HT_OK) return st;
+  if ((st = check_params(sw, p)) != HT_OK) return st;
+  if (n_gen < 0 || n_gen > 100000) return fail(HT_ERR_ARG, "n_generations %d out of range", n_gen);
+  if (sw->n_frames * sw->n_particles == 0 || n_gen == 0) return HT_OK;
+  if ((st = check_slots_set(c)) != HT_OK) return st;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  GraphKey key;
+  std::memset(&key, 0, sizeof key);
+  key.sw = *sw;
+  key.p = *p;
+  key.gens = n_gen;
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    // size every buffer before capture: nothing may be allocated while capturing
+    const int F = sw->n_frames, P = sw->n_particles, K = p->refine_topk;
+    const bool refine = K > 0 && p->refine_steps > 0;
+    const int most = std::max(F * P, refine ? F * 4 * K : 0);
+    if ((st = ensure_workspace(c, most, c->max_tiles(), refine, s)) != HT_OK) return st;
+    if (refine && (st = ensure_refine(c, F * K, s)) != HT_OK) return st;
+    hipStream_t cs;
+    HT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return fail(HT_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    st = HT_OK;
+    e = ht::launch_pso_init(c->d_model, *sw, c->n_dof, cs);
+    if (e != hipSuccess) st = fail(HT_ERR_HIP, "init launch: %s", hipGetErrorString(e));
+    for (int i = 0; i < n_gen && st == HT_OK; ++i) st = pso_step_impl(c, *sw, *p, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (st != HT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(HT_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(HT_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    it = c->graphs.emplace(key, exec).first;
+  }
+  HT_HIP(hipGraphLaunch(it->second, s));
+  return HT_OK;
+}
+
+ht_status ht_autotune(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_particles,
+                      const float* poses, float* cost, int repeats, ht_launch_config* out,
+                      void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if (n_frames <= 0 || n_particles <= 0 || !frame_slots || !poses || !cost || repeats < 1 || !out)
+    return fail(HT_ERR_ARG, "bad autotune arguments");
+  if ((st = check_slots_set(c)) != HT_OK) return st;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (capturing(s)) return fail(HT_ERR_STATE, "autotune cannot run during graph capture");
+  const ht_launch_config saved = c->lc;
+  hipEvent_t e0, e1;
+  HT_HIP(hipEventCreate(&e0));
+  HT_HIP(hipEventCreate(&e1));
+  float best = INFINITY;
+  ht_launch_config best_cfg = saved;
+  const int tpis[] = {4, 8, 16, 32, 64};
+  const int gpcs[] = {1, 2, 4, 8};
+  for (int tpi : tpis) {
+    for (int gpc : gpcs) {
+      c->lc = ht_launch_config{tpi, gpc};
+      st = ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, nullptr, nullptr,
+                         nullptr, s);
+      if (st != HT_OK) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < repeats && st == HT_OK; ++r)
+        st = ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, nullptr, nullptr,
+                           nullptr, s);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (st == HT_OK && ms < best) {
+        best = ms;
+        best_cfg = c->lc;
+      }
+    }
+    if (st != HT_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != HT_OK) {
+    c->lc = saved;
+    return st;
+  }
+  c->lc = best_cfg;
+  *out = best_cfg;
+  return HT_OK;
+}
+
+ht_status ht_get_launch_config(ht_ctx* c, ht_launch_config* out) {
+  g_err.clear();
+  if (!c || !out) return fail(HT_ERR_ARG, "NULL argument");
+  *out = c->lc;
+  return HT_OK;
+}
+
+ht_status ht_set_launch_config(ht_ctx* c, const ht_launch_config* cfg) {
+  g_err.clear();
+  if (!c || !cfg) return fail(HT_ERR_ARG, "NULL argument");
+  if (cfg->tiles_per_item < kMinTilesPerItem || cfg->tiles_per_item > 1024)
+    return fail(HT_ERR_ARG, "tiles_per_item %d out of %d..1024", cfg->tiles_per_item, kMinTilesPerItem);
+  if (cfg->groups_per_cu < 1 || cfg->groups_per_cu > 64)
+    return fail(HT_ERR_ARG, "groups_per_cu %d out of 1..64", cfg->groups_per_cu);
+  c->lc = *cfg;
+  return HT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal data layout shared by the host API (ht_api.cpp) and the kernels (ht_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "handtrack.h"
+
+namespace ht {
+
+constexpr int kTile = 8;            // 8x8 pixel tile = one wavefront of 64 lanes
+constexpr int kTilePx = kTile * kTile;
+constexpr int kWave = 64;
+constexpr int kBlock = 256;         // 4 wavefronts per workgroup
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kRec = 16;            // floats per primitive record
+constexpr float kDMatch = 10.0f;    // d_m, mm
+constexpr float kDClamp = 40.0f;    // d_M, mm
+constexpr double kLambda = 20.0;
+constexpr double kLambdaK = 10.0;
+
+// Observation word: bits 0..15 depth (mm, 0 = undefined), bit 16 skin, bit 17 pixel inside
+// the ROI (tiles over-hang the ROI on its right and bottom edges).
+constexpr uint32_t kSkinBit = 1u << 16;
+constexpr uint32_t kValidBit = 1u << 17;
+
+// Hand model as laid out in device memory.
+struct DevModel {
+  int n_dof, n_seg, n_prim, n_kc;
+  int max_depth;
+  int seg_parent[HT_MAX_SEG];
+  int seg_root_dof[HT_MAX_SEG];
+  int seg_depth[HT_MAX_SEG];
+  int seg_dof[HT_MAX_SEG][2];
+  double seg_off[HT_MAX_SEG][12];        // row-major 3x4
+  double seg_axis[HT_MAX_SEG][2][3];
+  int prim_type[HT_MAX_PRIM];
+  int prim_seg[HT_MAX_PRIM];
+  double prim_frame[HT_MAX_PRIM][12];
+  double prim_size[HT_MAX_PRIM][3];
+  float lo[HT_MAX_DOF], hi[HT_MAX_DOF];
+  int mutate[HT_MAX_DOF];
+  int kc_a[HT_MAX_KC], kc_b[HT_MAX_KC];
+  uint32_t dof_desc[HT_MAX_DOF];         // segments moved by each pose parameter
+  int dof_trans[HT_MAX_DOF];             // 1 for the wrist translations (mm), else angle
+};
+
+// Primitive index masks per type (bits for primitives 0..63 and 64..127).
+struct TypeMasks {
+  uint64_t m[3][2];
+};
+
+// One observation slot.
+struct FrameSlot {
+  int W, H, TW, TH;          // ROI size and tile grid
+  float sx, sy, sz;          // ray d = ((u-cx)*sx, (v-cy)*sy, sz); depth = t * sz
+  float cx, cy, fx, fy;
+  float bg;                  // background plane depth B (<= 0: none)
+  int set;
+  const uint32_t* words;     // [TH*TW][64] tile-major observation words
+  const float* tile_td;      // [TH*TW] sum of min(|o_d - r_bg|, d_M) over the tile
+  const int* tile_skin;      // [TH*TW] skin pixels of the tile
+  const double* totals;      // [2]: the same two sums over the whole ROI
+};
+
+// Per-particle summary written by the kinematics kernel.
+struct PInfo {
+  int tx0, ty0, tw, n_tiles;  // tile rectangle covering every primitive's screen box
+  int n_items;                // work items of the ray-cast kernel
+  int slot;                   // observation slot (-1: unset slot)
+  float kc;                   // collision term of Eq. 5
+  int valid;                  // 0: non-finite pose or unset slot
+};
+
+struct Partial {
+  float td;   // clamped depth sum minus the background sum of the processed tiles
+  int a;      // sum(o_s and r_m)
+  int o;      // sum(o_s or r_m) minus the background skin count of the processed tiles
+  int pad;
+};
+
+// Workspace of one evaluation call (device pointers, owned by the context).
+struct Workspace {
+  float* recs;           // [n_total][n_prim][kRec]
+  int4* boxes;           // [n_total][n_prim] pixel box (u0, u1, v0, v1), empty = (1, 0, 1, 0)
+  PInfo* pinfo;          // [n_total]
+  float* dof_frame;      // [n_total][n_dof][8]: kind, axis xyz, point xyz (camera frame)
+  float* seg_org;        // [n_total][n_seg][4]
+  int* item_off;         // [n_total + 1]
+  int* item_map;         // [max_items]
+  Partial* partial;      // [max_items]
+  float* wrench;         // [max_items][n_seg][6] (gradient only)
+  int* counters;         // [0] dequeue counter, [1] total items
+  int max_items;
+};
+
+struct EvalArgs {
+  const DevModel* model;
+  const FrameSlot* slots;
+  const int* frame_slots;
+  int n_frames, n_particles;
+  const float* poses;
+  float* cost;
+  float* grad;                 // NULL for forward only
+  const uint8_t* pixel_mask;   // gradient mask of frame 0, may be NULL
+  ht_debug dbg;                // pointers may be NULL
+  int dbg_W, dbg_H;
+  float dbg_bg;
+  TypeMasks type_masks;
+  int tiles_per_item;
+  int grid;                    // persistent workgroups
+  int n_prim, n_seg, n_dof;
+};
+
+// Launch helpers implemented in ht_kernels.hip.
+hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, int W, int H,
+                                   int TW, int TH, uint32_t* words, float* tile_td,
+                                   int* tile_skin, double* totals, float bg, hipStream_t s);
+hipError_t launch_eval(const EvalArgs& a, const Workspace& ws, hipStream_t s);
+hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s);
+hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht_pso_params& p,
+                             int n_dof, hipStream_t s);
+hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
+                                float* rcost, int* active, hipStream_t s);
+hipError_t launch_refine_propose(const DevModel* model, int n_ref, int n_dof, float eta_rot,
+                                 float eta_trans, const float* rx, const float* grad,
+                                 const int* active, float* cand, hipStream_t s);
+hipError_t launch_refine_accept(int n_ref, int n_dof, float* rx, float* rcost, const float* cand,
+                                const float* ccost, int* active, hipStream_t s);
+hipError_t launch_refine_gather(const ht_swarm& sw, int K, int n_dof, const int* sel,
+                                const float* rx, const float* rcost, hipStream_t s);
+
+}  // namespace ht

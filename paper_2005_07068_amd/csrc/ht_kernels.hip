@@ -1,0 +1,871 @@
+// Evaluation kernels: observation packing, forward kinematics prologue, work scheduling,
+// persistent ray cast + Eq. 4 cost terms + reduction (with the optional adjoint), finalize.
+//
+// Work decomposition: an 8x8 pixel tile is one wavefront (64 lanes, one pixel each).  The
+// primitives of a particle are culled per tile by their conservative screen boxes with a
+// ballot; tiles that no primitive touches render the background, whose cost terms are
+// summed once per observation, so only touched tiles are visited.  A work item is a run of
+// `tiles_per_item` touched-rectangle tiles of one particle; persistent workgroups of four
+// wavefronts dequeue items, stage the particle's primitive table in LDS and write one
+// partial per item, which the finalize kernel combines in item order (deterministic).
+#include <float.h>
+#include <math.h>
+
+#include "ht_device.h"
+
+namespace ht {
+
+// ------------------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// C = A * B for 3x4 affine transforms (row-major, implicit last row 0 0 0 1).
+__device__ inline void mul34(const double* A, const double* B, double* C) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double v = A[i * 4 + 0] * B[0 * 4 + j] + A[i * 4 + 1] * B[1 * 4 + j] +
+                 A[i * 4 + 2] * B[2 * 4 + j];
+      if (j == 3) v += A[i * 4 + 3];
+      C[i * 4 + j] = v;
+    }
+  }
+}
+
+// T <- T * Rot(axis, angle) (Rodrigues), rotation part only.
+__device__ inline void post_rotate(double* T, const double* a, double ang) {
+  double s, c;
+  sincos(ang, &s, &c);
+  const double C = 1.0 - c;
+  const double R[9] = {c + a[0] * a[0] * C, a[0] * a[1] * C - a[2] * s, a[0] * a[2] * C + a[1] * s,
+                       a[1] * a[0] * C + a[2] * s, c + a[1] * a[1] * C, a[1] * a[2] * C - a[0] * s,
+                       a[2] * a[0] * C - a[1] * s, a[2] * a[1] * C + a[0] * s, c + a[2] * a[2] * C};
+  double out[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      out[i * 3 + j] = T[i * 4 + 0] * R[0 * 3 + j] + T[i * 4 + 1] * R[1 * 3 + j] +
+                       T[i * 4 + 2] * R[2 * 3 + j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) T[i * 4 + j] = out[i * 3 + j];
+}
+
+__device__ __forceinline__ void split(double x, float& hi, float& lo) {
+  hi = (float)x;
+  lo = (float)(x - (double)hi);
+}
+
+// ------------------------------------------------------------------------------------
+// observation packing: one wavefront per tile
+
+__global__ __launch_bounds__(kBlock) void pack_kernel(const uint16_t* __restrict__ depth,
+                                                      const uint8_t* __restrict__ skin, int W,
+                                                      int H, int TW, int TH,
+                                                      uint32_t* __restrict__ words,
+                                                      float* __restrict__ tile_td,
+                                                      int* __restrict__ tile_skin, float bg) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (tile >= TW * TH) return;
+  const int tx = tile % TW, ty = tile / TW;
+  const int u = tx * kTile + (lane & 7), v = ty * kTile + (lane >> 3);
+  uint32_t w = 0;
+  float td = 0.0f;
+  int sk = 0;
+  if (u < W && v < H) {
+    const uint32_t d = depth[(size_t)v * W + u];
+    const int s = skin[(size_t)v * W + u] != 0;
+    w = d | (s ? kSkinBit : 0u) | kValidBit;
+    const float rbg = bg > 0.0f ? bg : 0.0f;
+    td = fminf(fabsf((float)d - rbg), kDClamp);
+    sk = s;
+  }
+  words[(size_t)tile * kTilePx + lane] = w;
+  td = wave_sum(td);
+  sk = wave_sum(sk);
+  if (lane == 0) {
+    tile_td[tile] = td;
+    tile_skin[tile] = sk;
+  }
+}
+
+// Whole-ROI background sums in a fixed order (one workgroup).
+__global__ __launch_bounds__(kBlock) void total_kernel(const float* __restrict__ tile_td,
+                                                       const int* __restrict__ tile_skin,
+                                                       int n_tiles, double* __restrict__ out) {
+  __shared__ double s_td[kBlock];
+  __shared__ double s_sk[kBlock];
+  double td = 0.0, sk = 0.0;
+  for (int i = threadIdx.x; i < n_tiles; i += kBlock) {
+    td += (double)tile_td[i];
+    sk += (double)tile_skin[i];
+  }
+  s_td[threadIdx.x] = td;
+  s_sk[threadIdx.x] = sk;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s_td[threadIdx.x] += s_td[threadIdx.x + o];
+      s_sk[threadIdx.x] += s_sk[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s_td[0];
+    out[1] = s_sk[0];
+  }
+}
+
+hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, int W, int H,
+                                   int TW, int TH, uint32_t* words, float* tile_td,
+                                   int* tile_skin, double* totals, float bg, hipStream_t s) {
+  const int n_tiles = TW * TH;
+  hipLaunchKernelGGL(pack_kernel, dim3((n_tiles + kWavesPerBlock - 1) / kWavesPerBlock),
+                     dim3(kBlock), 0, s, depth, skin, W, H, TW, TH, words, tile_td, tile_skin,
+                     bg);
+  hipLaunchKernelGGL(total_kernel, dim3(1), dim3(kBlock), 0, s, tile_td, tile_skin, n_tiles,
+                     totals);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// forward kinematics prologue: one wavefront per particle (FP64 inside)
+
+__global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
+  __shared__ double s_T[kWavesPerBlock][HT_MAX_SEG][12];
+  __shared__ double s_h[kWavesPerBlock][HT_MAX_DOF];
+  const DevModel& M = *a.model;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  const int n_total = a.n_frames * a.n_particles;
+  const int p = blockIdx.x * kWavesPerBlock + w;
+  const bool active = p < n_total;
+  const int n_dof = a.n_dof, n_seg = a.n_seg, n_prim = a.n_prim;
+  const int tpi = a.tiles_per_item;
+
+  bool finite = true;
+  if (active) {
+    for (int i = lane; i < n_dof; i += kWave) {
+      const float x = a.poses[(size_t)p * n_dof + i];
+      s_h[w][i] = (double)x;
+      finite = finite && isfinite(x);
+    }
+  }
+  finite = __ballot(!finite) == 0ull;
+  int slot = -1;
+  if (active) slot = a.frame_slots[p / a.n_particles];
+  const bool slot_ok = active && slot >= 0 && slot < HT_MAX_SLOTS && a.slots[slot].set;
+  const bool valid = slot_ok && finite;
+  __syncthreads();
+
+  // segment transforms, level by level (parents precede children)
+  for (int level = 0; level <= M.max_depth; ++level) {
+    if (valid && lane < n_seg && M.seg_depth[lane] == level) {
+      double T[12], T0[12];
+      const int par = M.seg_parent[lane];
+      if (par < 0) {
+        const int b = M.seg_root_dof[lane];
+        const double* q = &s_h[w][b];
+        double sx, cx, sy, cy, sz, cz;
+        sincos(q[3], &sx, &cx);
+        sincos(q[4], &sy, &cy);
+        sincos(q[5], &sz, &cz);
+        // Rz(tz) Ry(ty) Rx(tx)
+        const double Rzy[9] = {cz * cy, -sz, cz * sy, sz * cy, cz, sz * sy, -sy, 0.0, cy};
+        T0[0] = Rzy[0];
+        T0[1] = Rzy[1] * cx + Rzy[2] * sx;
+        T0[2] = -Rzy[1] * sx + Rzy[2] * cx;
+        T0[3] = q[0];
+        T0[4] = Rzy[3];
+        T0[5] = Rzy[4] * cx + Rzy[5] * sx;
+        T0[6] = -Rzy[4] * sx + Rzy[5] * cx;
+        T0[7] = q[1];
+        T0[8] = Rzy[6];
+        T0[9] = Rzy[7] * cx + Rzy[8] * sx;
+        T0[10] = -Rzy[7] * sx + Rzy[8] * cx;
+        T0[11] = q[2];
+        // wrist dofs: translations along camera axes; rotations about Rz Ry e_x, Rz e_y, e_z
+        // through the wrist position
+        float* df = ws.dof_frame + ((size_t)p * n_dof + b) * 8;
+        for (int i = 0; i < 3; ++i) {
+          float* f = df + i * 8;
+          f[0] = 1.0f;
+          f[1] = i == 0;
+          f[2] = i == 1;
+          f[3] = i == 2;
+          f[4] = f[5] = f[6] = f[7] = 0.0f;
+        }
+        const double ax[3][3] = {{T0[0], T0[4], T0[8]}, {-sz, cz, 0.0}, {0.0, 0.0, 1.0}};
+        for (int i = 0; i < 3; ++i) {
+          float* f = df + (3 + i) * 8;
+          f[0] = 0.0f;
+          f[1] = (float)ax[i][0];
+          f[2] = (float)ax[i][1];
+          f[3] = (float)ax[i][2];
+          f[4] = (float)q[0];
+          f[5] = (float)q[1];
+          f[6] = (float)q[2];
+          f[7] = 0.0f;
+        }
+      } else {
+        for (int i = 0; i < 12; ++i) T0[i] = s_T[w][par][i];
+      }
+      mul34(T0, M.seg_off[lane], T);
+      for (int j = 0; j < 2; ++j) {
+        const int dof = M.seg_dof[lane][j];
+        if (dof < 0) continue;
+        const double* ax = M.seg_axis[lane][j];
+        float* f = ws.dof_frame + ((size_t)p * n_dof + dof) * 8;
+        f[0] = 0.0f;
+        for (int i = 0; i < 3; ++i) {
+          f[1 + i] = (float)(T[i * 4 + 0] * ax[0] + T[i * 4 + 1] * ax[1] + T[i * 4 + 2] * ax[2]);
+          f[4 + i] = (float)T[i * 4 + 3];
+        }
+        f[7] = 0.0f;
+        post_rotate(T, ax, s_h[w][dof]);
+      }
+      for (int i = 0; i < 12; ++i) s_T[w][lane][i] = T[i];
+      float* so = ws.seg_org + ((size_t)p * n_seg + lane) * 4;
+      so[0] = (float)T[3];
+      so[1] = (float)T[7];
+      so[2] = (float)T[11];
+      so[3] = 0.0f;
+    }
+    __syncthreads();
+  }
+
+  // primitive records and screen boxes
+  int bu0 = INT_MAX, bu1 = INT_MIN, bv0 = INT_MAX, bv1 = INT_MIN;
+  if (valid) {
+    const FrameSlot fs = a.slots[slot];
+    for (int k = lane; k < n_prim; k += kWave) {
+      const int s = M.prim_seg[k];
+      double F[12];
+      mul34(s_T[w][s], M.prim_frame[k], F);
+      const double* sz = M.prim_size[k];
+      const int typ = M.prim_type[k];
+      float rec[kRec];
+      for (int i = 0; i < kRec; ++i) rec[i] = 0.0f;
+      const double c[3] = {F[3], F[7], F[11]};
+      const double* T = s_T[w][s];
+      double lo3[3], hi3[3];
+      split(c[0], rec[0], rec[4]);
+      split(c[1], rec[1], rec[5]);
+      split(c[2], rec[2], rec[6]);
+      rec[12] = (float)(c[0] - T[3]);
+      rec[13] = (float)(c[1] - T[7]);
+      rec[14] = (float)(c[2] - T[11]);
+      rec[15] = __int_as_float(s);
+      if (typ == HT_SPHERE) {
+        const double r = sz[0];
+        rec[3] = (float)(r * r);
+        for (int i = 0; i < 3; ++i) {
+          lo3[i] = c[i] - r;
+          hi3[i] = c[i] + r;
+        }
+      } else if (typ == HT_CYLINDER) {
+        const double r = sz[0], L = sz[1];
+        double u[3] = {F[2], F[6], F[10]};
+        const double nu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        for (int i = 0; i < 3; ++i) u[i] /= nu;
+        rec[3] = (float)(r * r);
+        rec[7] = (float)L;
+        rec[8] = (float)u[0];
+        rec[9] = (float)u[1];
+        rec[10] = (float)u[2];
+        rec[11] = (float)(c[0] * u[0] + c[1] * u[1] + c[2] * u[2]);
+        for (int i = 0; i < 3; ++i) {
+          const double e = r * sqrt(fmax(0.0, 1.0 - u[i] * u[i]));
+          const double c1 = c[i] + L * u[i];
+          lo3[i] = fmin(c[i], c1) - e;
+          hi3[i] = fmax(c[i], c1) + e;
+        }
+      } else {
+        // Q = R diag(1/s^2) R^T, R = rotation part of F
+        double Q[6] = {0, 0, 0, 0, 0, 0};
+        for (int j = 0; j < 3; ++j) {
+          const double inv = 1.0 / (sz[j] * sz[j]);
+          const double r0 = F[0 * 4 + j], r1 = F[1 * 4 + j], r2 = F[2 * 4 + j];
+          Q[0] += inv * r0 * r0;
+          Q[1] += inv * r0 * r1;
+          Q[2] += inv * r0 * r2;
+          Q[3] += inv * r1 * r1;
+          Q[4] += inv * r1 * r2;
+          Q[5] += inv * r2 * r2;
+        }
+        rec[3] = (float)Q[0];
+        rec[7] = (float)Q[1];
+        rec[8] = (float)Q[2];
+        rec[9] = (float)Q[3];
+        rec[10] = (float)Q[4];
+        rec[11] = (float)Q[5];
+        for (int i = 0; i < 3; ++i) {
+          const double e = sqrt((F[i * 4 + 0] * sz[0]) * (F[i * 4 + 0] * sz[0]) +
+                                (F[i * 4 + 1] * sz[1]) * (F[i * 4 + 1] * sz[1]) +
+                                (F[i * 4 + 2] * sz[2]) * (F[i * 4 + 2] * sz[2]));
+          lo3[i] = c[i] - e;
+          hi3[i] = c[i] + e;
+        }
+      }
+      float4* dst = reinterpret_cast<float4*>(ws.recs + ((size_t)p * n_prim + k) * kRec);
+      for (int i = 0; i < 4; ++i)
+        dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
+
+      // conservative pixel box of the axis-aligned 3D box
+      int4 box;
+      if (!(lo3[2] > 1.0)) {
+        box = make_int4(0, fs.W - 1, 0, fs.H - 1);
+      } else if (fs.bg > 0.0f && lo3[2] >= (double)fs.bg) {
+        box = make_int4(1, 0, 1, 0);   // entirely behind the background plane
+      } else {
+        const double xmin = fmin(lo3[0] / lo3[2], lo3[0] / hi3[2]);
+        const double xmax = fmax(hi3[0] / lo3[2], hi3[0] / hi3[2]);
+        const double ymin = fmin(lo3[1] / lo3[2], lo3[1] / hi3[2]);
+        const double ymax = fmax(hi3[1] / lo3[2], hi3[1] / hi3[2]);
+        const double lim = 1.0e6;
+        const double u0 = fmin(fmax(floor(fs.cx + fs.fx * xmin), -1.0), lim);
+        const double u1 = fmin(fmax(ceil(fs.cx + fs.fx * xmax), -1.0), lim);
+        const double v0 = fmin(fmax(floor(fs.cy + fs.fy * ymin), -1.0), lim);
+        const double v1 = fmin(fmax(ceil(fs.cy + fs.fy * ymax), -1.0), lim);
+        box.x = max((int)u0, 0);
+        box.y = min((int)u1, fs.W - 1);
+        box.z = max((int)v0, 0);
+        box.w = min((int)v1, fs.H - 1);
+        if (box.x > box.y || box.z > box.w) box = make_int4(1, 0, 1, 0);
+      }
+      ws.boxes[(size_t)p * n_prim + k] = box;
+      if (box.x <= box.y) {
+        bu0 = min(bu0, box.x);
+        bu1 = max(bu1, box.y);
+        bv0 = min(bv0, box.z);
+        bv1 = max(bv1, box.w);
+      }
+    }
+  }
+  bu0 = wave_min(bu0);
+  bv0 = wave_min(bv0);
+  bu1 = wave_max(bu1);
+  bv1 = wave_max(bv1);
+  if (active && lane == 0) {
+    PInfo pi;
+    pi.slot = slot_ok ? slot : -1;
+    pi.valid = valid ? 1 : 0;
+    double kc = 0.0;
+    if (valid)
+      for (int i = 0; i < M.n_kc; ++i) kc += fmax(-(s_h[w][M.kc_a[i]] - s_h[w][M.kc_b[i]]), 0.0);
+    pi.kc = (float)kc;
+    if (valid && bu0 <= bu1) {
+      pi.tx0 = bu0 / kTile;
+      pi.ty0 = bv0 / kTile;
+      pi.tw = bu1 / kTile - pi.tx0 + 1;
+      pi.n_tiles = pi.tw * (bv1 / kTile - pi.ty0 + 1);
+    } else {
+      pi.tx0 = pi.ty0 = 0;
+      pi.tw = 1;
+      pi.n_tiles = 0;
+    }
+    pi.n_items = (pi.n_tiles + tpi - 1) / tpi;
+    ws.pinfo[p] = pi;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// exclusive scan of the per-particle item counts, item -> particle map, queue reset
+
+constexpr int kSchedBlock = 1024;
+
+__global__ __launch_bounds__(kSchedBlock) void sched_kernel(int n_total, Workspace ws) {
+  __shared__ int s_sum[kSchedBlock];
+  const int t = threadIdx.x;
+  const int chunk = (n_total + kSchedBlock - 1) / kSchedBlock;
+  const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
+  int local = 0;
+  for (int i = b; i < e; ++i) local += ws.pinfo[i].n_items;
+  s_sum[t] = local;
+  __syncthreads();
+  // Hillis-Steele inclusive scan
+  for (int o = 1; o < kSchedBlock; o <<= 1) {
+    const int v = t >= o ? s_sum[t - o] : 0;
+    __syncthreads();
+    s_sum[t] += v;
+    __syncthreads();
+  }
+  int off = s_sum[t] - local;
+  for (int i = b; i < e; ++i) {
+    ws.item_off[i] = off;
+    const int n = ws.pinfo[i].n_items;
+    for (int j = 0; j < n; ++j) ws.item_map[off + j] = i;
+    off += n;
+  }
+  if (t == kSchedBlock - 1) {
+    ws.item_off[n_total] = s_sum[t];
+    ws.counters[1] = s_sum[t];
+    ws.counters[0] = 0;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// per-pixel background for the debug images
+
+__global__ __launch_bounds__(kBlock) void debug_fill_kernel(ht_debug dbg, size_t n, float bg) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  if (dbg.depth) dbg.depth[i] = bg > 0.0f ? bg : 0.0f;
+  if (dbg.hit) dbg.hit[i] = 0;
+  if (dbg.rm) dbg.rm[i] = 0;
+  if (dbg.winner) dbg.winner[i] = -1;
+}
+
+// ------------------------------------------------------------------------------------
+// ray-primitive intersections (FP32; centres carried as hi + lo pairs)
+//
+// The ray is x = t d with d = ((u - cx) sx, (v - cy) sy, sz) exact in FP32; depth = t sz.
+// Every test first forms the offset of the ray's closest-approach point from the primitive
+// centre, which is accurate because d is exact and the centre is a double-float pair; the
+// hit decision and the half-chord then come from small, well-conditioned quantities.
+
+struct Hit {
+  float t;        // ray parameter of the entry point
+  bool ok;
+  float nx, ny, nz;   // outward normal direction at the entry (unnormalised)
+  float rx, ry, rz;   // entry point minus the primitive reference point
+};
+
+template <bool GRAD>
+__device__ __forceinline__ void sphere_test(const float* r, float dx, float dy, float dz,
+                                            float inv_dd, Hit& h) {
+  const float b = fmaf(dx, r[0], fmaf(dy, r[1], dz * r[2]));
+  const float t0 = b * inv_dd;
+  const float vx = fmaf(t0, dx, -r[0]) - r[4];
+  const float vy = fmaf(t0, dy, -r[1]) - r[5];
+  const float vz = fmaf(t0, dz, -r[2]) - r[6];
+  const float rho2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
+  const float h2 = r[3] - rho2;
+  h.ok = h2 >= 0.0f;
+  const float hs = fast_sqrt(fmaxf(h2, 0.0f) * inv_dd);
+  h.t = t0 - hs;
+  if (GRAD) {
+    h.rx = fmaf(-hs, dx, vx);
+    h.ry = fmaf(-hs, dy, vy);
+    h.rz = fmaf(-hs, dz, vz);
+    h.nx = h.rx;
+    h.ny = h.ry;
+    h.nz = h.rz;
+  }
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void ellipsoid_test(const float* r, float dx, float dy, float dz,
+                                               Hit& h) {
+  const float q00 = r[3], q01 = r[7], q02 = r[8], q11 = r[9], q12 = r[10], q22 = r[11];
+  const float qdx = fmaf(q00, dx, fmaf(q01, dy, q02 * dz));
+  const float qdy = fmaf(q01, dx, fmaf(q11, dy, q12 * dz));
+  const float qdz = fmaf(q02, dx, fmaf(q12, dy, q22 * dz));
+  const float dqd = fmaf(dx, qdx, fmaf(dy, qdy, dz * qdz));
+  const float cqd = fmaf(r[0], qdx, fmaf(r[1], qdy, r[2] * qdz));
+  const float inv = fast_rcp(dqd);
+  const float t0 = cqd * inv;
+  const float vx = fmaf(t0, dx, -r[0]) - r[4];
+  const float vy = fmaf(t0, dy, -r[1]) - r[5];
+  const float vz = fmaf(t0, dz, -r[2]) - r[6];
+  const float qvx = fmaf(q00, vx, fmaf(q01, vy, q02 * vz));
+  const float qvy = fmaf(q01, vx, fmaf(q11, vy, q12 * vz));
+  const float qvz = fmaf(q02, vx, fmaf(q12, vy, q22 * vz));
+  // t0 carries the rounding of c.Qd; the linear term B re-centres the chord exactly
+  const float B = fmaf(vx, qdx, fmaf(vy, qdy, vz * qdz));
+  const float cc = -B * inv;
+  const float m = fmaf(B, B * inv, 1.0f - fmaf(vx, qvx, fmaf(vy, qvy, vz * qvz)));
+  h.ok = m >= 0.0f;
+  const float tin = cc - fast_sqrt(fmaxf(m, 0.0f) * inv);
+  h.t = t0 + tin;
+  if (GRAD) {
+    h.rx = fmaf(tin, dx, vx);
+    h.ry = fmaf(tin, dy, vy);
+    h.rz = fmaf(tin, dz, vz);
+    h.nx = fmaf(tin, qdx, qvx);
+    h.ny = fmaf(tin, qdy, qvy);
+    h.nz = fmaf(tin, qdz, qvz);
+  }
+}
+
+// Closed cylinder as the intersection of the infinite cylinder and the slab 0 <= s <= L:
+// both intervals are expressed as offsets from the reference parameter t_r (the closest
+// approach to the axis), so the hit test compares small accurate numbers.
+template <bool GRAD>
+__device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy, float dz,
+                                              float dd, Hit& h) {
+  const float ux = r[8], uy = r[9], uz = r[10], L = r[7];
+  const float da = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
+  const float px = fmaf(-da, ux, dx), py = fmaf(-da, uy, dy), pz = fmaf(-da, uz, dz);
+  const float A = fmaf(px, px, fmaf(py, py, pz * pz));
+  const bool par = A < 1.0e-6f * dd;          // ray within ~1e-3 rad of the axis
+  const float inv_da = fast_rcp(da);
+  const float invA = fast_rcp(A);
+  const float t_side = fmaf(px, r[0], fmaf(py, r[1], pz * r[2])) * invA;
+  const float t_mid = (r[11] + 0.5f * L) * inv_da;
+  const float tr = par ? t_mid : t_side;
+  const float vx = fmaf(tr, dx, -r[0]) - r[4];
+  const float vy = fmaf(tr, dy, -r[1]) - r[5];
+  const float vz = fmaf(tr, dz, -r[2]) - r[6];
+  const float a3 = fmaf(vx, ux, fmaf(vy, uy, vz * uz));
+  const float wx = fmaf(-a3, ux, vx), wy = fmaf(-a3, uy, vy), wz = fmaf(-a3, uz, vz);
+  const float rho2 = fmaf(wx, wx, fmaf(wy, wy, wz * wz));
+  // t_side carries the rounding of the perpendicular part of d (large when the ray is close
+  // to the axis); the linear term B of the side quadratic re-centres the chord exactly
+  const float B = fmaf(wx, px, fmaf(wy, py, wz * pz));
+  const float cc = par ? 0.0f : -B * invA;
+  const float h2 = par ? r[3] - rho2 : fmaf(B, B * invA, r[3] - rho2);
+  const float hs = par ? INFINITY : fast_sqrt(fmaxf(h2, 0.0f) * invA);
+  float din, dout;
+  if (da != 0.0f) {
+    const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
+    din = fminf(d0, d1);
+    dout = fmaxf(d0, d1);
+  } else {
+    const bool inside = a3 >= 0.0f && a3 <= L;
+    din = inside ? -INFINITY : INFINITY;
+    dout = inside ? INFINITY : -INFINITY;
+  }
+  const float tin = fmaxf(cc - hs, din), tout = fminf(cc + hs, dout);
+  h.ok = h2 >= 0.0f && tin <= tout;
+  h.t = tr + tin;
+  if (GRAD) {
+    // entry point relative to p0 and the outward normal of the entry surface
+    const bool cap = din > cc - hs;
+    h.rx = fmaf(tin, dx, vx);
+    h.ry = fmaf(tin, dy, vy);
+    h.rz = fmaf(tin, dz, vz);
+    const float sgn = da > 0.0f ? -1.0f : 1.0f;
+    h.nx = cap ? sgn * ux : fmaf(tin, px, wx);
+    h.ny = cap ? sgn * uy : fmaf(tin, py, wy);
+    h.nz = cap ? sgn * uz : fmaf(tin, pz, wz);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// persistent ray cast + cost terms + reduction
+
+template <bool GRAD, bool DEBUG>
+__global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace ws,
+                                                         TypeMasks tm) {
+  __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
+  __shared__ int4 s_box[HT_MAX_PRIM];
+  __shared__ int s_item;
+  __shared__ float s_td[kWavesPerBlock];
+  __shared__ int s_a[kWavesPerBlock], s_o[kWavesPerBlock];
+  __shared__ float s_wr[GRAD ? kWavesPerBlock : 1][GRAD ? HT_MAX_SEG : 1][6];
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+  const int n_prim = a.n_prim, n_seg = a.n_seg;
+  const int tpi = a.tiles_per_item;
+  const int total = ws.counters[1];
+  int cur_p = -1;
+  PInfo pi{};
+  FrameSlot fs{};
+
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    const int p = ws.item_map[item];
+    if (p != cur_p) {
+      const float4* src = reinterpret_cast<const float4*>(ws.recs + (size_t)p * n_prim * kRec);
+      for (int i = tid; i < n_prim * (kRec / 4); i += kBlock) s_rec[i] = src[i];
+      for (int i = tid; i < n_prim; i += kBlock) s_box[i] = ws.boxes[(size_t)p * n_prim + i];
+      cur_p = p;
+      pi = ws.pinfo[p];
+      fs = a.slots[pi.slot];
+      __syncthreads();
+    }
+    if (GRAD) {
+      for (int i = lane; i < n_seg * 6; i += kWave) s_wr[wave][i / 6][i % 6] = 0.0f;
+    }
+    const int c = item - ws.item_off[p];
+    const int t_end = min((c + 1) * tpi, pi.n_tiles);
+    float acc_td = 0.0f;
+    int acc_a = 0, acc_o = 0;
+    const float* recs = reinterpret_cast<const float*>(s_rec);
+
+    for (int t = c * tpi + wave; t < t_end; t += kWavesPerBlock) {
+      const int tx = pi.tx0 + t % pi.tw, ty = pi.ty0 + t / pi.tw;
+      const int x0 = tx * kTile, y0 = ty * kTile;
+      uint64_t mk[2];
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int k = lane + half * kWave;
+        bool ov = false;
+        if (k < n_prim) {
+          const int4 b = s_box[k];
+          ov = b.x <= x0 + kTile - 1 && b.y >= x0 && b.z <= y0 + kTile - 1 && b.w >= y0;
+        }
+        mk[half] = __ballot(ov);
+      }
+      if ((mk[0] | mk[1]) == 0ull) continue;
+
+      const int tile_idx = ty * fs.TW + tx;
+      const int u = x0 + (lane & 7), v = y0 + (lane >> 3);
+      const uint32_t word = fs.words[(size_t)tile_idx * kTilePx + lane];
+      const bool valid = (word & kValidBit) != 0;
+      const float od = (float)(word & 0xFFFFu);
+      const bool os = (word & kSkinBit) != 0;
+      const float dx = ((float)u - fs.cx) * fs.sx;
+      const float dy = ((float)v - fs.cy) * fs.sy;
+      const float dz = fs.sz;
+      const float dd = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const float inv_dd = fast_rcp(dd);
+      float zmin = fs.bg > 0.0f ? fs.bg : INFINITY;
+      int win = -1;
+      float wnx = 0, wny = 0, wnz = 0, wrx = 0, wry = 0, wrz = 0;
+
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+#pragma unroll
+        for (int typ = 0; typ < 3; ++typ) {
+          uint64_t m = mk[half] & tm.m[typ][half];
+          while (m) {
+            const int k = __builtin_ctzll(m) + half * kWave;
+            m &= m - 1;
+            const float* r = recs + k * kRec;
+            Hit h;
+            if (typ == HT_SPHERE) sphere_test<GRAD>(r, dx, dy, dz, inv_dd, h);
+            else if (typ == HT_CYLINDER) cylinder_test<GRAD>(r, dx, dy, dz, dd, h);
+            else ellipsoid_test<GRAD>(r, dx, dy, dz, h);
+            const float z = h.t * dz;
+            // nearest entry; ties keep the lower primitive index
+            const bool take = h.ok && (z < zmin || (z == zmin && win >= 0 && k < win));
+            if (take) {
+              zmin = z;
+              win = k;
+              if (GRAD) {
+                wnx = h.nx; wny = h.ny; wnz = h.nz;
+                wrx = h.rx; wry = h.ry; wrz = h.rz;
+              }
+            }
+          }
+        }
+      }
+      const bool hit = win >= 0;
+      const float rd = hit ? zmin : (fs.bg > 0.0f ? fs.bg : 0.0f);
+      const float diff = fabsf(od - rd);
+      const float td = fminf(diff, kDClamp);
+      const bool rm = hit && (diff < kDMatch || od == 0.0f);
+      if (valid) {
+        acc_td += td;
+        acc_a += (os && rm) ? 1 : 0;
+        acc_o += (os || rm) ? 1 : 0;
+      }
+      if (lane == 0) {
+        acc_td -= fs.tile_td[tile_idx];
+        acc_o -= fs.tile_skin[tile_idx];
+      }
+      if (DEBUG && valid) {
+        const size_t pix = ((size_t)p * a.dbg_H + v) * a.dbg_W + u;
+        if (a.dbg.depth) a.dbg.depth[pix] = rd;
+        if (a.dbg.hit) a.dbg.hit[pix] = hit ? 1 : 0;
+        if (a.dbg.rm) a.dbg.rm[pix] = rm ? 1 : 0;
+        if (a.dbg.winner) a.dbg.winner[pix] = win;
+      }
+      if (GRAD) {
+        // adjoint: coefficient of the depth term, then the per-segment wrench
+        bool act = valid && hit && diff < kDClamp && od != rd;
+        if (act && a.pixel_mask) act = a.pixel_mask[(size_t)v * fs.W + u] != 0;
+        int seg = -1;
+        float kap = 0.0f;
+        float mx = 0, my = 0, mz = 0;
+        if (act) {
+          const float* r = recs + win * kRec;
+          seg = __float_as_int(r[15]);
+          const float nd = fmaf(wnx, dx, fmaf(wny, dy, wnz * dz));
+          kap = (rd > od ? 1.0f : -1.0f) * dz / nd;
+          // lever arm from the segment origin: (entry - ref) + (ref - origin)
+          const float lx = wrx + r[12], ly = wry + r[13], lz = wrz + r[14];
+          mx = kap * (ly * wnz - lz * wny);
+          my = kap * (lz * wnx - lx * wnz);
+          mz = kap * (lx * wny - ly * wnx);
+        }
+        const float fx = kap * wnx, fy = kap * wny, fz = kap * wnz;
+        // segments present in this tile, reduced one at a time (uniform loop)
+        uint32_t segmask = act ? (1u << seg) : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) segmask |= (uint32_t)__shfl_xor((int)segmask, o);
+        while (segmask) {
+          const int s = __builtin_ctz(segmask);
+          segmask &= segmask - 1;
+          const bool mine = seg == s;
+          const float vals[6] = {mine ? mx : 0.f, mine ? my : 0.f, mine ? mz : 0.f,
+                                 mine ? fx : 0.f, mine ? fy : 0.f, mine ? fz : 0.f};
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            const float sum = wave_sum(vals[q]);
+            if (lane == 0) s_wr[wave][s][q] += sum;
+          }
+        }
+      }
+    }
+
+    acc_td = wave_sum(acc_td);
+    acc_a = wave_sum(acc_a);
+    acc_o = wave_sum(acc_o);
+    if (lane == 0) {
+      s_td[wave] = acc_td;
+      s_a[wave] = acc_a;
+      s_o[wave] = acc_o;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Partial pr;
+      pr.td = ((s_td[0] + s_td[1]) + s_td[2]) + s_td[3];
+      pr.a = s_a[0] + s_a[1] + s_a[2] + s_a[3];
+      pr.o = s_o[0] + s_o[1] + s_o[2] + s_o[3];
+      pr.pad = 0;
+      ws.partial[item] = pr;
+    }
+    if (GRAD) {
+      for (int i = tid; i < n_seg * 6; i += kBlock) {
+        const int s = i / 6, q = i % 6;
+        ws.wrench[(size_t)item * n_seg * 6 + i] =
+            ((s_wr[0][s][q] + s_wr[1][s][q]) + s_wr[2][s][q]) + s_wr[3][s][q];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// finalize: combine partials in item order, Eq. 4-5, and the kinematic adjoint
+
+template <bool GRAD>
+__global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace ws) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int n_total = a.n_frames * a.n_particles;
+  if (p >= n_total) return;
+  const PInfo pi = ws.pinfo[p];
+  const int n_dof = a.n_dof, n_seg = a.n_seg;
+  if (!pi.valid) {
+    a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
+    if (GRAD)
+      for (int j = 0; j < n_dof; ++j) a.grad[(size_t)p * n_dof + j] = 0.0f;
+    return;
+  }
+  const FrameSlot& fs = a.slots[pi.slot];
+  double S_d = fs.totals[0];
+  long long S_and = 0, S_or = (long long)fs.totals[1];
+  const int b = ws.item_off[p], e = b + pi.n_items;
+  for (int i = b; i < e; ++i) {
+    const Partial pr = ws.partial[i];
+    S_d += (double)pr.td;
+    S_and += pr.a;
+    S_or += pr.o;
+  }
+  double D;
+  if (S_or == 0) {
+    D = kLambda;
+  } else {
+    D = S_d / (double)S_or +
+        kLambda * (1.0 - 2.0 * (double)S_and / (double)(S_and + S_or));
+  }
+  a.cost[p] = (float)(D + kLambdaK * (double)pi.kc);
+  if (GRAD) {
+    const DevModel& M = *a.model;
+    // per-segment wrench (moment about the segment origin, force), summed in item order
+    double W[HT_MAX_SEG][6];
+    for (int s = 0; s < n_seg; ++s)
+      for (int q = 0; q < 6; ++q) W[s][q] = 0.0;
+    for (int i = b; i < e; ++i) {
+      const float* src = ws.wrench + (size_t)i * n_seg * 6;
+      for (int s = 0; s < n_seg; ++s)
+        for (int q = 0; q < 6; ++q) W[s][q] += (double)src[s * 6 + q];
+    }
+    const double inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
+    const float* org = ws.seg_org + (size_t)p * n_seg * 4;
+    for (int j = 0; j < n_dof; ++j) {
+      const float* f = ws.dof_frame + ((size_t)p * n_dof + j) * 8;
+      const uint32_t desc = M.dof_desc[j];
+      double g = 0.0;
+      for (int s = 0; s < n_seg; ++s) {
+        if (!((desc >> s) & 1u)) continue;
+        if (f[0] != 0.0f) {
+          g += f[1] * W[s][3] + f[2] * W[s][4] + f[3] * W[s][5];
+        } else {
+          // a . (M_s + (q_s - q_j) x F_s)
+          const double lx = (double)org[s * 4 + 0] - f[4];
+          const double ly = (double)org[s * 4 + 1] - f[5];
+          const double lz = (double)org[s * 4 + 2] - f[6];
+          const double mx = W[s][0] + (ly * W[s][5] - lz * W[s][4]);
+          const double my = W[s][1] + (lz * W[s][3] - lx * W[s][5]);
+          const double mz = W[s][2] + (lx * W[s][4] - ly * W[s][3]);
+          g += f[1] * mx + f[2] * my + f[3] * mz;
+        }
+      }
+      g *= inv_or;
+      a.grad[(size_t)p * n_dof + j] = (float)g;
+    }
+    const float* h = a.poses + (size_t)p * n_dof;
+    for (int i = 0; i < M.n_kc; ++i) {
+      if ((double)h[M.kc_a[i]] - (double)h[M.kc_b[i]] < 0.0) {
+        a.grad[(size_t)p * n_dof + M.kc_a[i]] -= (float)kLambdaK;
+        a.grad[(size_t)p * n_dof + M.kc_b[i]] += (float)kLambdaK;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+
+hipError_t launch_eval(const EvalArgs& a, const Workspace& ws, hipStream_t s) {
+  const int n_total = a.n_frames * a.n_particles;
+  if (n_total == 0) return hipSuccess;
+  hipLaunchKernelGGL(fk_kernel, dim3((n_total + kWavesPerBlock - 1) / kWavesPerBlock),
+                     dim3(kBlock), 0, s, a, ws);
+  hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kSchedBlock), 0, s, n_total, ws);
+  const bool dbg = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner;
+  if (dbg) {
+    const size_t n = (size_t)a.n_particles * a.dbg_H * a.dbg_W;
+    // background value of slot 0 of the call is passed through dbg_* by the host
+    hipLaunchKernelGGL(debug_fill_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, a.dbg, n, a.dbg_bg);
+  }
+  TypeMasks tm = a.type_masks;
+  const dim3 grid(a.grid), block(kBlock);
+  if (a.grad) {
+    if (dbg) hipLaunchKernelGGL((raycast_kernel<true, true>), grid, block, 0, s, a, ws, tm);
+    else hipLaunchKernelGGL((raycast_kernel<true, false>), grid, block, 0, s, a, ws, tm);
+    hipLaunchKernelGGL(finalize_kernel<true>, dim3((n_total + kBlock - 1) / kBlock),
+                       dim3(kBlock), 0, s, a, ws);
+  } else {
+    if (dbg) hipLaunchKernelGGL((raycast_kernel<false, true>), grid, block, 0, s, a, ws, tm);
+    else hipLaunchKernelGGL((raycast_kernel<false, false>), grid, block, 0, s, a, ws, tm);
+    hipLaunchKernelGGL(finalize_kernel<false>, dim3((n_total + kBlock - 1) / kBlock),
+                       dim3(kBlock), 0, s, a, ws);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ht

@@ -1,0 +1,355 @@
+// Particle swarm kernels: initialisation, the generation update of Eq. 6-7 with the mutation
+// of section III.B, and the three stages of gradient refinement (select, propose, accept).
+//
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed, counter
+// (dimension, frame * P + particle, generation, stream); uniform = (word >> 8) * 2^-24.
+// Stream 0 gives r1 (word 0) and r2 (word 1) of Eq. 6, stream 1 the initial positions,
+// stream 2 the mutation re-draws.
+#include <math.h>
+
+#include "ht_device.h"
+
+namespace ht {
+
+namespace {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
+    }
+    const uint32_t hi0 = __umulhi(kPhiloxM0, c.x), lo0 = kPhiloxM0 * c.x;
+    const uint32_t hi1 = __umulhi(kPhiloxM1, c.z), lo1 = kPhiloxM1 * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+__device__ __forceinline__ float unit(uint32_t w) { return (float)(w >> 8) * 0x1.0p-24f; }
+
+__device__ __forceinline__ uint4 draw(uint64_t seed, int dim, int gpart, int gen, int stream) {
+  return philox4x32_10(make_uint4((uint32_t)dim, (uint32_t)gpart, (uint32_t)gen, (uint32_t)stream),
+                       (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ float cost_key(float c) { return isnan(c) ? INFINITY : c; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void pso_init_kernel(const DevModel* __restrict__ M,
+                                                          ht_swarm sw, int n_dof) {
+  const int F = sw.n_frames, P = sw.n_particles;
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t n = (size_t)F * P * n_dof;
+  if (i < n) {
+    const int d = (int)(i % n_dof);
+    const int gp = (int)(i / n_dof);
+    const int f = gp / P;
+    const float lo = fmaxf(sw.init_lo[(size_t)f * n_dof + d], M->lo[d]);
+    const float hi = fminf(sw.init_hi[(size_t)f * n_dof + d], M->hi[d]);
+    const float u = unit(draw(sw.seed, d, gp, 0, 1).x);
+    const float x = fminf(fmaxf(fmaf(u, hi - lo, lo), lo), hi);
+    sw.x[i] = x;
+    sw.v[i] = 0.0f;
+    sw.pbest_x[i] = x;
+    if (gp % P == 0) sw.gbest_x[(size_t)f * n_dof + d] = x;
+    if (d == 0) {
+      sw.pbest_cost[gp] = INFINITY;
+      sw.cost[gp] = INFINITY;
+      if (gp % P == 0) {
+        sw.gbest_cost[f] = INFINITY;
+        sw.gen[f] = 0;
+      }
+    }
+  }
+}
+
+hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s) {
+  const size_t n = (size_t)sw.n_frames * sw.n_particles * n_dof;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pso_init_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, model, sw, n_dof);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// one generation's update for every frame: one workgroup per frame
+
+constexpr int kPsoBlock = 1024;
+
+__global__ __launch_bounds__(kPsoBlock) void pso_update_kernel(const DevModel* __restrict__ M,
+                                                               ht_swarm sw, ht_pso_params prm,
+                                                               int n_dof) {
+  extern __shared__ float s_mem[];
+  const int P = sw.n_particles;
+  float* s_cost = s_mem;          // [P] current costs (NaN -> +inf)
+  float* s_pb = s_mem + P;        // [P] personal best costs after this generation
+  __shared__ float s_rv[kPsoBlock / kWave];
+  __shared__ int s_ri[kPsoBlock / kWave];
+  __shared__ int s_g;
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  const int gen = sw.gen[f];
+  const size_t base = (size_t)f * P;
+
+  for (int i = tid; i < P; i += blockDim.x) {
+    const float c = cost_key(sw.cost[base + i]);
+    s_cost[i] = c;
+    float pb = sw.pbest_cost[base + i];
+    if (c < pb) {
+      pb = c;
+      for (int d = 0; d < n_dof; ++d)
+        sw.pbest_x[(base + i) * n_dof + d] = sw.x[(base + i) * n_dof + d];
+      sw.pbest_cost[base + i] = c;
+    }
+    s_pb[i] = pb;
+  }
+  __syncthreads();
+
+  // global best: lowest personal-best cost, ties to the lowest index
+  float bv = INFINITY;
+  int bi = INT_MAX;
+  for (int i = tid; i < P; i += blockDim.x) {
+    const float v = s_pb[i];
+    if (v < bv || (v == bv && i < bi)) {
+      bv = v;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ov = __shfl_xor(bv, o);
+    const int oi = __shfl_xor(bi, o);
+    if (ov < bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    s_rv[wv] = bv;
+    s_ri[wv] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float v = s_rv[0];
+    int idx = s_ri[0];
+    for (int q = 1; q < (int)blockDim.x / kWave; ++q) {
+      if (s_rv[q] < v || (s_rv[q] == v && s_ri[q] < idx)) {
+        v = s_rv[q];
+        idx = s_ri[q];
+      }
+    }
+    // every personal best is +inf only before any finite cost: keep particle 0
+    s_g = idx == INT_MAX ? 0 : idx;
+    sw.gbest_cost[f] = s_pb[s_g];
+  }
+  __syncthreads();
+  const int g = s_g;
+  for (int d = tid; d < n_dof; d += blockDim.x)
+    sw.gbest_x[(size_t)f * n_dof + d] = sw.pbest_x[(base + g) * n_dof + d];
+
+  const bool mutate_gen = prm.mutate_every > 0 && (gen + 1) % prm.mutate_every == 0;
+  const int n_mut = (int)floorf((float)P * prm.mutate_frac);
+  for (int i = tid; i < P; i += blockDim.x) {
+    const int gp = (int)(base + i);
+    bool mutated = false;
+    if (mutate_gen && n_mut > 0) {
+      // rank 0 is the worst: higher cost, ties to the higher index
+      const float ci = s_cost[i];
+      int rank = 0;
+      for (int j = 0; j < P; ++j) {
+        const float cj = s_cost[j];
+        rank += (cj > ci || (cj == ci && j > i)) ? 1 : 0;
+      }
+      mutated = rank < n_mut;
+    }
+    float* x = sw.x + (size_t)gp * n_dof;
+    float* v = sw.v + (size_t)gp * n_dof;
+    if (mutated) {
+      for (int d = 0; d < n_dof; ++d) {
+        if (!M->mutate[d]) continue;
+        const float u = unit(draw(sw.seed, d, gp, gen, 2).x);
+        x[d] = fmaf(u, M->hi[d] - M->lo[d], M->lo[d]);
+        v[d] = 0.0f;
+      }
+    } else {
+      const float* pb = sw.pbest_x + (size_t)gp * n_dof;
+      const float* gb = sw.pbest_x + (base + g) * n_dof;
+      for (int d = 0; d < n_dof; ++d) {
+        const uint4 r = draw(sw.seed, d, gp, gen, 0);
+        const float r1 = unit(r.x), r2 = unit(r.y);
+        const float xd = x[d];
+        const float t = fmaf(prm.c2 * r2, gb[d] - xd, fmaf(prm.c1 * r1, pb[d] - xd, v[d]));
+        float vn = prm.w * t;
+        float xn = xd + vn;
+        if (xn < M->lo[d]) {
+          xn = M->lo[d];
+          vn = 0.0f;
+        } else if (xn > M->hi[d]) {
+          xn = M->hi[d];
+          vn = 0.0f;
+        }
+        x[d] = xn;
+        v[d] = vn;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) sw.gen[f] = gen + 1;
+}
+
+hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht_pso_params& p,
+                             int n_dof, hipStream_t s) {
+  if (sw.n_frames == 0 || sw.n_particles == 0) return hipSuccess;
+  const int threads = sw.n_particles >= kPsoBlock ? kPsoBlock
+                                                  : ((sw.n_particles + kWave - 1) / kWave) * kWave;
+  const size_t shm = 2 * (size_t)sw.n_particles * sizeof(float);
+  hipLaunchKernelGGL(pso_update_kernel, dim3(sw.n_frames), dim3(threads), shm, s, model, sw, p,
+                     n_dof);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// gradient refinement
+//
+// select: the K lowest current costs of each frame (ties: lower index first), copied into
+// the refinement buffers; propose: four step lengths (1, 1/2, 1/4, 1/8) of the normalised
+// steepest-descent step in the eta-scaled space; accept: the first length whose cost is lower
+// than the current one, else the particle stops refining; gather: back into the swarm.
+
+__global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, int K, int n_dof,
+                                                                  int* __restrict__ sel,
+                                                                  float* __restrict__ rx,
+                                                                  float* __restrict__ rcost,
+                                                                  int* __restrict__ active) {
+  extern __shared__ float s_cost[];
+  const int P = sw.n_particles, f = blockIdx.x;
+  const size_t base = (size_t)f * P;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) s_cost[i] = cost_key(sw.cost[base + i]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    const float ci = s_cost[i];
+    int rank = 0;
+    for (int j = 0; j < P; ++j) {
+      const float cj = s_cost[j];
+      rank += (cj < ci || (cj == ci && j < i)) ? 1 : 0;
+    }
+    if (rank < K) {
+      const size_t r = (size_t)f * K + rank;
+      sel[r] = i;
+      rcost[r] = ci;
+      active[r] = 1;
+      for (int d = 0; d < n_dof; ++d) rx[r * n_dof + d] = sw.x[(base + i) * n_dof + d];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void refine_propose_kernel(const DevModel* __restrict__ M,
+                                                                int n_ref, int n_dof,
+                                                                float eta_rot, float eta_trans,
+                                                                const float* __restrict__ rx,
+                                                                const float* __restrict__ grad,
+                                                                const int* __restrict__ active,
+                                                                float* __restrict__ cand) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n_ref) return;
+  const float* x = rx + (size_t)r * n_dof;
+  const float* g = grad + (size_t)r * n_dof;
+  float gmax = 0.0f;
+  bool ok = active[r] != 0;
+  for (int d = 0; d < n_dof; ++d) {
+    const float eta = M->dof_trans[d] ? eta_trans : eta_rot;
+    const float gs = eta * g[d];
+    ok = ok && isfinite(gs);
+    gmax = fmaxf(gmax, fabsf(gs));
+  }
+  ok = ok && gmax > 0.0f;
+  for (int j = 0; j < 4; ++j) {
+    float* c = cand + ((size_t)r * 4 + j) * n_dof;
+    const float scale = ldexpf(1.0f, -j);
+    for (int d = 0; d < n_dof; ++d) {
+      float xn = x[d];
+      if (ok) {
+        const float eta = M->dof_trans[d] ? eta_trans : eta_rot;
+        const float step = eta * (eta * g[d] / gmax) * scale;
+        xn = fminf(fmaxf(x[d] - step, M->lo[d]), M->hi[d]);
+      }
+      c[d] = xn;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void refine_accept_kernel(int n_ref, int n_dof,
+                                                               float* __restrict__ rx,
+                                                               float* __restrict__ rcost,
+                                                               const float* __restrict__ cand,
+                                                               const float* __restrict__ ccost,
+                                                               int* __restrict__ active) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n_ref || !active[r]) return;
+  const float c0 = rcost[r];
+  for (int j = 0; j < 4; ++j) {
+    const float cj = ccost[(size_t)r * 4 + j];
+    if (cj < c0) {
+      for (int d = 0; d < n_dof; ++d)
+        rx[(size_t)r * n_dof + d] = cand[((size_t)r * 4 + j) * n_dof + d];
+      rcost[r] = cj;
+      return;
+    }
+  }
+  active[r] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void refine_gather_kernel(ht_swarm sw, int K, int n_dof,
+                                                               const int* __restrict__ sel,
+                                                               const float* __restrict__ rx,
+                                                               const float* __restrict__ rcost) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= sw.n_frames * K) return;
+  const int f = r / K;
+  const size_t gp = (size_t)f * sw.n_particles + sel[r];
+  for (int d = 0; d < n_dof; ++d) sw.x[gp * n_dof + d] = rx[(size_t)r * n_dof + d];
+  sw.cost[gp] = rcost[r];
+}
+
+hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
+                                float* rcost, int* active, hipStream_t s) {
+  const int threads = sw.n_particles >= kPsoBlock ? kPsoBlock
+                                                  : ((sw.n_particles + kWave - 1) / kWave) * kWave;
+  hipLaunchKernelGGL(refine_select_kernel, dim3(sw.n_frames), dim3(threads),
+                     (size_t)sw.n_particles * sizeof(float), s, sw, K, n_dof, sel, rx, rcost,
+                     active);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_propose(const DevModel* model, int n_ref, int n_dof, float eta_rot,
+                                 float eta_trans, const float* rx, const float* grad,
+                                 const int* active, float* cand, hipStream_t s) {
+  hipLaunchKernelGGL(refine_propose_kernel, dim3((n_ref + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     s, model, n_ref, n_dof, eta_rot, eta_trans, rx, grad, active, cand);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_accept(int n_ref, int n_dof, float* rx, float* rcost, const float* cand,
+                                const float* ccost, int* active, hipStream_t s) {
+  hipLaunchKernelGGL(refine_accept_kernel, dim3((n_ref + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     s, n_ref, n_dof, rx, rcost, cand, ccost, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_gather(const ht_swarm& sw, int K, int n_dof, const int* sel,
+                                const float* rx, const float* rcost, hipStream_t s) {
+  const int n = sw.n_frames * K;
+  hipLaunchKernelGGL(refine_gather_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     sw, K, n_dof, sel, rx, rcost);
+  return hipGetLastError();
+}
+
+}  // namespace ht

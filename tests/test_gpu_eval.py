@@ -1,0 +1,146 @@
+"""GPU parity of the evaluation path (kinematics, ray cast, Eq. 4-5 cost, reduction) against
+the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from gpu_util import (check_particle, eval_debug, frame_for, make_ctx, particles_for,
+                      torch_cuda)
+from oracle import cost as ocost
+from oracle import synth
+from workload import CONFIGS, make_hand_model, seed_sequence
+from workload.configs import camera_for_roi
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fwd64_parity_masks_depths_costs():
+    """configs[0] shape: 64x64, 40 primitives, 16 particles around the true pose."""
+    cfg, model, fr = frame_for(0)
+    poses = particles_for(model, fr, cfg.n_particles, seed=1)
+    poses[0] = fr["h_true"].astype(np.float32)
+    ctx = make_ctx(model, [fr])
+    cost, dbg = eval_debug(ctx, poses, 0, 64, 64)
+    diags = [check_particle(model, fr, poses[i], cost[i], dbg, i) for i in range(len(poses))]
+    print("fwd64", diags[:3])
+    assert sum(d["hits"] for d in diags) > 1000
+
+
+def test_ragged_roi_and_off_centre_camera():
+    """ROI sizes that are not multiples of the 8x8 tile, a non-square camera (fx != fy)."""
+    model = make_hand_model(seed_sequence(0, 777))
+    W, H = 61, 53
+    cam = (150.0, 128.0, 29.0, 27.5)
+    rng = np.random.default_rng(5)
+    from workload.handmodel import draw_true_pose_angles
+    h = synth.place_pose(model, draw_true_pose_angles(rng), cam, [(31.0, 26.0)])
+    from oracle import raycast
+    res = raycast.render(model, h, W, H, cam, 1500.0)
+    depth, skin = synth.observe(res, rng)
+    fr = {"depth": depth, "skin": skin, "cam": cam, "bg": 1500.0, "h_true": h}
+    poses = particles_for(model, fr, 6, seed=3)
+    ctx = make_ctx(model, [fr])
+    cost, dbg = eval_debug(ctx, poses, 0, W, H)
+    for i in range(len(poses)):
+        check_particle(model, fr, poses[i], cost[i], dbg, i)
+
+
+def test_no_background_plane_and_far_hand():
+    """B <= 0 (misses render 0) and a hypothesis entirely out of view."""
+    cfg, model, fr = frame_for(0, model_seed=1)
+    fr = dict(fr, bg=0.0)
+    poses = particles_for(model, fr, 4, seed=7)
+    poses[3, 20] += 3000.0
+    ctx = make_ctx(model, [fr])
+    cost, dbg = eval_debug(ctx, poses, 0, 64, 64)
+    for i in range(len(poses)):
+        check_particle(model, fr, poses[i], cost[i], dbg, i)
+    assert not dbg["hit"][3].any()
+
+
+def test_debug_and_plain_costs_identical_and_deterministic():
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(1)
+    poses = particles_for(model, fr, 64, seed=2)
+    ctx = make_ctx(model, [fr])
+    c_dbg, _ = eval_debug(ctx, poses, 0, 128, 128)
+    dev = torch.device("cuda:0")
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    p = torch.tensor(poses, device=dev)
+    c1 = ctx.eval(p, slots).cpu().numpy()
+    c2 = ctx.eval(p, slots).cpu().numpy()
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(c1, c_dbg)
+    for tpi, gpc in ((4, 1), (64, 8)):
+        ctx.set_launch_config(tpi, gpc)
+        c3 = ctx.eval(p, slots).cpu().numpy()
+        assert np.allclose(c3, c1, rtol=1e-6, atol=0)
+
+
+def test_nonfinite_pose_unset_slot_and_empty_call():
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(0)
+    poses = particles_for(model, fr, 3, seed=4)
+    poses[1, 7] = np.nan
+    poses[2, 22] = np.inf
+    ctx = make_ctx(model, [fr])
+    dev = torch.device("cuda:0")
+    c = ctx.eval(torch.tensor(poses, device=dev), torch.zeros(1, dtype=torch.int32, device=dev))
+    c = c.cpu().numpy()
+    assert np.isfinite(c[0]) and c[1] == np.inf and c[2] == np.inf
+    # a frame slot that was never set scores NaN (no fault)
+    c = ctx.eval(torch.tensor(poses[:1], device=dev),
+                 torch.full((1,), 5, dtype=torch.int32, device=dev)).cpu().numpy()
+    assert np.isnan(c[0])
+    empty = torch.zeros((0, model["n_dof"]), device=dev)
+    out = ctx.eval(empty, torch.zeros(1, dtype=torch.int32, device=dev))
+    assert out.numel() == 0
+
+
+def test_batched_frames_equal_per_frame_calls():
+    """configs[3] shape: uneven ROIs in one launch == one call per frame (bit-identical)."""
+    torch = torch_cuda()
+    cfg = CONFIGS[3]
+    model = make_hand_model(seed_sequence(3, 10_000))
+    frames = [synth.make_frame(model, cfg, f) for f in range(6)]
+    ctx = make_ctx(model, frames)
+    dev = torch.device("cuda:0")
+    P = 16
+    poses = np.stack([particles_for(model, fr, P, seed=10 + i) for i, fr in enumerate(frames)])
+    slots = torch.arange(len(frames), dtype=torch.int32, device=dev)
+    batched = ctx.eval(torch.tensor(poses, device=dev), slots).cpu().numpy()
+    for f in range(len(frames)):
+        one = ctx.eval(torch.tensor(poses[f], device=dev),
+                       torch.tensor([f], dtype=torch.int32, device=dev)).cpu().numpy()
+        assert np.array_equal(one, batched[f])
+    # and the first two frames' costs against the oracle
+    for f in range(2):
+        for i in range(0, P, 5):
+            E = ocost.objective(model, poses[f, i].astype(np.float64), frames[f])
+            assert abs(batched[f, i] - E) <= 1e-3 * E
+
+
+def test_full_size_adjoint_shape_sampled_particles():
+    """configs[2] shape (320x240, 256 particles): every cost computed, 6 sampled vs oracle."""
+    cfg, model, fr = frame_for(2)
+    poses = particles_for(model, fr, cfg.n_particles, seed=11)
+    ctx = make_ctx(model, [fr])
+    cost, dbg = eval_debug(ctx, poses, 0, 320, 240)
+    assert np.all(np.isfinite(cost))
+    for i in (0, 37, 101, 180, 222, 255):
+        check_particle(model, fr, poses[i], cost[i], dbg, i)
+
+
+def test_full_frame_two_hands_sampled_particles():
+    """configs[4] shape: 640x480, two hands (80 primitives, 52-D), 1024 particles."""
+    cfg, model, fr = frame_for(4)
+    poses = particles_for(model, fr, cfg.n_particles, seed=12)
+    ctx = make_ctx(model, [fr])
+    cost, dbg = eval_debug(ctx, poses, 0, 640, 480)
+    assert np.all(np.isfinite(cost))
+    for i in (0, 511, 1023):
+        check_particle(model, fr, poses[i], cost[i], dbg, i)
+
+
+def test_camera_helper_and_config_shapes():
+    assert camera_for_roi(64, 64) == (144.0, 144.0, 31.5, 31.5)
+    assert camera_for_roi(640, 480, True)[0] == 575.0

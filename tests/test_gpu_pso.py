@@ -1,0 +1,113 @@
+"""GPU swarm kernels against the oracle's swarm update (Eq. 6-7, mutation of section III.B):
+initialisation and single generations given identical state and costs; graph replay."""
+import numpy as np
+import pytest
+
+import paper_2005_07068_amd as ht
+from gpu_util import frame_for, make_ctx, torch_cuda
+from oracle import philox, pso
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(cfg_idx=1, P=64):
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(cfg_idx)
+    ctx = make_ctx(model, [fr])
+    dev = torch.device("cuda:0")
+    from workload.handmodel import init_halfwidth
+    delta = init_halfwidth(model["n_dof"], 10.0, 20.0)
+    lo = (fr["h_true"] - delta).astype(np.float32)
+    hi = (fr["h_true"] + delta).astype(np.float32)
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    sw = ctx.swarm(slots, P, torch.tensor(lo), torch.tensor(hi), seed=123456789012345)
+    return torch, ctx, model, fr, sw, lo, hi
+
+
+def _host(sw):
+    return {k: sw[k].cpu().numpy().astype(np.float64) if k != "gen" else
+            sw[k].cpu().numpy().astype(np.int64)
+            for k in ("x", "v", "pbest_x", "pbest_cost", "gbest_x", "gbest_cost", "gen")}
+
+
+def test_init_matches_oracle():
+    torch, ctx, model, fr, sw, lo, hi = _setup()
+    ctx.pso_init(sw)
+    torch.cuda.synchronize()
+    ref = pso.init_state(np.maximum(lo, model["bounds_lo"].astype(np.float32)).astype(np.float64),
+                         np.minimum(hi, model["bounds_hi"].astype(np.float32)).astype(np.float64),
+                         64, 123456789012345)
+    x = sw["x"].cpu().numpy()
+    assert np.allclose(x, ref["x"], rtol=0, atol=1e-4)
+    assert np.all(sw["v"].cpu().numpy() == 0) and np.all(sw["gen"].cpu().numpy() == 0)
+    assert np.all(np.isinf(sw["pbest_cost"].cpu().numpy()))
+
+
+@pytest.mark.parametrize("gen", [0, 2])
+def test_single_generation_matches_oracle(gen):
+    torch, ctx, model, fr, sw, lo, hi = _setup()
+    ctx.pso_init(sw)
+    rng = np.random.default_rng(gen)
+    # a mid-run state: random velocities and personal bests, generation counter `gen`
+    sw["v"].copy_(torch.tensor(rng.uniform(-0.05, 0.05, sw["v"].shape).astype(np.float32)))
+    pb = sw["x"].cpu().numpy() + rng.uniform(-0.02, 0.02, sw["x"].shape).astype(np.float32)
+    sw["pbest_x"].copy_(torch.tensor(pb))
+    sw["pbest_cost"].copy_(torch.tensor(rng.uniform(28, 60, (1, 64)).astype(np.float32)))
+    sw["gen"].fill_(gen)
+    torch.cuda.synchronize()
+    before = _host(sw)
+    params = ht.pso_params(w=0.72, c1=2.05, c2=2.05)
+    ctx.pso_step(sw, params)
+    torch.cuda.synchronize()
+    costs = sw["cost"].cpu().numpy().astype(np.float64)
+    after = _host(sw)
+    ref = pso.update(before, costs, pso.PsoParams(w=0.72, c1=2.05, c2=2.05),
+                     model["bounds_lo"].astype(np.float32), model["bounds_hi"].astype(np.float32),
+                     model["mutate_mask"], 123456789012345)
+    assert np.array_equal(after["pbest_cost"], ref["pbest_cost"])
+    assert np.array_equal(after["gbest_cost"], ref["gbest_cost"])
+    assert after["gen"][0] == gen + 1
+    for k in ("x", "v", "pbest_x", "gbest_x"):
+        assert np.allclose(after[k], ref[k], rtol=1e-5, atol=2e-5), k
+    if gen == 2:
+        moved = np.any(after["x"][0, :, :20] != before["x"][0, :, :20], axis=1)
+        assert moved.sum() >= 32
+
+
+def test_graph_replay_equals_eager_and_gbest_monotone():
+    torch, ctx, model, fr, sw, lo, hi = _setup()
+    params = ht.pso_params()
+    ctx.pso_init(sw)
+    hist = []
+    for _ in range(8):
+        ctx.pso_step(sw, params)
+        hist.append(float(sw["gbest_cost"].cpu()[0]))
+    eager = sw["gbest_x"].cpu().numpy().copy()
+    assert all(b <= a for a, b in zip(hist, hist[1:]))
+    for _ in range(3):
+        sw["x"].zero_()
+        ctx.pso_run_graph(sw, params, 8)
+        torch.cuda.synchronize()
+        assert np.array_equal(sw["gbest_x"].cpu().numpy(), eager)
+        assert float(sw["gbest_cost"].cpu()[0]) == hist[-1]
+        # eager work between replays
+        ctx.eval(sw["x"][0], sw["frame_slots"])
+
+
+def test_refinement_never_raises_the_cost():
+    torch, ctx, model, fr, sw, lo, hi = _setup(P=64)
+    ctx.pso_init(sw)
+    plain = ht.pso_params(mutate_every=0)
+    ctx.pso_step(sw, plain)
+    x = sw["x"].clone()
+    c0 = ctx.eval(x[0], sw["frame_slots"]).cpu().numpy()
+    refine = ht.pso_params(mutate_every=0, refine_topk=8, refine_steps=3)
+    # the step evaluates x, refines the 8 best, then moves the swarm; the refined costs land
+    # in sw["cost"] before the move
+    ctx.pso_step(sw, refine)
+    c1 = sw["cost"].cpu().numpy()[0]
+    top = np.argsort(c0, kind="stable")[:8]
+    assert np.all(c1[top] <= c0[top])
+    assert np.any(c1[top] < c0[top])
+    others = np.setdiff1d(np.arange(64), top)
+    assert np.array_equal(c1[others], c0[others])
