@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the hand-tracking hot path on one MI355X.
+
+One step is one whole particle-swarm run on one synthetic frame (or batch of frames): swarm
+initialisation, then every generation evaluates E (Eq. 5) for all particles (kinematics
+prologue, ray cast, Eq. 4 cost terms, reduction), optionally refines the best particles with
+the adjoint gradient, and moves the swarm (Eq. 6-7, mutation), all replayed from one HIP graph
+with the inputs resident in HBM.  The metric is particle evaluations per second (forward and
+gradient evaluations both count).
+
+Default workload: the full-resolution hybrid (640x480 depth + skin, two hands = 80 primitives
+and 52 parameters per particle, 1024 particles x 20 generations, 3 gradient steps on the best
+32 per generation).  --config 1 (128x128, 64 x 30 plain swarm) and --config 3 (64 frames of
+uneven ROIs, 64 x 30 per frame, one batched launch per generation) are the other workloads.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 157.3e12      # MI355X vector FP32, FLOP/s
+PEAK_HBM = 8.0e12              # MI355X HBM3E, B/s
+METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at equal pose error"
+
+
+def load_workload(idx: int):
+    from workload import CONFIGS, make_hand_model, seed_sequence
+    cfg = CONFIGS[idx]
+    d = np.load(os.path.join(ROOT, "workload", "data", f"config{idx}.npz"))
+    frames = [{"depth": d[f"depth_{f}"], "skin": d[f"skin_{f}"], "cam": tuple(d["cam"][f]),
+               "bg": float(d["bg"]), "h_true": d["h_true"][f]} for f in range(cfg.n_frames)]
+    model = make_hand_model(seed_sequence(idx, 10_000), cfg.n_hands)
+    return cfg, model, frames, float(d["flops_per_eval"]), int(d["flops_sample"])
+
+
+def joint_error_deg(h, h_true, n_hands):
+    """Mean |delta| over the finger angles, degrees."""
+    idx = np.concatenate([np.arange(20) + 26 * k for k in range(n_hands)])
+    return float(np.degrees(np.mean(np.abs(np.asarray(h)[..., idx] - np.asarray(h_true)[..., idx]))))
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _oracle_eval(args):
+    model, frame, pose = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cost
+    with threadpool_limits(1):
+        return cost.objective(model, pose, frame)
+
+
+def cpu_baseline(model, frames, poses, budget_s):
+    """The oracle, as it stands, on a bounded sample of the same evaluations: one process
+    per host core (at most 16, the host share of one GPU), one BLAS thread each."""
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    t = time.perf_counter()
+    _oracle_eval((model, frames[0], poses[0][0]))
+    t1 = time.perf_counter() - t
+    log(f"cpu baseline: one oracle evaluation takes {t1:.2f} s; {cores} worker processes")
+    per_core = max(1, int(budget_s / max(t1, 1e-3)))
+    n = min(cores * per_core, sum(len(p) for p in poses))
+    jobs = []
+    f = 0
+    while len(jobs) < n:
+        for pose in poses[f % len(poses)][: max(1, n // len(poses))]:
+            jobs.append((model, frames[f % len(frames)], pose))
+            if len(jobs) >= n:
+                break
+        f += 1
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_eval, jobs, chunksize=1)
+    dt = time.perf_counter() - t
+    return {"value": len(jobs) / dt, "unit": "particle evals/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{len(jobs)} forward evaluations of the benchmark's initial particles "
+                      f"(FP64 NumPy oracle, one process per core, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=4, choices=[1, 3, 4])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--launch-config", default=None,
+                    help="tiles_per_item,groups_per_cu; skips the autotuner")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: there is no multi-GPU path in this library "
+              "(frames, or the particles of one frame, would shard across GPUs)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from workload.handmodel import init_halfwidth
+
+    log(f"loading workload {args.config}")
+    cfg, model, frames, flops_per_eval, flops_sample = load_workload(args.config)
+    baseline = None
+    if not args.no_cpu_baseline:
+        # before the GPU is initialised: the worker processes are forked from this one
+        from oracle import pso as opso
+        d = init_halfwidth(model["n_dof"], cfg.init_angle_deg, cfg.init_trans_mm)
+        st = opso.init_state([fr["h_true"] - d for fr in frames[:8]],
+                             [fr["h_true"] + d for fr in frames[:8]], cfg.n_particles, 2005_07068)
+        poses = [st["x"][f].astype(np.float32).astype(np.float64) for f in range(len(st["x"]))]
+        baseline = cpu_baseline(model, frames, poses, args.cpu_seconds)
+        log(f"cpu baseline: {baseline['value']:.3g} evals/s")
+
+    log("initialising the GPU")
+    import torch
+
+    import paper_2005_07068_amd as ht
+    dev = torch.device("cuda:0")
+    ctx = ht.Context(0)
+    ctx.set_model(model)
+    for f, fr in enumerate(frames):
+        ctx.set_observation(f, fr["depth"], fr["skin"], fr["cam"], fr["bg"])
+    F, P, G = cfg.n_frames, cfg.n_particles, cfg.n_generations
+    K, S = cfg.refine_topk, cfg.refine_steps
+    max_px = max(fr["depth"].size for fr in frames)
+    ctx.reserve(F * max(P, 4 * K), max_px)
+    delta = init_halfwidth(model["n_dof"], cfg.init_angle_deg, cfg.init_trans_mm)
+    h_true = np.stack([fr["h_true"] for fr in frames])
+    lo = torch.tensor(h_true - delta, dtype=torch.float32)
+    hi = torch.tensor(h_true + delta, dtype=torch.float32)
+    slots = torch.arange(F, dtype=torch.int32, device=dev)
+    sw = ctx.swarm(slots, P, lo, hi, seed=2005_07068)
+    params = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, mutate_every=3, mutate_frac=0.5,
+                           refine_topk=K, refine_steps=S)
+
+    # launch shape: project autotuner on this workload's evaluation (outside the timed region)
+    log("context ready; launch shape")
+    ctx.pso_init(sw)
+    init_x = sw["x"].clone()
+    if args.launch_config:
+        tpi, gpc = (int(v) for v in args.launch_config.split(","))
+        ctx.set_launch_config(tpi, gpc)
+        tuned = {"tiles_per_item": tpi, "groups_per_cu": gpc, "source": "given"}
+    else:
+        tpi, gpc = ctx.autotune(init_x, slots, repeats=3)
+        tuned = {"tiles_per_item": tpi, "groups_per_cu": gpc, "source": "autotuner"}
+
+    evals_per_step = F * P * G + F * G * S * (K + 4 * K)
+    log(f"launch shape {tuned}; capturing and warming up")
+    for _ in range(args.warmup):
+        ctx.pso_run_graph(sw, params, G)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        ctx.pso_run_graph(sw, params, G)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    value = evals_per_step * args.steps / (ms / 1e3)
+    gbest = sw["gbest_x"].cpu().numpy().astype(np.float64)
+    err = joint_error_deg(gbest, h_true, cfg.n_hands)
+
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; per-kernel trace of one step")
+    # per-kernel device time of one eager step (same kernels as a graph replay)
+    ctx.profile_begin()
+    ctx.pso_init(sw)
+    for _ in range(G):
+        ctx.pso_step(sw, params)
+    stats = ctx.profile_end()
+    rc = stats["raycast"]
+    avg_ms = rc["ms"] / max(rc["launches"], 1)
+    particles_per_launch = rc["particles"] / max(rc["launches"], 1)
+    flops_launch = flops_per_eval * particles_per_launch
+    achieved = flops_launch / (avg_ms / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                "kernel": "raycast_kernel<false,false>", "avg_launch_ms": avg_ms,
+                "particles_per_launch": particles_per_launch,
+                "algorithmic_flops_per_eval": flops_per_eval}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "particle evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded oracle renders + sensor noise model)",
+        "config": {"workload": f"{cfg.name}: {F} frame(s) "
+                               f"{'x'.join(map(str, frames[0]['depth'].shape[::-1]))}"
+                               f"{' (uneven ROIs)' if cfg.roi is None else ''}, "
+                               f"{cfg.n_hands} hand(s) {model['n_prim']} primitives "
+                               f"{model['n_dof']} DOF, {P} particles x {G} generations"
+                               + (f", {S} gradient steps on the best {K}" if K else ""),
+                   "frames": F, "particles": P, "generations": G, "refine_topk": K,
+                   "refine_steps": S, "evals_per_step": evals_per_step,
+                   "launch": tuned, "parallelism": "1 GPU"},
+        "ms_per_frame": ms_per_step / F,
+        "wall_s": wall,
+        "final_joint_error_deg": err,
+        "roofline": roofline,
+        "kernels": {k: {"launches": v["launches"],
+                        "avg_ms": v["ms"] / v["launches"] if v["launches"] else 0.0}
+                    for k, v in stats.items()},
+    }
+    if baseline is not None:
+        line["cpu_baseline"] = baseline
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

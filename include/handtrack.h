@@ -223,6 +223,29 @@ ht_status ht_autotune(ht_ctx* ctx, int n_frames, const int32_t* frame_slots, int
                       const float* poses, float* cost, int repeats, ht_launch_config* out,
                       void* hip_stream);
 
+/* Per-kernel tracing of eager calls: between ht_profile_begin and ht_profile_end every kernel
+ * the library enqueues outside graph capture is bracketed by HIP events on its own stream.
+ * ht_profile_end synchronises those events, fills stats[HT_K_COUNT] (launch count, particles
+ * processed, summed device milliseconds per kernel kind) and stops tracing. */
+enum {
+  HT_K_FK = 0,            /* kinematics prologue             */
+  HT_K_SCHED = 1,         /* work-list scan                  */
+  HT_K_RAYCAST = 2,       /* ray cast + cost terms (forward) */
+  HT_K_RAYCAST_GRAD = 3,  /* ray cast + cost + adjoint       */
+  HT_K_FINALIZE = 4,      /* cost assembly (+ kinematic adjoint) */
+  HT_K_PSO = 5,           /* swarm init / update             */
+  HT_K_REFINE = 6,        /* refinement select/propose/accept/gather */
+  HT_K_COUNT = 7
+};
+typedef struct {
+  int32_t launches;
+  int64_t particles;
+  double total_ms;
+} ht_kernel_stat;
+
+ht_status ht_profile_begin(ht_ctx* ctx);
+ht_status ht_profile_end(ht_ctx* ctx, ht_kernel_stat* stats);
+
 #ifdef __cplusplus
 }
 #endif

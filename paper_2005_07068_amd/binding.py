@@ -67,6 +67,13 @@ class LaunchConfig(C.Structure):
     _fields_ = [("tiles_per_item", C.c_int32), ("groups_per_cu", C.c_int32)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("launches", C.c_int32), ("particles", C.c_int64), ("total_ms", C.c_double)]
+
+
+KERNEL_KINDS = ("fk", "sched", "raycast", "raycast_grad", "finalize", "pso", "refine")
+
+
 _lib = None
 
 
@@ -97,7 +104,9 @@ def load_library(path: str = LIB_PATH):
     lib.ht_get_launch_config.argtypes = [P, C.POINTER(LaunchConfig)]
     lib.ht_set_launch_config.argtypes = [P, C.POINTER(LaunchConfig)]
     lib.ht_autotune.argtypes = [P, I, P, I, P, P, I, C.POINTER(LaunchConfig), P]
-    for name in ("ht_create", "ht_set_model", "ht_set_observation", "ht_reserve",
+    lib.ht_profile_begin.argtypes = [P]
+    lib.ht_profile_end.argtypes = [P, C.POINTER(KernelStat)]
+    for name in ("ht_profile_begin", "ht_profile_end", "ht_create", "ht_set_model", "ht_set_observation", "ht_reserve",
                  "ht_eval_particles", "ht_eval_particles_grad", "ht_pso_init", "ht_pso_step",
                  "ht_pso_run_graph", "ht_get_launch_config", "ht_set_launch_config",
                  "ht_autotune"):
@@ -283,6 +292,17 @@ class Context:
     def pso_run_graph(self, sw, params: PsoParams, n_generations: int):
         _check(self.lib.ht_pso_run_graph(self.handle, C.byref(sw["_struct"]), C.byref(params),
                                          n_generations, _stream()))
+
+    # -- tracing ------------------------------------------------------------------------
+    def profile_begin(self):
+        _check(self.lib.ht_profile_begin(self.handle))
+
+    def profile_end(self) -> dict:
+        """Per kernel kind: launches, particles and summed device milliseconds."""
+        stats = (KernelStat * len(KERNEL_KINDS))()
+        _check(self.lib.ht_profile_end(self.handle, stats))
+        return {k: {"launches": s.launches, "particles": s.particles, "ms": s.total_ms}
+                for k, s in zip(KERNEL_KINDS, stats)}
 
     # -- launch shape -------------------------------------------------------------------
     def launch_config(self):

@@ -106,6 +106,14 @@ struct ht_ctx {
   int* r_slots = nullptr;     // [4 * cap_ref] frame slot of each refined particle
   int cap_ref = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
+  // tracing of eager launches
+  struct ProfRec {
+    int kind;
+    int particles;
+    hipEvent_t e0, e1;
+  };
+  bool prof = false;
+  std::vector<ProfRec> prof_recs;
 
   int max_tiles() const {
     int m = 0;
@@ -183,6 +191,22 @@ ht_status ensure_workspace(ht_ctx* c, int n_total, int max_tiles, bool grad, hip
   return HT_OK;
 }
 
+// Run `launch` on stream s, bracketed by HIP events when tracing (and not capturing).
+template <class F>
+hipError_t traced(ht_ctx* c, int kind, int particles, hipStream_t s, F&& launch) {
+  if (!c->prof || capturing(s)) return launch();
+  ht_ctx::ProfRec r{kind, particles, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&r.e0);
+  if (e == hipSuccess) e = hipEventCreate(&r.e1);
+  if (e == hipSuccess) e = hipEventRecord(r.e0, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(r.e1, s);
+  c->prof_recs.push_back(r);
+  return e;
+}
+
 ht_status check_ctx(ht_ctx* c, bool need_model = true) {
   if (!c) return fail(HT_ERR_ARG, "context is NULL");
   if (need_model && !c->has_model) return fail(HT_ERR_STATE, "no model: call ht_set_model first");
@@ -233,7 +257,11 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.n_prim = c->n_prim;
   a.n_seg = c->n_seg;
   a.n_dof = c->n_dof;
-  HT_HIP(launch_eval(a, c->ws, s));
+  const int kinds[kNumStages] = {HT_K_FK, HT_K_SCHED, grad ? HT_K_RAYCAST_GRAD : HT_K_RAYCAST,
+                                 HT_K_FINALIZE};
+  for (int stage = 0; stage < kNumStages; ++stage)
+    HT_HIP(traced(c, kinds[stage], n_total, s,
+                  [&] { return launch_eval_stage(stage, a, c->ws, s); }));
   return HT_OK;
 }
 
@@ -623,21 +651,21 @@ ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, h
   if (K > 0 && p.refine_steps > 0) {
     const int n_ref = F * K;
     if ((st = ensure_refine(c, n_ref, s)) != HT_OK) return st;
-    HT_HIP(ht::launch_refine_select(sw, K, D, c->r_sel, c->r_x, c->r_cost, c->r_active, s));
+    HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_select(sw, K, D, c->r_sel, c->r_x, c->r_cost, c->r_active, s); }));
     for (int step = 0; step < p.refine_steps; ++step) {
       st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s);
       if (st != HT_OK) return st;
-      HT_HIP(ht::launch_refine_propose(c->d_model, n_ref, D, p.eta_rot, p.eta_trans, c->r_x,
-                                       c->r_grad, c->r_active, c->r_cand, s));
+      HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_propose(c->d_model, n_ref, D, p.eta_rot, p.eta_trans, c->r_x,
+                                       c->r_grad, c->r_active, c->r_cand, s); }));
       st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, nullptr, nullptr,
                          nullptr, s);
       if (st != HT_OK) return st;
-      HT_HIP(ht::launch_refine_accept(n_ref, D, c->r_x, c->r_cost, c->r_cand, c->r_ccost,
-                                      c->r_active, s));
+      HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_accept(n_ref, D, c->r_x, c->r_cost, c->r_cand, c->r_ccost,
+                                      c->r_active, s); }));
     }
-    HT_HIP(ht::launch_refine_gather(sw, K, D, c->r_sel, c->r_x, c->r_cost, s));
+    HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_gather(sw, K, D, c->r_sel, c->r_x, c->r_cost, s); }));
   }
-  HT_HIP(ht::launch_pso_update(c->d_model, sw, p, D, s));
+  HT_HIP(traced(c, HT_K_PSO, F * P, s, [&] { return ht::launch_pso_update(c->d_model, sw, p, D, s); }));
   return HT_OK;
 }
 
@@ -651,7 +679,9 @@ ht_status ht_pso_init(ht_ctx* c, const ht_swarm* sw, void* stream) {
   if (st != HT_OK) return st;
   if ((st = check_swarm(c, sw)) != HT_OK) return st;
   DeviceGuard g(c->device);
-  HT_HIP(ht::launch_pso_init(c->d_model, *sw, c->n_dof, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  HT_HIP(traced(c, HT_K_PSO, sw->n_frames * sw->n_particles, s,
+                [&] { return ht::launch_pso_init(c->d_model, *sw, c->n_dof, s); }));
   return HT_OK;
 }
 
@@ -771,6 +801,41 @@ ht_status ht_autotune(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n
   c->lc = best_cfg;
   *out = best_cfg;
   return HT_OK;
+}
+
+ht_status ht_profile_begin(ht_ctx* c) {
+  g_err.clear();
+  if (!c) return fail(HT_ERR_ARG, "context is NULL");
+  DeviceGuard g(c->device);
+  for (auto& r : c->prof_recs) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  c->prof_recs.clear();
+  c->prof = true;
+  return HT_OK;
+}
+
+ht_status ht_profile_end(ht_ctx* c, ht_kernel_stat* stats) {
+  g_err.clear();
+  if (!c || !stats) return fail(HT_ERR_ARG, "NULL argument");
+  DeviceGuard g(c->device);
+  for (int k = 0; k < HT_K_COUNT; ++k) stats[k] = ht_kernel_stat{0, 0, 0.0};
+  ht_status st = HT_OK;
+  for (auto& r : c->prof_recs) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(r.e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.e0, r.e1);
+    if (e != hipSuccess && st == HT_OK) st = fail(HT_ERR_HIP, "event timing: %s", hipGetErrorString(e));
+    stats[r.kind].launches += 1;
+    stats[r.kind].particles += r.particles;
+    stats[r.kind].total_ms += ms;
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  c->prof_recs.clear();
+  c->prof = false;
+  return st;
 }
 
 ht_status ht_get_launch_config(ht_ctx* c, ht_launch_config* out) {

@@ -116,7 +116,8 @@ struct EvalArgs {
 hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, int W, int H,
                                    int TW, int TH, uint32_t* words, float* tile_td,
                                    int* tile_skin, double* totals, float bg, hipStream_t s);
-hipError_t launch_eval(const EvalArgs& a, const Workspace& ws, hipStream_t s);
+enum { kStageFk = 0, kStageSched = 1, kStageRaycast = 2, kStageFinalize = 3, kNumStages = 4 };
+hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s);
 hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s);
 hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht_pso_params& p,
                              int n_dof, hipStream_t s);

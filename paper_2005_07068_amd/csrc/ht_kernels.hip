@@ -839,31 +839,47 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace 
 
 // ------------------------------------------------------------------------------------
 
-hipError_t launch_eval(const EvalArgs& a, const Workspace& ws, hipStream_t s) {
+// The evaluation is four launches on one stream; `stage` selects one so the host can
+// bracket each with HIP events when profiling.
+hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s) {
   const int n_total = a.n_frames * a.n_particles;
   if (n_total == 0) return hipSuccess;
-  hipLaunchKernelGGL(fk_kernel, dim3((n_total + kWavesPerBlock - 1) / kWavesPerBlock),
-                     dim3(kBlock), 0, s, a, ws);
-  hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kSchedBlock), 0, s, n_total, ws);
   const bool dbg = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner;
-  if (dbg) {
-    const size_t n = (size_t)a.n_particles * a.dbg_H * a.dbg_W;
-    // background value of slot 0 of the call is passed through dbg_* by the host
-    hipLaunchKernelGGL(debug_fill_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, a.dbg, n, a.dbg_bg);
-  }
-  TypeMasks tm = a.type_masks;
-  const dim3 grid(a.grid), block(kBlock);
-  if (a.grad) {
-    if (dbg) hipLaunchKernelGGL((raycast_kernel<true, true>), grid, block, 0, s, a, ws, tm);
-    else hipLaunchKernelGGL((raycast_kernel<true, false>), grid, block, 0, s, a, ws, tm);
-    hipLaunchKernelGGL(finalize_kernel<true>, dim3((n_total + kBlock - 1) / kBlock),
-                       dim3(kBlock), 0, s, a, ws);
-  } else {
-    if (dbg) hipLaunchKernelGGL((raycast_kernel<false, true>), grid, block, 0, s, a, ws, tm);
-    else hipLaunchKernelGGL((raycast_kernel<false, false>), grid, block, 0, s, a, ws, tm);
-    hipLaunchKernelGGL(finalize_kernel<false>, dim3((n_total + kBlock - 1) / kBlock),
-                       dim3(kBlock), 0, s, a, ws);
+  switch (stage) {
+    case kStageFk:
+      hipLaunchKernelGGL(fk_kernel, dim3((n_total + kWavesPerBlock - 1) / kWavesPerBlock),
+                         dim3(kBlock), 0, s, a, ws);
+      break;
+    case kStageSched:
+      hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kSchedBlock), 0, s, n_total, ws);
+      if (dbg) {
+        const size_t n = (size_t)a.n_particles * a.dbg_H * a.dbg_W;
+        hipLaunchKernelGGL(debug_fill_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, s, a.dbg, n, a.dbg_bg);
+      }
+      break;
+    case kStageRaycast: {
+      const TypeMasks tm = a.type_masks;
+      const dim3 grid(a.grid), block(kBlock);
+      if (a.grad) {
+        if (dbg) hipLaunchKernelGGL((raycast_kernel<true, true>), grid, block, 0, s, a, ws, tm);
+        else hipLaunchKernelGGL((raycast_kernel<true, false>), grid, block, 0, s, a, ws, tm);
+      } else {
+        if (dbg) hipLaunchKernelGGL((raycast_kernel<false, true>), grid, block, 0, s, a, ws, tm);
+        else hipLaunchKernelGGL((raycast_kernel<false, false>), grid, block, 0, s, a, ws, tm);
+      }
+      break;
+    }
+    case kStageFinalize:
+      if (a.grad)
+        hipLaunchKernelGGL(finalize_kernel<true>, dim3((n_total + kBlock - 1) / kBlock),
+                           dim3(kBlock), 0, s, a, ws);
+      else
+        hipLaunchKernelGGL(finalize_kernel<false>, dim3((n_total + kBlock - 1) / kBlock),
+                           dim3(kBlock), 0, s, a, ws);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

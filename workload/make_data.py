@@ -1,0 +1,72 @@
+"""Write the seeded synthetic observations of the five workloads to workload/data/*.npz.
+
+Every stored value comes from the CPU oracle: a seeded true pose per frame is rendered by the
+oracle and the noise model of the workloads is applied (the simulation protocol of section
+V.A.1 with sensor noise); the algorithmic work per evaluation (for roofline figures) is the
+oracle's coverage count on a sample of particles drawn like the swarm's initial particles.
+
+    python -m workload.make_data            # all configs
+    python -m workload.make_data 1 4        # some
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+from oracle import flops, raycast, synth
+from workload import CONFIGS, make_hand_model, seed_sequence
+from workload.handmodel import perturbed_particles
+
+DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+def model_seed(idx: int):
+    return seed_sequence(idx, 10_000)
+
+
+def make(idx: int, flop_samples: int = 8) -> str:
+    cfg = CONFIGS[idx]
+    model = make_hand_model(model_seed(idx), cfg.n_hands)
+    out = {}
+    cams, hs = [], []
+    for f in range(cfg.n_frames):
+        fr = synth.make_frame(model, cfg, f)
+        out[f"depth_{f}"] = fr["depth"]
+        out[f"skin_{f}"] = fr["skin"]
+        cams.append(fr["cam"])
+        hs.append(fr["h_true"])
+    out["cam"] = np.array(cams, np.float64)
+    out["h_true"] = np.array(hs, np.float64)
+    out["bg"] = np.float64(synth.BACKGROUND_MM)
+    # algorithmic work per evaluation on particles drawn like the swarm's initial ones
+    rng = np.random.default_rng(seed_sequence(idx, 20_000))
+    work, pixels = [], []
+    frames = rng.choice(cfg.n_frames, size=min(flop_samples, cfg.n_frames), replace=False) \
+        if cfg.n_frames > 1 else np.zeros(1, int)
+    per_frame = max(1, flop_samples // len(frames))
+    for f in frames:
+        H, W = out[f"depth_{f}"].shape
+        poses = perturbed_particles(rng, out["h_true"][f], per_frame, cfg.init_angle_deg,
+                                    cfg.init_trans_mm, model["bounds_lo"], model["bounds_hi"])
+        for h in poses:
+            res = raycast.render(model, h, W, H, tuple(out["cam"][f]), synth.BACKGROUND_MM)
+            work.append(flops.eval_flops(res, model["prim_type"]))
+            pixels.append(W * H)
+    out["flops_per_eval"] = np.float64(np.mean(work))
+    out["flops_sample"] = np.int64(len(work))
+    os.makedirs(DATA, exist_ok=True)
+    path = os.path.join(DATA, f"config{idx}.npz")
+    np.savez_compressed(path, **out)
+    return path
+
+
+if __name__ == "__main__":
+    which = [int(a) for a in sys.argv[1:]] or sorted(CONFIGS)
+    for i in which:
+        t = time.time()
+        p = make(i)
+        print(f"config {i}: {p} ({os.path.getsize(p) / 1e6:.2f} MB, {time.time() - t:.1f} s)",
+              flush=True)
