@@ -51,6 +51,65 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=8):
+    """Plain swarm (the paper's 64 particles x 30 generations) against the workload's
+    gradient-refined swarm on the same frame(s): final mean joint error, ms per frame (graph
+    replay) and, for the refined swarm, the evaluations it needs to reach the plain swarm's
+    final error (mean over seeds)."""
+    F = slots.numel()
+    plain_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2)
+    ref_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, refine_topk=cfg.refine_topk,
+                          refine_steps=cfg.refine_steps)
+    P, G = cfg.n_particles, cfg.n_generations
+    per_gen = F * P + F * cfg.refine_steps * 5 * cfg.refine_topk
+    out = {"plain": {"particles": 64, "generations": 30, "err": [], "ms": []},
+           "refined": {"particles": P, "generations": G, "err": [], "ms": [],
+                       "evals_to_plain_err": []}}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for s in range(seeds):
+        sw = ctx.swarm(slots, 64, lo, hi, seed=1000 + s)
+        ctx.pso_run_graph(sw, plain_p, 30)
+        torch.cuda.synchronize()
+        e0.record()
+        ctx.pso_run_graph(sw, plain_p, 30)
+        e1.record()
+        torch.cuda.synchronize()
+        plain_err = joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
+                                    cfg.n_hands)
+        out["plain"]["err"].append(plain_err)
+        out["plain"]["ms"].append(e0.elapsed_time(e1) / F)
+        sw = ctx.swarm(slots, P, lo, hi, seed=1000 + s)
+        ctx.pso_run_graph(sw, ref_p, G)
+        torch.cuda.synchronize()
+        e0.record()
+        ctx.pso_run_graph(sw, ref_p, G)
+        e1.record()
+        torch.cuda.synchronize()
+        out["refined"]["ms"].append(e0.elapsed_time(e1) / F)
+        # per-generation error of the refined swarm (eager steps, outside any timing)
+        ctx.pso_init(sw)
+        reach = None
+        for g in range(G):
+            ctx.pso_step(sw, ref_p)
+            err = joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
+                                  cfg.n_hands)
+            if reach is None and err <= plain_err:
+                reach = (g + 1) * per_gen
+        out["refined"]["err"].append(err)
+        out["refined"]["evals_to_plain_err"].append(reach)
+    summary = {}
+    for k, v in out.items():
+        summary[k] = {"particles": v["particles"], "generations": v["generations"],
+                      "mean_joint_error_deg": float(np.mean(v["err"])),
+                      "ms_per_frame": float(np.mean(v["ms"]))}
+    reached = [r for r in out["refined"]["evals_to_plain_err"] if r is not None]
+    summary["refined"]["seeds_reaching_plain_error"] = len(reached)
+    summary["refined"]["mean_evals_to_plain_error"] = float(np.mean(reached)) if reached else None
+    summary["plain"]["evals"] = 64 * 30
+    summary["seeds"] = seeds
+    return summary
+
+
 def _oracle_eval(args):
     model, frame, pose = args
     from threadpoolctl import threadpool_limits
@@ -96,9 +155,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=4, choices=[1, 3, 4])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-study", action="store_true",
+                    help="skip the plain-versus-refined swarm comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--launch-config", default=None,
-                    help="tiles_per_item,groups_per_cu; skips the autotuner")
+                    help="tiles_per_item,groups_per_cu,cull; skips the autotuner")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path in this library "
@@ -148,12 +209,13 @@ def main():
     ctx.pso_init(sw)
     init_x = sw["x"].clone()
     if args.launch_config:
-        tpi, gpc = (int(v) for v in args.launch_config.split(","))
-        ctx.set_launch_config(tpi, gpc)
-        tuned = {"tiles_per_item": tpi, "groups_per_cu": gpc, "source": "given"}
+        tpi, gpc, cull = (int(v) for v in args.launch_config.split(","))
+        ctx.set_launch_config(tpi, gpc, cull)
+        tuned = {"tiles_per_item": tpi, "groups_per_cu": gpc, "cull": cull, "source": "given"}
     else:
-        tpi, gpc = ctx.autotune(init_x, slots, repeats=3)
-        tuned = {"tiles_per_item": tpi, "groups_per_cu": gpc, "source": "autotuner"}
+        tpi, gpc, cull = ctx.autotune(init_x, slots, repeats=3)
+        tuned = {"tiles_per_item": tpi, "groups_per_cu": gpc, "cull": cull,
+                 "source": "autotuner"}
 
     evals_per_step = F * P * G + F * G * S * (K + 4 * K)
     log(f"launch shape {tuned}; capturing and warming up")
@@ -214,6 +276,10 @@ def main():
                         "avg_ms": v["ms"] / v["launches"] if v["launches"] else 0.0}
                     for k, v in stats.items()},
     }
+    if K > 0 and not args.no_study:
+        log("plain versus gradient-refined swarm over seeds")
+        line["plain_vs_refined"] = plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi,
+                                                    h_true)
     if baseline is not None:
         line["cpu_baseline"] = baseline
     print(json.dumps(line), flush=True)

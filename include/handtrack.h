@@ -207,10 +207,13 @@ ht_status ht_pso_step(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_params* p
 ht_status ht_pso_run_graph(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_params* params,
                            int n_generations, void* hip_stream);
 
-/* Launch shape of the batched persistent ray-cast kernel. */
+/* Launch shape of the batched persistent ray-cast kernel.  tiles_per_item is shortened
+ * automatically for launches too small to give every compute unit a work item. */
 typedef struct {
   int32_t tiles_per_item;   /* 8x8-pixel tiles per work item (one work item per workgroup) */
   int32_t groups_per_cu;    /* persistent workgroups per compute unit                       */
+  int32_t cull;             /* 0: primitive screen boxes only; 1: also each primitive's
+                               bounding capsule against the tile's four frustum planes     */
 } ht_launch_config;
 
 ht_status ht_get_launch_config(ht_ctx* ctx, ht_launch_config* out);
@@ -218,7 +221,8 @@ ht_status ht_set_launch_config(ht_ctx* ctx, const ht_launch_config* cfg);
 
 /* Autotune the launch shape on the given workload (timed with HIP events on hip_stream,
  * synchronising it), keep the fastest in the context and return it in *out.
- * The candidate list is tiles_per_item x groups_per_cu over small powers of two. */
+ * The candidates are tiles_per_item in {4..64} x groups_per_cu in {1..8} (powers of two) x
+ * cull in {0, 1}. */
 ht_status ht_autotune(ht_ctx* ctx, int n_frames, const int32_t* frame_slots, int n_particles,
                       const float* poses, float* cost, int repeats, ht_launch_config* out,
                       void* hip_stream);

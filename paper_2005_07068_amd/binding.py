@@ -64,7 +64,7 @@ class PsoParams(C.Structure):
 
 
 class LaunchConfig(C.Structure):
-    _fields_ = [("tiles_per_item", C.c_int32), ("groups_per_cu", C.c_int32)]
+    _fields_ = [("tiles_per_item", C.c_int32), ("groups_per_cu", C.c_int32), ("cull", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -308,10 +308,10 @@ class Context:
     def launch_config(self):
         lc = LaunchConfig()
         _check(self.lib.ht_get_launch_config(self.handle, C.byref(lc)))
-        return lc.tiles_per_item, lc.groups_per_cu
+        return lc.tiles_per_item, lc.groups_per_cu, lc.cull
 
-    def set_launch_config(self, tiles_per_item: int, groups_per_cu: int):
-        lc = LaunchConfig(tiles_per_item, groups_per_cu)
+    def set_launch_config(self, tiles_per_item: int, groups_per_cu: int, cull: int = 1):
+        lc = LaunchConfig(tiles_per_item, groups_per_cu, cull)
         _check(self.lib.ht_set_launch_config(self.handle, C.byref(lc)))
 
     def autotune(self, poses, frame_slots, repeats: int = 5):
@@ -321,7 +321,7 @@ class Context:
         lc = LaunchConfig()
         _check(self.lib.ht_autotune(self.handle, F, _ptr(frame_slots), P, _ptr(poses.contiguous()),
                                     _ptr(cost), repeats, C.byref(lc), _stream()))
-        return lc.tiles_per_item, lc.groups_per_cu
+        return lc.tiles_per_item, lc.groups_per_cu, lc.cull
 
 
 def header_functions(header_path: str | None = None) -> list[str]:

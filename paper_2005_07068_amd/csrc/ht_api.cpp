@@ -94,7 +94,7 @@ struct ht_ctx {
   int cap_items = 0;
   int cap_tiles = 0;
   bool cap_wrench = false;
-  ht_launch_config lc{16, 4};
+  ht_launch_config lc{16, 4, 1};
   // swarm refinement scratch
   float* r_x = nullptr;       // [cap_ref][n_dof] current positions of the refined particles
   float* r_cost = nullptr;    // [cap_ref]
@@ -105,6 +105,8 @@ struct ht_ctx {
   int* r_active = nullptr;    // [cap_ref]
   int* r_slots = nullptr;     // [4 * cap_ref] frame slot of each refined particle
   int cap_ref = 0;
+  int* pso_flags = nullptr;   // [cap_flags] per-particle improved / mutated flags
+  int cap_flags = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
   // tracing of eager launches
   struct ProfRec {
@@ -136,6 +138,7 @@ void free_workspace(ht_ctx* c) {
   invalidate_graphs(c);
   dfree(c->ws.recs);
   dfree(c->ws.boxes);
+  dfree(c->ws.caps);
   dfree(c->ws.pinfo);
   dfree(c->ws.dof_frame);
   dfree(c->ws.seg_org);
@@ -174,6 +177,7 @@ ht_status ensure_workspace(ht_ctx* c, int n_total, int max_tiles, bool grad, hip
   auto& w = c->ws;
   HT_HIP(hipMalloc(&w.recs, (size_t)np * c->n_prim * ht::kRec * sizeof(float)));
   HT_HIP(hipMalloc(&w.boxes, (size_t)np * c->n_prim * sizeof(int4)));
+  HT_HIP(hipMalloc(&w.caps, (size_t)np * c->n_prim * 2 * sizeof(float4)));
   HT_HIP(hipMalloc(&w.pinfo, (size_t)np * sizeof(ht::PInfo)));
   HT_HIP(hipMalloc(&w.dof_frame, (size_t)np * c->n_dof * 8 * sizeof(float)));
   HT_HIP(hipMalloc(&w.seg_org, (size_t)np * c->n_seg * 4 * sizeof(float)));
@@ -249,7 +253,13 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
     a.dbg_bg = sh.entry.bg;
   }
   a.type_masks = c->tmask;
-  a.tiles_per_item = c->lc.tiles_per_item;
+  // small launches (a few particles) take shorter work items so the persistent grid still
+  // gets about one item per compute unit; about a quarter of an ROI's tiles are touched
+  int tpi = c->lc.tiles_per_item;
+  const long long est_tiles = (long long)n_total * c->max_tiles() / 4;
+  while (tpi > 8 && est_tiles / tpi < (long long)c->n_cu) tpi /= 2;
+  a.tiles_per_item = std::max(std::min(tpi, c->lc.tiles_per_item), kMinTilesPerItem);
+  a.cull = c->lc.cull;
   const long long bound = (long long)n_total *
                           ((c->max_tiles() + a.tiles_per_item - 1) / a.tiles_per_item);
   a.grid = (int)std::max<long long>(1, std::min<long long>((long long)c->n_cu * c->lc.groups_per_cu,
@@ -320,6 +330,7 @@ void ht_destroy(ht_ctx* c) {
   dfree(c->r_sel);
   dfree(c->r_active);
   dfree(c->r_slots);
+  dfree(c->pso_flags);
   dfree(c->d_slots);
   dfree(c->d_model);
   delete c;
@@ -595,6 +606,7 @@ ht_status check_swarm(ht_ctx* c, const ht_swarm* sw) {
   if (!sw) return fail(HT_ERR_ARG, "swarm is NULL");
   if (sw->n_frames < 0 || sw->n_particles < 0) return fail(HT_ERR_ARG, "negative swarm counts");
   if (sw->n_frames > HT_MAX_SLOTS) return fail(HT_ERR_ARG, "too many frames");
+  if (sw->n_particles > 4096) return fail(HT_ERR_ARG, "at most 4096 particles per frame");
   if ((long long)sw->n_frames * sw->n_particles > (1 << 22)) return fail(HT_ERR_ARG, "swarm too large");
   if (sw->n_frames * sw->n_particles == 0) return HT_OK;
   if (!sw->frame_slots || !sw->x || !sw->v || !sw->pbest_x || !sw->pbest_cost || !sw->gbest_x ||
@@ -622,6 +634,7 @@ ht_status ensure_refine(ht_ctx* c, int n_ref, hipStream_t s) {
   if (n_ref <= c->cap_ref) return HT_OK;
   if (capturing(s)) return fail(HT_ERR_STATE, "refinement buffers too small during capture");
   HT_HIP(hipDeviceSynchronize());
+  invalidate_graphs(c);   // captured graphs hold the old buffers
   dfree(c->r_x);
   dfree(c->r_cost);
   dfree(c->r_grad);
@@ -665,7 +678,16 @@ ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, h
     }
     HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_gather(sw, K, D, c->r_sel, c->r_x, c->r_cost, s); }));
   }
-  HT_HIP(traced(c, HT_K_PSO, F * P, s, [&] { return ht::launch_pso_update(c->d_model, sw, p, D, s); }));
+  if (F * P > c->cap_flags) {
+    if (capturing(s)) return fail(HT_ERR_STATE, "swarm flags too small during capture");
+    HT_HIP(hipDeviceSynchronize());
+    invalidate_graphs(c);   // captured graphs hold the old buffers
+    dfree(c->pso_flags);
+    HT_HIP(hipMalloc(&c->pso_flags, (size_t)F * P * sizeof(int)));
+    c->cap_flags = F * P;
+  }
+  HT_HIP(traced(c, HT_K_PSO, F * P, s,
+                [&] { return ht::launch_pso_update(c->d_model, sw, p, D, c->pso_flags, s); }));
   return HT_OK;
 }
 
@@ -722,6 +744,13 @@ ht_status ht_pso_run_graph(ht_ctx* c, const ht_swarm* sw, const ht_pso_params* p
     const int most = std::max(F * P, refine ? F * 4 * K : 0);
     if ((st = ensure_workspace(c, most, c->max_tiles(), refine, s)) != HT_OK) return st;
     if (refine && (st = ensure_refine(c, F * K, s)) != HT_OK) return st;
+    if (F * P > c->cap_flags) {
+      HT_HIP(hipDeviceSynchronize());
+      invalidate_graphs(c);   // captured graphs hold the old buffers
+      dfree(c->pso_flags);
+      HT_HIP(hipMalloc(&c->pso_flags, (size_t)F * P * sizeof(int)));
+      c->cap_flags = F * P;
+    }
     hipStream_t cs;
     HT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -771,26 +800,28 @@ ht_status ht_autotune(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n
   ht_launch_config best_cfg = saved;
   const int tpis[] = {4, 8, 16, 32, 64};
   const int gpcs[] = {1, 2, 4, 8};
-  for (int tpi : tpis) {
-    for (int gpc : gpcs) {
-      c->lc = ht_launch_config{tpi, gpc};
-      st = ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, nullptr, nullptr,
-                         nullptr, s);
-      if (st != HT_OK) break;
-      (void)hipEventRecord(e0, s);
-      for (int r = 0; r < repeats && st == HT_OK; ++r)
+  for (int cull = 0; cull < 2 && st == HT_OK; ++cull) {
+    for (int tpi : tpis) {
+      for (int gpc : gpcs) {
+        c->lc = ht_launch_config{tpi, gpc, cull};
         st = ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, nullptr, nullptr,
                            nullptr, s);
-      (void)hipEventRecord(e1, s);
-      (void)hipEventSynchronize(e1);
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (st == HT_OK && ms < best) {
-        best = ms;
-        best_cfg = c->lc;
+        if (st != HT_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < repeats && st == HT_OK; ++r)
+          st = ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, nullptr,
+                             nullptr, nullptr, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (st == HT_OK && ms < best) {
+          best = ms;
+          best_cfg = c->lc;
+        }
       }
+      if (st != HT_OK) break;
     }
-    if (st != HT_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -850,6 +881,7 @@ ht_status ht_set_launch_config(ht_ctx* c, const ht_launch_config* cfg) {
   if (!c || !cfg) return fail(HT_ERR_ARG, "NULL argument");
   if (cfg->tiles_per_item < kMinTilesPerItem || cfg->tiles_per_item > 1024)
     return fail(HT_ERR_ARG, "tiles_per_item %d out of %d..1024", cfg->tiles_per_item, kMinTilesPerItem);
+  if (cfg->cull != 0 && cfg->cull != 1) return fail(HT_ERR_ARG, "cull must be 0 or 1");
   if (cfg->groups_per_cu < 1 || cfg->groups_per_cu > 64)
     return fail(HT_ERR_ARG, "groups_per_cu %d out of 1..64", cfg->groups_per_cu);
   c->lc = *cfg;

@@ -83,6 +83,7 @@ struct Partial {
 struct Workspace {
   float* recs;           // [n_total][n_prim][kRec]
   int4* boxes;           // [n_total][n_prim] pixel box (u0, u1, v0, v1), empty = (1, 0, 1, 0)
+  float4* caps;          // [n_total][n_prim][2] bounding capsule: (p0, r), (p1, 0)
   PInfo* pinfo;          // [n_total]
   float* dof_frame;      // [n_total][n_dof][8]: kind, axis xyz, point xyz (camera frame)
   float* seg_org;        // [n_total][n_seg][4]
@@ -108,6 +109,7 @@ struct EvalArgs {
   float dbg_bg;
   TypeMasks type_masks;
   int tiles_per_item;
+  int cull;                    // 1: capsule-vs-tile-frustum test after the screen box test
   int grid;                    // persistent workgroups
   int n_prim, n_seg, n_dof;
 };
@@ -120,7 +122,7 @@ enum { kStageFk = 0, kStageSched = 1, kStageRaycast = 2, kStageFinalize = 3, kNu
 hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s);
 hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s);
 hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht_pso_params& p,
-                             int n_dof, hipStream_t s);
+                             int n_dof, int* flags, hipStream_t s);
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
                                 float* rcost, int* active, hipStream_t s);
 hipError_t launch_refine_propose(const DevModel* model, int n_ref, int n_dof, float eta_rot,

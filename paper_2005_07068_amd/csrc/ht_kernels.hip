@@ -56,10 +56,8 @@ __device__ inline void mul34(const double* A, const double* B, double* C) {
   }
 }
 
-// T <- T * Rot(axis, angle) (Rodrigues), rotation part only.
-__device__ inline void post_rotate(double* T, const double* a, double ang) {
-  double s, c;
-  sincos(ang, &s, &c);
+// T <- T * Rot(axis, angle) (Rodrigues) given sin and cos of the angle; rotation part only.
+__device__ inline void post_rotate(double* T, const double* a, double s, double c) {
   const double C = 1.0 - c;
   const double R[9] = {c + a[0] * a[0] * C, a[0] * a[1] * C - a[2] * s, a[0] * a[2] * C + a[1] * s,
                        a[1] * a[0] * C + a[2] * s, c + a[1] * a[1] * C, a[1] * a[2] * C - a[0] * s,
@@ -156,11 +154,46 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
 }
 
 // ------------------------------------------------------------------------------------
-// forward kinematics prologue: one wavefront per particle (FP64 inside)
+// work list: exclusive scan of the per-particle item counts, item -> particle map, queue
+// reset.  Run by one workgroup of kBlock threads.
+
+__device__ void schedule_items(int n_total, const Workspace& ws) {
+  __shared__ int s_sum[kBlock];
+  const int t = threadIdx.x;
+  const int chunk = (n_total + kBlock - 1) / kBlock;
+  const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
+  int local = 0;
+  for (int i = b; i < e; ++i) local += ws.pinfo[i].n_items;
+  s_sum[t] = local;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {   // Hillis-Steele inclusive scan
+    const int v = t >= o ? s_sum[t - o] : 0;
+    __syncthreads();
+    s_sum[t] += v;
+    __syncthreads();
+  }
+  int off = s_sum[t] - local;
+  for (int i = b; i < e; ++i) {
+    ws.item_off[i] = off;
+    const int n = ws.pinfo[i].n_items;
+    for (int j = 0; j < n; ++j) ws.item_map[off + j] = i;
+    off += n;
+  }
+  if (t == kBlock - 1) {
+    ws.item_off[n_total] = s_sum[t];
+    ws.counters[1] = s_sum[t];
+    ws.counters[0] = 0;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// forward kinematics prologue: one wavefront per particle (FP64 inside); the last workgroup
+// to finish builds the work list
 
 __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   __shared__ double s_T[kWavesPerBlock][HT_MAX_SEG][12];
   __shared__ double s_h[kWavesPerBlock][HT_MAX_DOF];
+  __shared__ double s_sin[kWavesPerBlock][HT_MAX_DOF], s_cos[kWavesPerBlock][HT_MAX_DOF];
   const DevModel& M = *a.model;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
   const int n_total = a.n_frames * a.n_particles;
@@ -169,12 +202,18 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   const int n_dof = a.n_dof, n_seg = a.n_seg, n_prim = a.n_prim;
   const int tpi = a.tiles_per_item;
 
+  // every angle's sine and cosine at once (one lane per pose parameter), so the tree walk
+  // below is trigonometry-free
   bool finite = true;
   if (active) {
     for (int i = lane; i < n_dof; i += kWave) {
       const float x = a.poses[(size_t)p * n_dof + i];
       s_h[w][i] = (double)x;
       finite = finite && isfinite(x);
+      double sv = 0.0, cv = 1.0;
+      if (isfinite(x)) sincos((double)x, &sv, &cv);
+      s_sin[w][i] = sv;
+      s_cos[w][i] = cv;
     }
   }
   finite = __ballot(!finite) == 0ull;
@@ -192,10 +231,9 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       if (par < 0) {
         const int b = M.seg_root_dof[lane];
         const double* q = &s_h[w][b];
-        double sx, cx, sy, cy, sz, cz;
-        sincos(q[3], &sx, &cx);
-        sincos(q[4], &sy, &cy);
-        sincos(q[5], &sz, &cz);
+        const double sx = s_sin[w][b + 3], cx = s_cos[w][b + 3];
+        const double sy = s_sin[w][b + 4], cy = s_cos[w][b + 4];
+        const double sz = s_sin[w][b + 5], cz = s_cos[w][b + 5];
         // Rz(tz) Ry(ty) Rx(tx)
         const double Rzy[9] = {cz * cy, -sz, cz * sy, sz * cy, cz, sz * sy, -sy, 0.0, cy};
         T0[0] = Rzy[0];
@@ -248,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
           f[4 + i] = (float)T[i * 4 + 3];
         }
         f[7] = 0.0f;
-        post_rotate(T, ax, s_h[w][dof]);
+        post_rotate(T, ax, s_sin[w][dof], s_cos[w][dof]);
       }
       for (int i = 0; i < 12; ++i) s_T[w][lane][i] = T[i];
       float* so = ws.seg_org + ((size_t)p * n_seg + lane) * 4;
@@ -337,6 +375,39 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       for (int i = 0; i < 4; ++i)
         dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
 
+      // bounding capsule (segment p0-p1, radius r) for per-tile frustum culling.  An
+      // ellipsoid with semi-axes a >= b >= c lies in the capsule along its a-axis from
+      // -(a - b) to (a - b) with radius b.
+      double q0[3], q1[3], cr;
+      if (typ == HT_SPHERE) {
+        for (int i = 0; i < 3; ++i) q0[i] = q1[i] = c[i];
+        cr = sz[0];
+      } else if (typ == HT_CYLINDER) {
+        for (int i = 0; i < 3; ++i) {
+          q0[i] = c[i];
+          q1[i] = c[i] + sz[1] * (double)rec[8 + i];
+        }
+        cr = sz[0];
+      } else {
+        int ia = 0;
+        for (int i = 1; i < 3; ++i)
+          if (sz[i] > sz[ia]) ia = i;
+        double b2 = 0.0;
+        for (int i = 0; i < 3; ++i)
+          if (i != ia) b2 = fmax(b2, sz[i]);
+        const double hl = sz[ia] - b2;
+        for (int i = 0; i < 3; ++i) {
+          q0[i] = c[i] - hl * F[i * 4 + ia];
+          q1[i] = c[i] + hl * F[i * 4 + ia];
+        }
+        cr = b2;
+      }
+      // margin for the FP32 rounding of the capsule and of the culling test
+      cr += 0.01 + 1e-6 * (fabs(c[0]) + fabs(c[1]) + fabs(c[2]));
+      float4* cap = ws.caps + ((size_t)p * n_prim + k) * 2;
+      cap[0] = make_float4((float)q0[0], (float)q0[1], (float)q0[2], (float)cr);
+      cap[1] = make_float4((float)q1[0], (float)q1[1], (float)q1[2], 0.0f);
+
       // conservative pixel box of the axis-aligned 3D box
       int4 box;
       if (!(lo3[2] > 1.0)) {
@@ -393,41 +464,14 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
     pi.n_items = (pi.n_tiles + tpi - 1) / tpi;
     ws.pinfo[p] = pi;
   }
+
 }
 
-// ------------------------------------------------------------------------------------
-// exclusive scan of the per-particle item counts, item -> particle map, queue reset
-
-constexpr int kSchedBlock = 1024;
-
-__global__ __launch_bounds__(kSchedBlock) void sched_kernel(int n_total, Workspace ws) {
-  __shared__ int s_sum[kSchedBlock];
-  const int t = threadIdx.x;
-  const int chunk = (n_total + kSchedBlock - 1) / kSchedBlock;
-  const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
-  int local = 0;
-  for (int i = b; i < e; ++i) local += ws.pinfo[i].n_items;
-  s_sum[t] = local;
-  __syncthreads();
-  // Hillis-Steele inclusive scan
-  for (int o = 1; o < kSchedBlock; o <<= 1) {
-    const int v = t >= o ? s_sum[t - o] : 0;
-    __syncthreads();
-    s_sum[t] += v;
-    __syncthreads();
-  }
-  int off = s_sum[t] - local;
-  for (int i = b; i < e; ++i) {
-    ws.item_off[i] = off;
-    const int n = ws.pinfo[i].n_items;
-    for (int j = 0; j < n; ++j) ws.item_map[off + j] = i;
-    off += n;
-  }
-  if (t == kSchedBlock - 1) {
-    ws.item_off[n_total] = s_sum[t];
-    ws.counters[1] = s_sum[t];
-    ws.counters[0] = 0;
-  }
+// The work list is built by its own one-workgroup launch: folding it into the kinematics
+// kernel as "the last workgroup to finish builds it" needs a device-scope fence in every
+// workgroup, which on a multi-XCD part (one L2 per XCD) costs far more than a launch.
+__global__ __launch_bounds__(kBlock) void sched_kernel(int n_total, Workspace ws) {
+  schedule_items(n_total, ws);
 }
 
 // ------------------------------------------------------------------------------------
@@ -542,18 +586,15 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   const float cc = par ? 0.0f : -B * invA;
   const float h2 = par ? r[3] - rho2 : fmaf(B, B * invA, r[3] - rho2);
   const float hs = par ? INFINITY : fast_sqrt(fmaxf(h2, 0.0f) * invA);
-  float din, dout;
-  if (da != 0.0f) {
-    const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
-    din = fminf(d0, d1);
-    dout = fmaxf(d0, d1);
-  } else {
-    const bool inside = a3 >= 0.0f && a3 <= L;
-    din = inside ? -INFINITY : INFINITY;
-    dout = inside ? INFINITY : -INFINITY;
-  }
+  // slab 0 <= s <= L as offsets from t_r; a ray perpendicular to the axis (da == 0) is inside
+  // the slab everywhere or nowhere
+  const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
+  const bool flat = da == 0.0f;
+  const bool inside = (a3 >= 0.0f) & (a3 <= L);
+  const float din = flat ? (inside ? -INFINITY : INFINITY) : fminf(d0, d1);
+  const float dout = flat ? (inside ? INFINITY : -INFINITY) : fmaxf(d0, d1);
   const float tin = fmaxf(cc - hs, din), tout = fminf(cc + hs, dout);
-  h.ok = h2 >= 0.0f && tin <= tout;
+  h.ok = (h2 >= 0.0f) & (tin <= tout);
   h.t = tr + tin;
   if (GRAD) {
     // entry point relative to p0 and the outward normal of the entry surface
@@ -576,6 +617,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
                                                          TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
   __shared__ int4 s_box[HT_MAX_PRIM];
+  __shared__ float4 s_cap[2 * HT_MAX_PRIM];
   __shared__ int s_item;
   __shared__ float s_td[kWavesPerBlock];
   __shared__ int s_a[kWavesPerBlock], s_o[kWavesPerBlock];
@@ -600,6 +642,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       const float4* src = reinterpret_cast<const float4*>(ws.recs + (size_t)p * n_prim * kRec);
       for (int i = tid; i < n_prim * (kRec / 4); i += kBlock) s_rec[i] = src[i];
       for (int i = tid; i < n_prim; i += kBlock) s_box[i] = ws.boxes[(size_t)p * n_prim + i];
+      for (int i = tid; i < 2 * n_prim; i += kBlock)
+        s_cap[i] = ws.caps[(size_t)p * n_prim * 2 + i];
       cur_p = p;
       pi = ws.pinfo[p];
       fs = a.slots[pi.slot];
@@ -617,6 +661,16 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
     for (int t = c * tpi + wave; t < t_end; t += kWavesPerBlock) {
       const int tx = pi.tx0 + t % pi.tw, ty = pi.ty0 + t / pi.tw;
       const int x0 = tx * kTile, y0 = ty * kTile;
+      // culling, one lane per primitive: screen box overlap, then the bounding capsule
+      // against the four planes through the camera that bound the tile's pixel rays
+      // (x/z in [ax0, ax1], y/z in [ay0, ay1])
+      const float inv_sz = 1.0f / fs.sz;
+      const float ax0 = ((float)x0 - fs.cx) * fs.sx * inv_sz;
+      const float ax1 = ((float)(x0 + kTile - 1) - fs.cx) * fs.sx * inv_sz;
+      const float ay0 = ((float)y0 - fs.cy) * fs.sy * inv_sz;
+      const float ay1 = ((float)(y0 + kTile - 1) - fs.cy) * fs.sy * inv_sz;
+      const float nx0 = sqrtf(fmaf(ax0, ax0, 1.0f)), nx1 = sqrtf(fmaf(ax1, ax1, 1.0f));
+      const float ny0 = sqrtf(fmaf(ay0, ay0, 1.0f)), ny1 = sqrtf(fmaf(ay1, ay1, 1.0f));
       uint64_t mk[2];
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
@@ -625,6 +679,14 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
         if (k < n_prim) {
           const int4 b = s_box[k];
           ov = b.x <= x0 + kTile - 1 && b.y >= x0 && b.z <= y0 + kTile - 1 && b.w >= y0;
+          if (ov && a.cull) {
+            const float4 c0 = s_cap[2 * k], c1 = s_cap[2 * k + 1];
+            const float r = c0.w;
+            ov = fmaxf(fmaf(-ax0, c0.z, c0.x), fmaf(-ax0, c1.z, c1.x)) >= -r * nx0 &&
+                 fmaxf(fmaf(ax1, c0.z, -c0.x), fmaf(ax1, c1.z, -c1.x)) >= -r * nx1 &&
+                 fmaxf(fmaf(-ay0, c0.z, c0.y), fmaf(-ay0, c1.z, c1.y)) >= -r * ny0 &&
+                 fmaxf(fmaf(ay1, c0.z, -c0.y), fmaf(ay1, c1.z, -c1.y)) >= -r * ny1;
+          }
         }
         mk[half] = __ballot(ov);
       }
@@ -659,15 +721,17 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
             else if (typ == HT_CYLINDER) cylinder_test<GRAD>(r, dx, dy, dz, dd, h);
             else ellipsoid_test<GRAD>(r, dx, dy, dz, h);
             const float z = h.t * dz;
-            // nearest entry; ties keep the lower primitive index
-            const bool take = h.ok && (z < zmin || (z == zmin && win >= 0 && k < win));
-            if (take) {
-              zmin = z;
-              win = k;
-              if (GRAD) {
-                wnx = h.nx; wny = h.ny; wnz = h.nz;
-                wrx = h.rx; wry = h.ry; wrz = h.rz;
-              }
+            // nearest entry; ties keep the lower primitive index (branch-free selects)
+            const bool take = h.ok & ((z < zmin) | ((z == zmin) & (k < win)));
+            zmin = take ? z : zmin;
+            win = take ? k : win;
+            if (GRAD) {
+              wnx = take ? h.nx : wnx;
+              wny = take ? h.ny : wny;
+              wnz = take ? h.nz : wnz;
+              wrx = take ? h.rx : wrx;
+              wry = take ? h.ry : wry;
+              wrz = take ? h.rz : wrz;
             }
           }
         }
@@ -761,19 +825,9 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 // ------------------------------------------------------------------------------------
 // finalize: combine partials in item order, Eq. 4-5, and the kinematic adjoint
 
-template <bool GRAD>
-__global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace ws) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  const int n_total = a.n_frames * a.n_particles;
-  if (p >= n_total) return;
-  const PInfo pi = ws.pinfo[p];
-  const int n_dof = a.n_dof, n_seg = a.n_seg;
-  if (!pi.valid) {
-    a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
-    if (GRAD)
-      for (int j = 0; j < n_dof; ++j) a.grad[(size_t)p * n_dof + j] = 0.0f;
-    return;
-  }
+// Eq. 4-5 from the particle's partials, summed in item order (FP64).
+__device__ inline float assemble_cost(const EvalArgs& a, const Workspace& ws, const PInfo& pi,
+                                      int p, long long* s_or_out) {
   const FrameSlot& fs = a.slots[pi.slot];
   double S_d = fs.totals[0];
   long long S_and = 0, S_or = (long long)fs.totals[1];
@@ -791,49 +845,81 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace 
     D = S_d / (double)S_or +
         kLambda * (1.0 - 2.0 * (double)S_and / (double)(S_and + S_or));
   }
-  a.cost[p] = (float)(D + kLambdaK * (double)pi.kc);
-  if (GRAD) {
-    const DevModel& M = *a.model;
-    // per-segment wrench (moment about the segment origin, force), summed in item order
-    double W[HT_MAX_SEG][6];
-    for (int s = 0; s < n_seg; ++s)
-      for (int q = 0; q < 6; ++q) W[s][q] = 0.0;
-    for (int i = b; i < e; ++i) {
-      const float* src = ws.wrench + (size_t)i * n_seg * 6;
-      for (int s = 0; s < n_seg; ++s)
-        for (int q = 0; q < 6; ++q) W[s][q] += (double)src[s * 6 + q];
-    }
-    const double inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
+  if (s_or_out) *s_or_out = S_or;
+  return (float)(D + kLambdaK * (double)pi.kc);
+}
+
+// Forward: one thread per particle.
+__global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace ws) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int n_total = a.n_frames * a.n_particles;
+  if (p >= n_total) return;
+  const PInfo pi = ws.pinfo[p];
+  a.cost[p] = pi.valid ? assemble_cost(a, ws, pi, p, nullptr) : (pi.slot < 0 ? NAN : INFINITY);
+}
+
+// Gradient: one workgroup per particle.  Threads (segment, component) sum the per-item
+// wrenches in item order; then one thread per pose parameter applies the kinematic adjoint
+//   dE/dh_j = (1/S_or) sum_{s moved by j} a_j . (M_s + (q_s - q_j) x F_s)   (rotation)
+//   dE/dh_j = (1/S_or) sum_{s moved by j} e_j . F_s                       (translation)
+// with M_s, F_s the moment about the segment origin q_s and the force of segment s.
+__global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Workspace ws) {
+  __shared__ double s_W[HT_MAX_SEG * 6];
+  __shared__ double s_inv_or;
+  const int p = blockIdx.x, t = threadIdx.x;
+  const PInfo pi = ws.pinfo[p];
+  const int n_dof = a.n_dof, n_seg = a.n_seg;
+  if (!pi.valid) {
+    if (t == 0) a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
+    for (int j = t; j < n_dof; j += kBlock) a.grad[(size_t)p * n_dof + j] = 0.0f;
+    return;
+  }
+  const int b = ws.item_off[p], e = b + pi.n_items;
+  if (t < n_seg * 6) {
+    double acc = 0.0;
+    for (int i = b; i < e; ++i) acc += (double)ws.wrench[(size_t)i * n_seg * 6 + t];
+    s_W[t] = acc;
+  }
+  if (t == kBlock - 1) {
+    long long S_or = 0;
+    a.cost[p] = assemble_cost(a, ws, pi, p, &S_or);
+    s_inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
+  }
+  __syncthreads();
+  const DevModel& M = *a.model;
+  if (t < n_dof) {
+    const int j = t;
+    const float* f = ws.dof_frame + ((size_t)p * n_dof + j) * 8;
     const float* org = ws.seg_org + (size_t)p * n_seg * 4;
-    for (int j = 0; j < n_dof; ++j) {
-      const float* f = ws.dof_frame + ((size_t)p * n_dof + j) * 8;
-      const uint32_t desc = M.dof_desc[j];
-      double g = 0.0;
-      for (int s = 0; s < n_seg; ++s) {
-        if (!((desc >> s) & 1u)) continue;
-        if (f[0] != 0.0f) {
-          g += f[1] * W[s][3] + f[2] * W[s][4] + f[3] * W[s][5];
-        } else {
-          // a . (M_s + (q_s - q_j) x F_s)
-          const double lx = (double)org[s * 4 + 0] - f[4];
-          const double ly = (double)org[s * 4 + 1] - f[5];
-          const double lz = (double)org[s * 4 + 2] - f[6];
-          const double mx = W[s][0] + (ly * W[s][5] - lz * W[s][4]);
-          const double my = W[s][1] + (lz * W[s][3] - lx * W[s][5]);
-          const double mz = W[s][2] + (lx * W[s][4] - ly * W[s][3]);
-          g += f[1] * mx + f[2] * my + f[3] * mz;
-        }
+    const uint32_t desc = M.dof_desc[j];
+    const bool trans = f[0] != 0.0f;
+    const double ax = f[1], ay = f[2], az = f[3];
+    double g = 0.0;
+    for (int s = 0; s < n_seg; ++s) {
+      if (!((desc >> s) & 1u)) continue;
+      const double* W = s_W + s * 6;
+      if (trans) {
+        g += ax * W[3] + ay * W[4] + az * W[5];
+      } else {
+        const double lx = (double)org[s * 4 + 0] - f[4];
+        const double ly = (double)org[s * 4 + 1] - f[5];
+        const double lz = (double)org[s * 4 + 2] - f[6];
+        const double mx = W[0] + (ly * W[5] - lz * W[4]);
+        const double my = W[1] + (lz * W[3] - lx * W[5]);
+        const double mz = W[2] + (lx * W[4] - ly * W[3]);
+        g += ax * mx + ay * my + az * mz;
       }
-      g *= inv_or;
-      a.grad[(size_t)p * n_dof + j] = (float)g;
     }
+    g *= s_inv_or;
+    // collision term of Eq. 5
     const float* h = a.poses + (size_t)p * n_dof;
     for (int i = 0; i < M.n_kc; ++i) {
       if ((double)h[M.kc_a[i]] - (double)h[M.kc_b[i]] < 0.0) {
-        a.grad[(size_t)p * n_dof + M.kc_a[i]] -= (float)kLambdaK;
-        a.grad[(size_t)p * n_dof + M.kc_b[i]] += (float)kLambdaK;
+        if (M.kc_a[i] == j) g -= kLambdaK;
+        if (M.kc_b[i] == j) g += kLambdaK;
       }
     }
+    a.grad[(size_t)p * n_dof + j] = (float)g;
   }
 }
 
@@ -851,7 +937,7 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
                          dim3(kBlock), 0, s, a, ws);
       break;
     case kStageSched:
-      hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kSchedBlock), 0, s, n_total, ws);
+      hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kBlock), 0, s, n_total, ws);
       if (dbg) {
         const size_t n = (size_t)a.n_particles * a.dbg_H * a.dbg_W;
         hipLaunchKernelGGL(debug_fill_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
@@ -872,10 +958,9 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
     }
     case kStageFinalize:
       if (a.grad)
-        hipLaunchKernelGGL(finalize_kernel<true>, dim3((n_total + kBlock - 1) / kBlock),
-                           dim3(kBlock), 0, s, a, ws);
+        hipLaunchKernelGGL(finalize_grad_kernel, dim3(n_total), dim3(kBlock), 0, s, a, ws);
       else
-        hipLaunchKernelGGL(finalize_kernel<false>, dim3((n_total + kBlock - 1) / kBlock),
+        hipLaunchKernelGGL(finalize_kernel, dim3((n_total + kBlock - 1) / kBlock),
                            dim3(kBlock), 0, s, a, ws);
       break;
     default:

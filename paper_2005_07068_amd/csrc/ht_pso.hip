@@ -1,10 +1,14 @@
 // Particle swarm kernels: initialisation, the generation update of Eq. 6-7 with the mutation
-// of section III.B, and the three stages of gradient refinement (select, propose, accept).
+// of section III.B, and the stages of gradient refinement (select, propose, accept, gather).
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed, counter
 // (dimension, frame * P + particle, generation, stream); uniform = (word >> 8) * 2^-24.
 // Stream 0 gives r1 (word 0) and r2 (word 1) of Eq. 6, stream 1 the initial positions,
 // stream 2 the mutation re-draws.
+//
+// A generation's update is two launches: `pso_best_kernel` (one workgroup per frame: personal
+// and global bests, the mutation ranking, the generation counter) and `pso_move_kernel` (one
+// thread per particle dimension: personal-best copy, then mutation or Eq. 6-7 with clamping).
 #include <math.h>
 
 #include "ht_device.h"
@@ -38,6 +42,11 @@ __device__ __forceinline__ uint4 draw(uint64_t seed, int dim, int gpart, int gen
 }
 
 __device__ __forceinline__ float cost_key(float c) { return isnan(c) ? INFINITY : c; }
+
+constexpr int kFlagImproved = 1, kFlagMutated = 2;
+constexpr int kPsoBlock = 1024;
+
+int threads_for(int n) { return n >= kPsoBlock ? kPsoBlock : ((n + kWave - 1) / kWave) * kWave; }
 
 }  // namespace
 
@@ -80,13 +89,10 @@ hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof,
 }
 
 // ------------------------------------------------------------------------------------
-// one generation's update for every frame: one workgroup per frame
+// generation update, part 1: one workgroup per frame
 
-constexpr int kPsoBlock = 1024;
-
-__global__ __launch_bounds__(kPsoBlock) void pso_update_kernel(const DevModel* __restrict__ M,
-                                                               ht_swarm sw, ht_pso_params prm,
-                                                               int n_dof) {
+__global__ __launch_bounds__(kPsoBlock) void pso_best_kernel(ht_swarm sw, ht_pso_params prm,
+                                                             int n_dof, int* __restrict__ flags) {
   extern __shared__ float s_mem[];
   const int P = sw.n_particles;
   float* s_cost = s_mem;          // [P] current costs (NaN -> +inf)
@@ -103,13 +109,14 @@ __global__ __launch_bounds__(kPsoBlock) void pso_update_kernel(const DevModel* _
     const float c = cost_key(sw.cost[base + i]);
     s_cost[i] = c;
     float pb = sw.pbest_cost[base + i];
+    int fl = 0;
     if (c < pb) {
       pb = c;
-      for (int d = 0; d < n_dof; ++d)
-        sw.pbest_x[(base + i) * n_dof + d] = sw.x[(base + i) * n_dof + d];
       sw.pbest_cost[base + i] = c;
+      fl = kFlagImproved;
     }
     s_pb[i] = pb;
+    flags[base + i] = fl;
   }
   __syncthreads();
 
@@ -146,21 +153,23 @@ __global__ __launch_bounds__(kPsoBlock) void pso_update_kernel(const DevModel* _
         idx = s_ri[q];
       }
     }
-    // every personal best is +inf only before any finite cost: keep particle 0
+    // all personal bests +inf (no finite cost yet): keep particle 0
     s_g = idx == INT_MAX ? 0 : idx;
     sw.gbest_cost[f] = s_pb[s_g];
   }
   __syncthreads();
   const int g = s_g;
+  // the global best position is the best particle's personal best, which is its current
+  // position if it improved in this generation (read before any position moves)
+  const bool g_improved = (flags[base + g] & kFlagImproved) != 0;
   for (int d = tid; d < n_dof; d += blockDim.x)
-    sw.gbest_x[(size_t)f * n_dof + d] = sw.pbest_x[(base + g) * n_dof + d];
+    sw.gbest_x[(size_t)f * n_dof + d] =
+        g_improved ? sw.x[(base + g) * n_dof + d] : sw.pbest_x[(base + g) * n_dof + d];
 
   const bool mutate_gen = prm.mutate_every > 0 && (gen + 1) % prm.mutate_every == 0;
   const int n_mut = (int)floorf((float)P * prm.mutate_frac);
-  for (int i = tid; i < P; i += blockDim.x) {
-    const int gp = (int)(base + i);
-    bool mutated = false;
-    if (mutate_gen && n_mut > 0) {
+  if (mutate_gen && n_mut > 0) {
+    for (int i = tid; i < P; i += blockDim.x) {
       // rank 0 is the worst: higher cost, ties to the higher index
       const float ci = s_cost[i];
       int rank = 0;
@@ -168,51 +177,67 @@ __global__ __launch_bounds__(kPsoBlock) void pso_update_kernel(const DevModel* _
         const float cj = s_cost[j];
         rank += (cj > ci || (cj == ci && j > i)) ? 1 : 0;
       }
-      mutated = rank < n_mut;
-    }
-    float* x = sw.x + (size_t)gp * n_dof;
-    float* v = sw.v + (size_t)gp * n_dof;
-    if (mutated) {
-      for (int d = 0; d < n_dof; ++d) {
-        if (!M->mutate[d]) continue;
-        const float u = unit(draw(sw.seed, d, gp, gen, 2).x);
-        x[d] = fmaf(u, M->hi[d] - M->lo[d], M->lo[d]);
-        v[d] = 0.0f;
-      }
-    } else {
-      const float* pb = sw.pbest_x + (size_t)gp * n_dof;
-      const float* gb = sw.pbest_x + (base + g) * n_dof;
-      for (int d = 0; d < n_dof; ++d) {
-        const uint4 r = draw(sw.seed, d, gp, gen, 0);
-        const float r1 = unit(r.x), r2 = unit(r.y);
-        const float xd = x[d];
-        const float t = fmaf(prm.c2 * r2, gb[d] - xd, fmaf(prm.c1 * r1, pb[d] - xd, v[d]));
-        float vn = prm.w * t;
-        float xn = xd + vn;
-        if (xn < M->lo[d]) {
-          xn = M->lo[d];
-          vn = 0.0f;
-        } else if (xn > M->hi[d]) {
-          xn = M->hi[d];
-          vn = 0.0f;
-        }
-        x[d] = xn;
-        v[d] = vn;
-      }
+      if (rank < n_mut) flags[base + i] |= kFlagMutated;
     }
   }
   __syncthreads();
   if (tid == 0) sw.gen[f] = gen + 1;
 }
 
+// generation update, part 2: one thread per (frame, particle, dimension)
+__global__ __launch_bounds__(kBlock) void pso_move_kernel(const DevModel* __restrict__ M,
+                                                          ht_swarm sw, ht_pso_params prm,
+                                                          int n_dof,
+                                                          const int* __restrict__ flags) {
+  const int P = sw.n_particles;
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (size_t)sw.n_frames * P * n_dof) return;
+  const int d = (int)(i % n_dof);
+  const int gp = (int)(i / n_dof);
+  const int f = gp / P;
+  const int gen = sw.gen[f] - 1;            // part 1 already advanced the counter
+  const int fl = flags[gp];
+  const float xd = sw.x[i];
+  float pb = sw.pbest_x[i];
+  if (fl & kFlagImproved) {
+    pb = xd;
+    sw.pbest_x[i] = xd;
+  }
+  const float lo = M->lo[d], hi = M->hi[d];
+  if (fl & kFlagMutated) {
+    if (M->mutate[d]) {
+      const float u = unit(draw(sw.seed, d, gp, gen, 2).x);
+      sw.x[i] = fmaf(u, hi - lo, lo);
+      sw.v[i] = 0.0f;
+    }
+    return;
+  }
+  const uint4 r = draw(sw.seed, d, gp, gen, 0);
+  const float r1 = unit(r.x), r2 = unit(r.y);
+  const float gb = sw.gbest_x[(size_t)f * n_dof + d];
+  const float t = fmaf(prm.c2 * r2, gb - xd, fmaf(prm.c1 * r1, pb - xd, sw.v[i]));
+  float vn = prm.w * t;
+  float xn = xd + vn;
+  if (xn < lo) {
+    xn = lo;
+    vn = 0.0f;
+  } else if (xn > hi) {
+    xn = hi;
+    vn = 0.0f;
+  }
+  sw.x[i] = xn;
+  sw.v[i] = vn;
+}
+
 hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht_pso_params& p,
-                             int n_dof, hipStream_t s) {
+                             int n_dof, int* flags, hipStream_t s) {
   if (sw.n_frames == 0 || sw.n_particles == 0) return hipSuccess;
-  const int threads = sw.n_particles >= kPsoBlock ? kPsoBlock
-                                                  : ((sw.n_particles + kWave - 1) / kWave) * kWave;
   const size_t shm = 2 * (size_t)sw.n_particles * sizeof(float);
-  hipLaunchKernelGGL(pso_update_kernel, dim3(sw.n_frames), dim3(threads), shm, s, model, sw, p,
-                     n_dof);
+  hipLaunchKernelGGL(pso_best_kernel, dim3(sw.n_frames), dim3(threads_for(sw.n_particles)), shm,
+                     s, sw, p, n_dof, flags);
+  const size_t n = (size_t)sw.n_frames * sw.n_particles * n_dof;
+  hipLaunchKernelGGL(pso_move_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, model, sw, p, n_dof, flags);
   return hipGetLastError();
 }
 
@@ -230,6 +255,7 @@ __global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, i
                                                                   float* __restrict__ rcost,
                                                                   int* __restrict__ active) {
   extern __shared__ float s_cost[];
+  int* s_sel = reinterpret_cast<int*>(s_cost + sw.n_particles);
   const int P = sw.n_particles, f = blockIdx.x;
   const size_t base = (size_t)f * P;
   for (int i = threadIdx.x; i < P; i += blockDim.x) s_cost[i] = cost_key(sw.cost[base + i]);
@@ -243,14 +269,20 @@ __global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, i
     }
     if (rank < K) {
       const size_t r = (size_t)f * K + rank;
+      s_sel[rank] = i;
       sel[r] = i;
       rcost[r] = ci;
       active[r] = 1;
-      for (int d = 0; d < n_dof; ++d) rx[r * n_dof + d] = sw.x[(base + i) * n_dof + d];
     }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < K * n_dof; e += blockDim.x) {
+    const int r = e / n_dof, d = e % n_dof;
+    rx[((size_t)f * K + r) * n_dof + d] = sw.x[(base + s_sel[r]) * n_dof + d];
   }
 }
 
+// one wavefront per refined particle, one lane per dimension
 __global__ __launch_bounds__(kBlock) void refine_propose_kernel(const DevModel* __restrict__ M,
                                                                 int n_ref, int n_dof,
                                                                 float eta_rot, float eta_trans,
@@ -258,31 +290,28 @@ __global__ __launch_bounds__(kBlock) void refine_propose_kernel(const DevModel* 
                                                                 const float* __restrict__ grad,
                                                                 const int* __restrict__ active,
                                                                 float* __restrict__ cand) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (r >= n_ref) return;
-  const float* x = rx + (size_t)r * n_dof;
-  const float* g = grad + (size_t)r * n_dof;
-  float gmax = 0.0f;
-  bool ok = active[r] != 0;
-  for (int d = 0; d < n_dof; ++d) {
-    const float eta = M->dof_trans[d] ? eta_trans : eta_rot;
-    const float gs = eta * g[d];
-    ok = ok && isfinite(gs);
-    gmax = fmaxf(gmax, fabsf(gs));
-  }
-  ok = ok && gmax > 0.0f;
+  const bool on = lane < n_dof;
+  const int d = on ? lane : 0;
+  const float eta = M->dof_trans[d] ? eta_trans : eta_rot;
+  const float x = on ? rx[(size_t)r * n_dof + d] : 0.0f;
+  const float gs = on ? eta * grad[(size_t)r * n_dof + d] : 0.0f;
+  float gmax = fabsf(gs);
+  bool fin = isfinite(gs);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o));
+  fin = __ballot(!fin) == 0ull;
+  const bool ok = active[r] != 0 && fin && gmax > 0.0f;
+  if (!on) return;
   for (int j = 0; j < 4; ++j) {
-    float* c = cand + ((size_t)r * 4 + j) * n_dof;
-    const float scale = ldexpf(1.0f, -j);
-    for (int d = 0; d < n_dof; ++d) {
-      float xn = x[d];
-      if (ok) {
-        const float eta = M->dof_trans[d] ? eta_trans : eta_rot;
-        const float step = eta * (eta * g[d] / gmax) * scale;
-        xn = fminf(fmaxf(x[d] - step, M->lo[d]), M->hi[d]);
-      }
-      c[d] = xn;
+    float xn = x;
+    if (ok) {
+      const float step = eta * (gs / gmax) * ldexpf(1.0f, -j);
+      xn = fminf(fmaxf(x - step, M->lo[d]), M->hi[d]);
     }
+    cand[((size_t)r * 4 + j) * n_dof + d] = xn;
   }
 }
 
@@ -292,63 +321,63 @@ __global__ __launch_bounds__(kBlock) void refine_accept_kernel(int n_ref, int n_
                                                                const float* __restrict__ cand,
                                                                const float* __restrict__ ccost,
                                                                int* __restrict__ active) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (r >= n_ref || !active[r]) return;
   const float c0 = rcost[r];
-  for (int j = 0; j < 4; ++j) {
-    const float cj = ccost[(size_t)r * 4 + j];
-    if (cj < c0) {
-      for (int d = 0; d < n_dof; ++d)
-        rx[(size_t)r * n_dof + d] = cand[((size_t)r * 4 + j) * n_dof + d];
-      rcost[r] = cj;
-      return;
-    }
+  int pick = -1;
+  for (int j = 3; j >= 0; --j)
+    if (ccost[(size_t)r * 4 + j] < c0) pick = j;
+  if (pick < 0) {
+    if (lane == 0) active[r] = 0;
+    return;
   }
-  active[r] = 0;
+  if (lane < n_dof) rx[(size_t)r * n_dof + lane] = cand[((size_t)r * 4 + pick) * n_dof + lane];
+  if (lane == 0) rcost[r] = ccost[(size_t)r * 4 + pick];
 }
 
 __global__ __launch_bounds__(kBlock) void refine_gather_kernel(ht_swarm sw, int K, int n_dof,
                                                                const int* __restrict__ sel,
                                                                const float* __restrict__ rx,
                                                                const float* __restrict__ rcost) {
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  if (r >= sw.n_frames * K) return;
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= (size_t)sw.n_frames * K * n_dof) return;
+  const int r = (int)(e / n_dof), d = (int)(e % n_dof);
   const int f = r / K;
   const size_t gp = (size_t)f * sw.n_particles + sel[r];
-  for (int d = 0; d < n_dof; ++d) sw.x[gp * n_dof + d] = rx[(size_t)r * n_dof + d];
-  sw.cost[gp] = rcost[r];
+  sw.x[gp * n_dof + d] = rx[e];
+  if (d == 0) sw.cost[gp] = rcost[r];
 }
 
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
                                 float* rcost, int* active, hipStream_t s) {
-  const int threads = sw.n_particles >= kPsoBlock ? kPsoBlock
-                                                  : ((sw.n_particles + kWave - 1) / kWave) * kWave;
-  hipLaunchKernelGGL(refine_select_kernel, dim3(sw.n_frames), dim3(threads),
-                     (size_t)sw.n_particles * sizeof(float), s, sw, K, n_dof, sel, rx, rcost,
-                     active);
+  hipLaunchKernelGGL(refine_select_kernel, dim3(sw.n_frames), dim3(threads_for(sw.n_particles)),
+                     (size_t)sw.n_particles * sizeof(float) + (size_t)K * sizeof(int), s, sw, K,
+                     n_dof, sel, rx, rcost, active);
   return hipGetLastError();
 }
 
 hipError_t launch_refine_propose(const DevModel* model, int n_ref, int n_dof, float eta_rot,
                                  float eta_trans, const float* rx, const float* grad,
                                  const int* active, float* cand, hipStream_t s) {
-  hipLaunchKernelGGL(refine_propose_kernel, dim3((n_ref + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                     s, model, n_ref, n_dof, eta_rot, eta_trans, rx, grad, active, cand);
+  hipLaunchKernelGGL(refine_propose_kernel, dim3((n_ref + kWavesPerBlock - 1) / kWavesPerBlock),
+                     dim3(kBlock), 0, s, model, n_ref, n_dof, eta_rot, eta_trans, rx, grad,
+                     active, cand);
   return hipGetLastError();
 }
 
 hipError_t launch_refine_accept(int n_ref, int n_dof, float* rx, float* rcost, const float* cand,
                                 const float* ccost, int* active, hipStream_t s) {
-  hipLaunchKernelGGL(refine_accept_kernel, dim3((n_ref + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                     s, n_ref, n_dof, rx, rcost, cand, ccost, active);
+  hipLaunchKernelGGL(refine_accept_kernel, dim3((n_ref + kWavesPerBlock - 1) / kWavesPerBlock),
+                     dim3(kBlock), 0, s, n_ref, n_dof, rx, rcost, cand, ccost, active);
   return hipGetLastError();
 }
 
 hipError_t launch_refine_gather(const ht_swarm& sw, int K, int n_dof, const int* sel,
                                 const float* rx, const float* rcost, hipStream_t s) {
-  const int n = sw.n_frames * K;
-  hipLaunchKernelGGL(refine_gather_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     sw, K, n_dof, sel, rx, rcost);
+  const size_t n = (size_t)sw.n_frames * K * n_dof;
+  hipLaunchKernelGGL(refine_gather_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, sw, K, n_dof, sel, rx, rcost);
   return hipGetLastError();
 }
 

@@ -70,8 +70,8 @@ def test_debug_and_plain_costs_identical_and_deterministic():
     c2 = ctx.eval(p, slots).cpu().numpy()
     assert np.array_equal(c1, c2)
     assert np.array_equal(c1, c_dbg)
-    for tpi, gpc in ((4, 1), (64, 8)):
-        ctx.set_launch_config(tpi, gpc)
+    for tpi, gpc, cull in ((4, 1, 0), (64, 8, 1), (16, 2, 0)):
+        ctx.set_launch_config(tpi, gpc, cull)
         c3 = ctx.eval(p, slots).cpu().numpy()
         assert np.allclose(c3, c1, rtol=1e-6, atol=0)
 

@@ -29,7 +29,7 @@ def test_adjoint_matches_fp64_gradient_on_smooth_pixels(i):
     scale = np.max(np.abs(g_ref))
     err = np.max(np.abs(g - g_ref))
     print(f"pose {i}: |g_ref|inf {scale:.4g}, max err {err:.3g}, rel {err / scale:.3g}")
-    assert err <= 1e-4 * scale
+    assert err <= 1e-5 * scale
 
 
 def test_autograd_function_backward():
