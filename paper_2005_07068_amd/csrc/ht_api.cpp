@@ -253,11 +253,12 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
     a.dbg_bg = sh.entry.bg;
   }
   a.type_masks = c->tmask;
-  // small launches (a few particles) take shorter work items so the persistent grid still
-  // gets about one item per compute unit; about a quarter of an ROI's tiles are touched
+  // small launches (a few particles) take shorter work items so that there are about as many
+  // items as persistent workgroups; about a quarter of an ROI's tiles are touched
   int tpi = c->lc.tiles_per_item;
   const long long est_tiles = (long long)n_total * c->max_tiles() / 4;
-  while (tpi > 8 && est_tiles / tpi < (long long)c->n_cu) tpi /= 2;
+  const long long groups = (long long)c->n_cu * c->lc.groups_per_cu;
+  while (tpi > 8 && est_tiles / tpi < groups) tpi /= 2;
   a.tiles_per_item = std::max(std::min(tpi, c->lc.tiles_per_item), kMinTilesPerItem);
   a.cull = c->lc.cull;
   const long long bound = (long long)n_total *
@@ -390,6 +391,12 @@ ht_status build_model(const ht_model* m, ht::DevModel& d, ht::TypeMasks& tm) {
   }
   for (int j = 0; j < m->n_dof; ++j)
     if (used[j] > 1) return fail(HT_ERR_ARG, "pose parameter %d drives more than one joint", j);
+  // kinematic trees (hands): trees beyond kMaxRects share the last tile rectangle
+  std::vector<int> tree(m->n_seg, 0);
+  d.n_roots = 0;
+  for (int s = 0; s < m->n_seg; ++s)
+    tree[s] = d.seg_parent[s] < 0 ? std::min(d.n_roots++, ht::kMaxRects - 1) : tree[d.seg_parent[s]];
+  d.n_roots = std::min(d.n_roots, ht::kMaxRects);
   // segments moved by each pose parameter: the driven segment and its descendants
   for (int s = 0; s < m->n_seg; ++s) {
     for (int q = s; q >= 0; q = d.seg_parent[q]) {
@@ -406,6 +413,7 @@ ht_status build_model(const ht_model* m, ht::DevModel& d, ht::TypeMasks& tm) {
     if (s < 0 || s >= m->n_seg) return fail(HT_ERR_ARG, "primitive %d: segment %d out of range", k, s);
     d.prim_type[k] = t;
     d.prim_seg[k] = s;
+    d.prim_root[k] = tree[s];
     for (int i = 0; i < 12; ++i) d.prim_frame[k][i] = m->prim_frame[k * 12 + i];
     const int need = t == HT_SPHERE ? 1 : (t == HT_CYLINDER ? 2 : 3);
     for (int i = 0; i < 3; ++i) {

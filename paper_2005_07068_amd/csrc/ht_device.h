@@ -43,7 +43,11 @@ struct DevModel {
   int kc_a[HT_MAX_KC], kc_b[HT_MAX_KC];
   uint32_t dof_desc[HT_MAX_DOF];         // segments moved by each pose parameter
   int dof_trans[HT_MAX_DOF];             // 1 for the wrist translations (mm), else angle
+  int n_roots;                           // independent kinematic trees (hands)
+  int prim_root[HT_MAX_PRIM];            // tree of each primitive
 };
+
+constexpr int kMaxRects = 4;             // tile rectangles per particle (one per tree)
 
 // Primitive index masks per type (bits for primitives 0..63 and 64..127).
 struct TypeMasks {
@@ -63,17 +67,22 @@ struct FrameSlot {
   const double* totals;      // [2]: the same two sums over the whole ROI
 };
 
-// Per-particle summary written by the kinematics kernel.
+// Per-particle summary written by the kinematics kernel.  The tiles to visit are the union of
+// up to kMaxRects disjoint rectangles (one per kinematic tree, overlapping ones merged), each
+// covering its primitives' screen boxes; tile t of the particle is found by walking them.
 struct PInfo {
-  int tx0, ty0, tw, n_tiles;  // tile rectangle covering every primitive's screen box
+  int4 rect[kMaxRects];       // tx0, ty0, tw, th (tiles)
+  int n_rects;
+  int n_tiles;                // sum of the rectangles' tiles
   int n_items;                // work items of the ray-cast kernel
   int slot;                   // observation slot (-1: unset slot)
   float kc;                   // collision term of Eq. 5
   int valid;                  // 0: non-finite pose or unset slot
+  int pad[2];
 };
 
 struct Partial {
-  float td;   // clamped depth sum minus the background sum of the processed tiles
+  double td;  // clamped depth sum minus the background sum of the processed tiles
   int a;      // sum(o_s and r_m)
   int o;      // sum(o_s or r_m) minus the background skin count of the processed tiles
   int pad;

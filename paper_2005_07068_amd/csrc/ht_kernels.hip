@@ -7,7 +7,10 @@
 // summed once per observation, so only touched tiles are visited.  A work item is a run of
 // `tiles_per_item` touched-rectangle tiles of one particle; persistent workgroups of four
 // wavefronts dequeue items, stage the particle's primitive table in LDS and write one
-// partial per item, which the finalize kernel combines in item order (deterministic).
+// partial per item, which the finalize kernel combines in item order (deterministic).  The
+// clamped depth sum is accumulated in FP64: its FP32 per-pixel terms are multiples of
+// 2^-15 mm (depths of at least 256 mm), so the sum is exact and the cost does not depend on
+// how the tiles were split into items.
 #include <float.h>
 #include <math.h>
 
@@ -22,6 +25,11 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 __device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -187,14 +195,27 @@ __device__ void schedule_items(int n_total, const Workspace& ws) {
 }
 
 // ------------------------------------------------------------------------------------
-// forward kinematics prologue: one wavefront per particle (FP64 inside); the last workgroup
-// to finish builds the work list
+// forward kinematics prologue: one wavefront per particle (FP64 inside)
 
 __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   __shared__ double s_T[kWavesPerBlock][HT_MAX_SEG][12];
   __shared__ double s_h[kWavesPerBlock][HT_MAX_DOF];
   __shared__ double s_sin[kWavesPerBlock][HT_MAX_DOF], s_cos[kWavesPerBlock][HT_MAX_DOF];
-  const DevModel& M = *a.model;
+  // the model tables, staged by one coalesced copy (the tree walk and the primitive set-up
+  // would otherwise wait on long chains of dependent global loads)
+  __shared__ __align__(16) DevModel s_model;
+  {
+    static_assert(sizeof(DevModel) % 4 == 0, "model copy in 4-byte words");
+    const uint4* src4 = reinterpret_cast<const uint4*>(a.model);
+    uint4* dst4 = reinterpret_cast<uint4*>(&s_model);
+    const int n4 = (int)(sizeof(DevModel) / 16);
+    for (int i = threadIdx.x; i < n4; i += kBlock) dst4[i] = src4[i];
+    const uint32_t* src1 = reinterpret_cast<const uint32_t*>(a.model);
+    uint32_t* dst1 = reinterpret_cast<uint32_t*>(&s_model);
+    for (int i = n4 * 4 + threadIdx.x; i < (int)(sizeof(DevModel) / 4); i += kBlock)
+      dst1[i] = src1[i];
+  }
+  const DevModel& M = s_model;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
   const int n_total = a.n_frames * a.n_particles;
   const int p = blockIdx.x * kWavesPerBlock + w;
@@ -299,7 +320,12 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   }
 
   // primitive records and screen boxes
-  int bu0 = INT_MAX, bu1 = INT_MIN, bv0 = INT_MAX, bv1 = INT_MIN;
+  int ru0[kMaxRects], ru1[kMaxRects], rv0[kMaxRects], rv1[kMaxRects];
+#pragma unroll
+  for (int r = 0; r < kMaxRects; ++r) {
+    ru0[r] = rv0[r] = INT_MAX;
+    ru1[r] = rv1[r] = INT_MIN;
+  }
   if (valid) {
     const FrameSlot fs = a.slots[slot];
     for (int k = lane; k < n_prim; k += kWave) {
@@ -415,10 +441,11 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       } else if (fs.bg > 0.0f && lo3[2] >= (double)fs.bg) {
         box = make_int4(1, 0, 1, 0);   // entirely behind the background plane
       } else {
-        const double xmin = fmin(lo3[0] / lo3[2], lo3[0] / hi3[2]);
-        const double xmax = fmax(hi3[0] / lo3[2], hi3[0] / hi3[2]);
-        const double ymin = fmin(lo3[1] / lo3[2], lo3[1] / hi3[2]);
-        const double ymax = fmax(hi3[1] / lo3[2], hi3[1] / hi3[2]);
+        const double izl = 1.0 / lo3[2], izh = 1.0 / hi3[2];
+        const double xmin = fmin(lo3[0] * izl, lo3[0] * izh);
+        const double xmax = fmax(hi3[0] * izl, hi3[0] * izh);
+        const double ymin = fmin(lo3[1] * izl, lo3[1] * izh);
+        const double ymax = fmax(hi3[1] * izl, hi3[1] * izh);
         const double lim = 1.0e6;
         const double u0 = fmin(fmax(floor(fs.cx + fs.fx * xmin), -1.0), lim);
         const double u1 = fmin(fmax(ceil(fs.cx + fs.fx * xmax), -1.0), lim);
@@ -432,39 +459,69 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       }
       ws.boxes[(size_t)p * n_prim + k] = box;
       if (box.x <= box.y) {
-        bu0 = min(bu0, box.x);
-        bu1 = max(bu1, box.y);
-        bv0 = min(bv0, box.z);
-        bv1 = max(bv1, box.w);
+        const int q = M.prim_root[k];
+#pragma unroll
+        for (int r = 0; r < kMaxRects; ++r) {
+          if (r != q) continue;
+          ru0[r] = min(ru0[r], box.x);
+          ru1[r] = max(ru1[r], box.y);
+          rv0[r] = min(rv0[r], box.z);
+          rv1[r] = max(rv1[r], box.w);
+        }
       }
     }
   }
-  bu0 = wave_min(bu0);
-  bv0 = wave_min(bv0);
-  bu1 = wave_max(bu1);
-  bv1 = wave_max(bv1);
+#pragma unroll
+  for (int r = 0; r < kMaxRects; ++r) {
+    ru0[r] = wave_min(ru0[r]);
+    rv0[r] = wave_min(rv0[r]);
+    ru1[r] = wave_max(ru1[r]);
+    rv1[r] = wave_max(rv1[r]);
+  }
   if (active && lane == 0) {
-    PInfo pi;
+    PInfo pi{};
     pi.slot = slot_ok ? slot : -1;
     pi.valid = valid ? 1 : 0;
     double kc = 0.0;
     if (valid)
       for (int i = 0; i < M.n_kc; ++i) kc += fmax(-(s_h[w][M.kc_a[i]] - s_h[w][M.kc_b[i]]), 0.0);
     pi.kc = (float)kc;
-    if (valid && bu0 <= bu1) {
-      pi.tx0 = bu0 / kTile;
-      pi.ty0 = bv0 / kTile;
-      pi.tw = bu1 / kTile - pi.tx0 + 1;
-      pi.n_tiles = pi.tw * (bv1 / kTile - pi.ty0 + 1);
-    } else {
-      pi.tx0 = pi.ty0 = 0;
-      pi.tw = 1;
-      pi.n_tiles = 0;
+    // one tile rectangle per tree, as (x0, y0, x1, y1) inclusive; merge overlapping ones so
+    // that no tile is visited twice
+    int4 R[kMaxRects];
+    int n = 0;
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < kMaxRects; ++r) {
+        if (ru0[r] > ru1[r]) continue;
+        R[n++] = make_int4(ru0[r] / kTile, rv0[r] / kTile, ru1[r] / kTile, rv1[r] / kTile);
+      }
+    }
+    bool merged = true;
+    while (merged) {
+      merged = false;
+      for (int i = 0; i < n && !merged; ++i) {
+        for (int j = i + 1; j < n && !merged; ++j) {
+          if (R[i].x <= R[j].z && R[j].x <= R[i].z && R[i].y <= R[j].w && R[j].y <= R[i].w) {
+            R[i] = make_int4(min(R[i].x, R[j].x), min(R[i].y, R[j].y), max(R[i].z, R[j].z),
+                             max(R[i].w, R[j].w));
+            R[j] = R[n - 1];
+            --n;
+            merged = true;
+          }
+        }
+      }
+    }
+    pi.n_rects = n;
+    pi.n_tiles = 0;
+    for (int i = 0; i < n; ++i) {
+      const int tw = R[i].z - R[i].x + 1, th = R[i].w - R[i].y + 1;
+      pi.rect[i] = make_int4(R[i].x, R[i].y, tw, th);
+      pi.n_tiles += tw * th;
     }
     pi.n_items = (pi.n_tiles + tpi - 1) / tpi;
     ws.pinfo[p] = pi;
   }
-
 }
 
 // The work list is built by its own one-workgroup launch: folding it into the kinematics
@@ -613,13 +670,16 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
 // persistent ray cast + cost terms + reduction
 
 template <bool GRAD, bool DEBUG>
-__global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace ws,
+// at least six wavefronts per SIMD (at most 80 VGPRs) to hide the LDS latency of the
+// per-primitive constants
+__global__ __launch_bounds__(kBlock, 6) void raycast_kernel(EvalArgs a, Workspace ws,
                                                          TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
   __shared__ int4 s_box[HT_MAX_PRIM];
   __shared__ float4 s_cap[2 * HT_MAX_PRIM];
   __shared__ int s_item;
-  __shared__ float s_td[kWavesPerBlock];
+  __shared__ PInfo s_pi;
+  __shared__ double s_td[kWavesPerBlock];
   __shared__ int s_a[kWavesPerBlock], s_o[kWavesPerBlock];
   __shared__ float s_wr[GRAD ? kWavesPerBlock : 1][GRAD ? HT_MAX_SEG : 1][6];
 
@@ -628,8 +688,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
   const int tpi = a.tiles_per_item;
   const int total = ws.counters[1];
   int cur_p = -1;
-  PInfo pi{};
   FrameSlot fs{};
+  const PInfo& pi = s_pi;
 
   for (;;) {
     if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1);
@@ -644,22 +704,38 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       for (int i = tid; i < n_prim; i += kBlock) s_box[i] = ws.boxes[(size_t)p * n_prim + i];
       for (int i = tid; i < 2 * n_prim; i += kBlock)
         s_cap[i] = ws.caps[(size_t)p * n_prim * 2 + i];
+      if (tid == 0) s_pi = ws.pinfo[p];
       cur_p = p;
-      pi = ws.pinfo[p];
-      fs = a.slots[pi.slot];
       __syncthreads();
+      fs = a.slots[s_pi.slot];
     }
     if (GRAD) {
       for (int i = lane; i < n_seg * 6; i += kWave) s_wr[wave][i / 6][i % 6] = 0.0f;
     }
     const int c = item - ws.item_off[p];
     const int t_end = min((c + 1) * tpi, pi.n_tiles);
-    float acc_td = 0.0f;
+    double acc_td = 0.0;   // exact: the FP32 terms are multiples of 2^-15 mm
     int acc_a = 0, acc_o = 0;
     const float* recs = reinterpret_cast<const float*>(s_rec);
 
     for (int t = c * tpi + wave; t < t_end; t += kWavesPerBlock) {
-      const int tx = pi.tx0 + t % pi.tw, ty = pi.ty0 + t / pi.tw;
+      // tile t of the particle: walk its rectangles (uniform branches, LDS reads at constant
+      // offsets)
+      int4 rc = pi.rect[0];
+      int tt = t;
+      if (pi.n_rects > 1 && tt >= rc.z * rc.w) {
+        tt -= rc.z * rc.w;
+        rc = pi.rect[1];
+        if (pi.n_rects > 2 && tt >= rc.z * rc.w) {
+          tt -= rc.z * rc.w;
+          rc = pi.rect[2];
+          if (pi.n_rects > 3 && tt >= rc.z * rc.w) {
+            tt -= rc.z * rc.w;
+            rc = pi.rect[3];
+          }
+        }
+      }
+      const int tx = rc.x + tt % rc.z, ty = rc.y + tt / rc.z;
       const int x0 = tx * kTile, y0 = ty * kTile;
       // culling, one lane per primitive: screen box overlap, then the bounding capsule
       // against the four planes through the camera that bound the tile's pixel rays
@@ -742,12 +818,12 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       const float td = fminf(diff, kDClamp);
       const bool rm = hit && (diff < kDMatch || od == 0.0f);
       if (valid) {
-        acc_td += td;
+        acc_td += (double)td;
         acc_a += (os && rm) ? 1 : 0;
         acc_o += (os || rm) ? 1 : 0;
       }
       if (lane == 0) {
-        acc_td -= fs.tile_td[tile_idx];
+        acc_td -= (double)fs.tile_td[tile_idx];
         acc_o -= fs.tile_skin[tile_idx];
       }
       if (DEBUG && valid) {
@@ -834,7 +910,7 @@ __device__ inline float assemble_cost(const EvalArgs& a, const Workspace& ws, co
   const int b = ws.item_off[p], e = b + pi.n_items;
   for (int i = b; i < e; ++i) {
     const Partial pr = ws.partial[i];
-    S_d += (double)pr.td;
+    S_d += pr.td;
     S_and += pr.a;
     S_or += pr.o;
   }
@@ -865,6 +941,7 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace 
 // with M_s, F_s the moment about the segment origin q_s and the force of segment s.
 __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Workspace ws) {
   __shared__ double s_W[HT_MAX_SEG * 6];
+  __shared__ double s_part[kWavesPerBlock][HT_MAX_SEG * 6];
   __shared__ double s_inv_or;
   const int p = blockIdx.x, t = threadIdx.x;
   const PInfo pi = ws.pinfo[p];
@@ -875,11 +952,21 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
     return;
   }
   const int b = ws.item_off[p], e = b + pi.n_items;
-  if (t < n_seg * 6) {
-    double acc = 0.0;
-    for (int i = b; i < e; ++i) acc += (double)ws.wrench[(size_t)i * n_seg * 6 + t];
-    s_W[t] = acc;
+  // wave q sums items b+q, b+q+4, ...; lane l sums values l, l+64, l+128; then the four
+  // partial sums are added in a fixed order
+  const int nv = n_seg * 6, lane = t & (kWave - 1), q = t >> 6;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int i = b + q; i < e; i += kWavesPerBlock) {
+    const float* src = ws.wrench + (size_t)i * nv;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (lane + k * kWave < nv) acc[k] += (double)src[lane + k * kWave];
   }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (lane + k * kWave < nv) s_part[q][lane + k * kWave] = acc[k];
+  __syncthreads();
+  if (t < nv) s_W[t] = ((s_part[0][t] + s_part[1][t]) + s_part[2][t]) + s_part[3][t];
   if (t == kBlock - 1) {
     long long S_or = 0;
     a.cost[p] = assemble_cost(a, ws, pi, p, &S_or);

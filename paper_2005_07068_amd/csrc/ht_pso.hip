@@ -48,6 +48,43 @@ constexpr int kPsoBlock = 1024;
 
 int threads_for(int n) { return n >= kPsoBlock ? kPsoBlock : ((n + kWave - 1) / kWave) * kWave; }
 
+int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Sort the P costs of a frame ascending by (cost, particle index) with a bitonic network in
+// LDS: key[i], idx[i] for i < n_pad (a power of two); entries past P sort last.  Afterwards
+// position r holds the particle of rank r, so the K best are positions 0..K-1 (ties: lower
+// index first) and the worst are the last positions (ties: the higher index is worse).
+__device__ void sort_costs(const float* __restrict__ cost, int P, int n_pad, float* key,
+                           int* idx) {
+  for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
+    key[i] = i < P ? cost_key(cost[i]) : INFINITY;
+    idx[i] = i;                     // padding indices exceed every particle index
+  }
+  __syncthreads();
+  for (int k = 2; k <= n_pad; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l <= i) continue;
+        const float ki = key[i], kl = key[l];
+        const int ii = idx[i], il = idx[l];
+        const bool i_after_l = ki > kl || (ki == kl && ii > il);
+        if (i_after_l == ((i & k) == 0)) {
+          key[i] = kl;
+          key[l] = ki;
+          idx[i] = il;
+          idx[l] = ii;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------
@@ -92,11 +129,13 @@ hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof,
 // generation update, part 1: one workgroup per frame
 
 __global__ __launch_bounds__(kPsoBlock) void pso_best_kernel(ht_swarm sw, ht_pso_params prm,
-                                                             int n_dof, int* __restrict__ flags) {
+                                                             int n_dof, int n_pad,
+                                                             int* __restrict__ flags) {
   extern __shared__ float s_mem[];
   const int P = sw.n_particles;
-  float* s_cost = s_mem;          // [P] current costs (NaN -> +inf)
-  float* s_pb = s_mem + P;        // [P] personal best costs after this generation
+  float* s_pb = s_mem;                                  // [P] personal bests after this step
+  float* s_key = s_mem + P;                             // [n_pad] sort keys
+  int* s_idx = reinterpret_cast<int*>(s_key + n_pad);   // [n_pad] sort payload
   __shared__ float s_rv[kPsoBlock / kWave];
   __shared__ int s_ri[kPsoBlock / kWave];
   __shared__ int s_g;
@@ -107,7 +146,6 @@ __global__ __launch_bounds__(kPsoBlock) void pso_best_kernel(ht_swarm sw, ht_pso
 
   for (int i = tid; i < P; i += blockDim.x) {
     const float c = cost_key(sw.cost[base + i]);
-    s_cost[i] = c;
     float pb = sw.pbest_cost[base + i];
     int fl = 0;
     if (c < pb) {
@@ -169,16 +207,9 @@ __global__ __launch_bounds__(kPsoBlock) void pso_best_kernel(ht_swarm sw, ht_pso
   const bool mutate_gen = prm.mutate_every > 0 && (gen + 1) % prm.mutate_every == 0;
   const int n_mut = (int)floorf((float)P * prm.mutate_frac);
   if (mutate_gen && n_mut > 0) {
-    for (int i = tid; i < P; i += blockDim.x) {
-      // rank 0 is the worst: higher cost, ties to the higher index
-      const float ci = s_cost[i];
-      int rank = 0;
-      for (int j = 0; j < P; ++j) {
-        const float cj = s_cost[j];
-        rank += (cj > ci || (cj == ci && j > i)) ? 1 : 0;
-      }
-      if (rank < n_mut) flags[base + i] |= kFlagMutated;
-    }
+    // the worst n_mut by current cost are the last positions of the ascending sort
+    sort_costs(sw.cost + base, P, n_pad, s_key, s_idx);
+    for (int r = P - n_mut + tid; r < P; r += blockDim.x) flags[base + s_idx[r]] |= kFlagMutated;
   }
   __syncthreads();
   if (tid == 0) sw.gen[f] = gen + 1;
@@ -232,9 +263,10 @@ __global__ __launch_bounds__(kBlock) void pso_move_kernel(const DevModel* __rest
 hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht_pso_params& p,
                              int n_dof, int* flags, hipStream_t s) {
   if (sw.n_frames == 0 || sw.n_particles == 0) return hipSuccess;
-  const size_t shm = 2 * (size_t)sw.n_particles * sizeof(float);
+  const int n_pad = pow2_at_least(sw.n_particles);
+  const size_t shm = (size_t)sw.n_particles * sizeof(float) + (size_t)n_pad * 8;
   hipLaunchKernelGGL(pso_best_kernel, dim3(sw.n_frames), dim3(threads_for(sw.n_particles)), shm,
-                     s, sw, p, n_dof, flags);
+                     s, sw, p, n_dof, n_pad, flags);
   const size_t n = (size_t)sw.n_frames * sw.n_particles * n_dof;
   hipLaunchKernelGGL(pso_move_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, s, model, sw, p, n_dof, flags);
@@ -250,35 +282,25 @@ hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht
 // than the current one, else the particle stops refining; gather: back into the swarm.
 
 __global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, int K, int n_dof,
+                                                                  int n_pad,
                                                                   int* __restrict__ sel,
                                                                   float* __restrict__ rx,
                                                                   float* __restrict__ rcost,
                                                                   int* __restrict__ active) {
-  extern __shared__ float s_cost[];
-  int* s_sel = reinterpret_cast<int*>(s_cost + sw.n_particles);
+  extern __shared__ float s_key[];
+  int* s_idx = reinterpret_cast<int*>(s_key + n_pad);
   const int P = sw.n_particles, f = blockIdx.x;
   const size_t base = (size_t)f * P;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) s_cost[i] = cost_key(sw.cost[base + i]);
-  __syncthreads();
-  for (int i = threadIdx.x; i < P; i += blockDim.x) {
-    const float ci = s_cost[i];
-    int rank = 0;
-    for (int j = 0; j < P; ++j) {
-      const float cj = s_cost[j];
-      rank += (cj < ci || (cj == ci && j < i)) ? 1 : 0;
-    }
-    if (rank < K) {
-      const size_t r = (size_t)f * K + rank;
-      s_sel[rank] = i;
-      sel[r] = i;
-      rcost[r] = ci;
-      active[r] = 1;
-    }
+  sort_costs(sw.cost + base, P, n_pad, s_key, s_idx);
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    const size_t q = (size_t)f * K + r;
+    sel[q] = s_idx[r];
+    rcost[q] = s_key[r];
+    active[q] = 1;
   }
-  __syncthreads();
   for (int e = threadIdx.x; e < K * n_dof; e += blockDim.x) {
     const int r = e / n_dof, d = e % n_dof;
-    rx[((size_t)f * K + r) * n_dof + d] = sw.x[(base + s_sel[r]) * n_dof + d];
+    rx[((size_t)f * K + r) * n_dof + d] = sw.x[(base + s_idx[r]) * n_dof + d];
   }
 }
 
@@ -351,9 +373,9 @@ __global__ __launch_bounds__(kBlock) void refine_gather_kernel(ht_swarm sw, int 
 
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
                                 float* rcost, int* active, hipStream_t s) {
+  const int n_pad = pow2_at_least(sw.n_particles);
   hipLaunchKernelGGL(refine_select_kernel, dim3(sw.n_frames), dim3(threads_for(sw.n_particles)),
-                     (size_t)sw.n_particles * sizeof(float) + (size_t)K * sizeof(int), s, sw, K,
-                     n_dof, sel, rx, rcost, active);
+                     (size_t)n_pad * 8, s, sw, K, n_dof, n_pad, sel, rx, rcost, active);
   return hipGetLastError();
 }
 
