@@ -110,6 +110,40 @@ def plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=8)
     return summary
 
 
+def pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16, P=64, G=30):
+    """Plain swarms of the paper's budget (64 particles x 30 generations) on the same frame(s):
+    the paper's constants (c1 = 2.8, c2 = 1.3, w from the constriction formula of Eq. 7)
+    against the workload's (w = 0.72, c1 = c2 = 2.05), each with and without the mutation
+    step; final joint error and gbest cost over seeds."""
+    phi = 2.8 + 1.3
+    w_paper = 2.0 / abs(2.0 - phi - np.sqrt(phi * phi - 4.0 * phi))   # constriction factor
+    variants = {
+        "workload_constants": dict(w=cfg.w, c1=cfg.c1, c2=cfg.c2, mutate_every=3),
+        "workload_constants_no_mutation": dict(w=cfg.w, c1=cfg.c1, c2=cfg.c2, mutate_every=0),
+        "paper_constants": dict(w=w_paper, c1=2.8, c2=1.3, mutate_every=3),
+        "paper_constants_no_mutation": dict(w=w_paper, c1=2.8, c2=1.3, mutate_every=0),
+    }
+    out = {}
+    for name, kw in variants.items():
+        errs, costs = [], []
+        params = ht.pso_params(**kw)
+        for s in range(seeds):
+            sw = ctx.swarm(slots, P, lo, hi, seed=5000 + s)
+            ctx.pso_init(sw)
+            for _ in range(G):
+                ctx.pso_step(sw, params)
+            errs.append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
+                                        cfg.n_hands))
+            costs.append(float(sw["gbest_cost"].cpu().numpy().mean()))
+        out[name] = {"w": float(kw["w"]), "c1": kw["c1"], "c2": kw["c2"],
+                     "mutation": kw["mutate_every"] > 0,
+                     "mean_joint_error_deg": float(np.mean(errs)),
+                     "median_joint_error_deg": float(np.median(errs)),
+                     "mean_final_cost": float(np.mean(costs))}
+    out["seeds"] = seeds
+    return out
+
+
 def _oracle_eval(args):
     model, frame, pose = args
     from threadpoolctl import threadpool_limits
@@ -157,6 +191,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-study", action="store_true",
                     help="skip the plain-versus-refined swarm comparison")
+    ap.add_argument("--ablation", action="store_true",
+                    help="add the swarm-constants / mutation ablation (plain swarm)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--launch-config", default=None,
                     help="tiles_per_item,groups_per_cu,cull; skips the autotuner")
@@ -280,6 +316,9 @@ def main():
         log("plain versus gradient-refined swarm over seeds")
         line["plain_vs_refined"] = plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi,
                                                     h_true)
+    if args.ablation:
+        log("swarm constants and mutation ablation over seeds")
+        line["pso_ablation"] = pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true)
     if baseline is not None:
         line["cpu_baseline"] = baseline
     print(json.dumps(line), flush=True)

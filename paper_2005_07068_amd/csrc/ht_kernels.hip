@@ -670,10 +670,10 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
 // persistent ray cast + cost terms + reduction
 
 template <bool GRAD, bool DEBUG>
-// at least six wavefronts per SIMD (at most 80 VGPRs) to hide the LDS latency of the
-// per-primitive constants
-__global__ __launch_bounds__(kBlock, 6) void raycast_kernel(EvalArgs a, Workspace ws,
-                                                         TypeMasks tm) {
+// (forcing six wavefronts per SIMD spills registers and measured slower than the five the
+// natural register count allows)
+__global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace ws,
+                                                      TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
   __shared__ int4 s_box[HT_MAX_PRIM];
   __shared__ float4 s_cap[2 * HT_MAX_PRIM];
