@@ -144,6 +144,88 @@ def pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16, P=
     return out
 
 
+def roofline_sweep(ht, torch, totals=(256, 4096, 65536), min_ms=10.0):
+    """Forward evaluation alone at growing particle counts: the 320x240 one-hand workload
+    (one frame) and the 64-frame uneven-ROI workload, particles drawn like an initial swarm
+    around the true poses, each size looped inside one captured graph for at least
+    ``min_ms``.  Reports evaluations/s and the ray-cast kernel's algorithmic FLOP rate."""
+    from workload.handmodel import init_halfwidth
+    out = []
+    for idx in (2, 3):
+        cfg, model, frames, flops_per_eval, _ = load_workload(idx)
+        ctx = ht.Context(0)
+        ctx.set_model(model)
+        for f, fr in enumerate(frames):
+            ctx.set_observation(f, fr["depth"], fr["skin"], fr["cam"], fr["bg"])
+        F = cfg.n_frames
+        max_px = max(fr["depth"].size for fr in frames)
+        dev = torch.device("cuda:0")
+        slots = torch.arange(F, dtype=torch.int32, device=dev)
+        delta = init_halfwidth(model["n_dof"], cfg.init_angle_deg, cfg.init_trans_mm)
+        h_true = np.stack([fr["h_true"] for fr in frames])
+        lo = torch.tensor(h_true - delta, dtype=torch.float32)
+        hi = torch.tensor(h_true + delta, dtype=torch.float32)
+        for total in totals:
+            P = max(total // F, 1)
+            log(f"sweep: workload {idx}, {F} x {P} particles")
+            ctx.reserve(F * P, max_px)
+            sw = ctx.swarm(slots, P, lo, hi, seed=77 + total)
+            ctx.pso_init(sw)
+            x = sw["x"].clone()
+            del sw
+            tpi, gpc, cull = ctx.autotune(x, slots, repeats=2)
+            cost = torch.empty((F, P), device=dev, dtype=torch.float32)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ctx.eval(x, slots, cost)
+            torch.cuda.synchronize()
+            e0.record()
+            ctx.eval(x, slots, cost)
+            e1.record()
+            torch.cuda.synchronize()
+            reps = max(1, int(np.ceil(min_ms / max(e0.elapsed_time(e1), 1e-3))))
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(reps):
+                    ctx.eval(x, slots, cost)
+            g.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(3):
+                g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms_eval = e0.elapsed_time(e1) / (3 * reps)
+            ctx.profile_begin()
+            ctx.eval(x, slots, cost)
+            st = ctx.profile_end()
+            rc_ms = st["raycast"]["ms"]
+            out.append({"workload": cfg.name, "frames": F, "particles_per_frame": P,
+                        "evals_per_launch": F * P, "launch": [tpi, gpc, cull],
+                        "graph_reps": reps, "ms_per_eval_call": ms_eval,
+                        "evals_per_s": F * P / (ms_eval / 1e3),
+                        "raycast_ms": rc_ms,
+                        "other_kernels_ms": {k: v["ms"] for k, v in st.items()
+                                             if k != "raycast" and v["launches"]},
+                        "raycast_tflops": flops_per_eval * F * P / (rc_ms / 1e3) / 1e12,
+                        "raycast_frac": flops_per_eval * F * P / (rc_ms / 1e3)
+                        / PEAK_FP32_VALU,
+                        "algorithmic_flops_per_eval": flops_per_eval})
+            del g, x, cost
+        ctx.close()
+    return out
+
+
+def copy_calibration(torch, mib: int):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda:0", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 4}
+
+
 def _oracle_eval(args):
     model, frame, pose = args
     from threadpoolctl import threadpool_limits
@@ -193,6 +275,10 @@ def main():
                     help="skip the plain-versus-refined swarm comparison")
     ap.add_argument("--ablation", action="store_true",
                     help="add the swarm-constants / mutation ablation (plain swarm)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="forward-only roofline sweep over particle counts (own JSON line)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--launch-config", default=None,
                     help="tiles_per_item,groups_per_cu,cull; skips the autotuner")
@@ -202,6 +288,16 @@ def main():
               "(frames, or the particles of one frame, would shard across GPUs)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration or args.sweep:
+        import torch
+
+        import paper_2005_07068_amd as ht
+        if args.copy_calibration:
+            print(json.dumps(copy_calibration(torch, args.copy_calibration)), flush=True)
+        else:
+            print(json.dumps({"roofline_sweep": roofline_sweep(ht, torch)}), flush=True)
+        return
 
     from workload.handmodel import init_halfwidth
 

@@ -212,8 +212,8 @@ ht_status ht_pso_run_graph(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_para
 typedef struct {
   int32_t tiles_per_item;   /* 8x8-pixel tiles per work item (one work item per workgroup) */
   int32_t groups_per_cu;    /* persistent workgroups per compute unit                       */
-  int32_t cull;             /* 0: primitive screen boxes only; 1: also each primitive's
-                               bounding capsule against the tile's four frustum planes     */
+  int32_t cull;             /* 0: primitive screen boxes from their 3D bounding boxes;
+                               1: clipped to the image extent of a bounding capsule        */
 } ht_launch_config;
 
 ht_status ht_get_launch_config(ht_ctx* ctx, ht_launch_config* out);

@@ -92,7 +92,6 @@ struct Partial {
 struct Workspace {
   float* recs;           // [n_total][n_prim][kRec]
   int4* boxes;           // [n_total][n_prim] pixel box (u0, u1, v0, v1), empty = (1, 0, 1, 0)
-  float4* caps;          // [n_total][n_prim][2] bounding capsule: (p0, r), (p1, 0)
   PInfo* pinfo;          // [n_total]
   float* dof_frame;      // [n_total][n_dof][8]: kind, axis xyz, point xyz (camera frame)
   float* seg_org;        // [n_total][n_seg][4]
@@ -118,7 +117,7 @@ struct EvalArgs {
   float dbg_bg;
   TypeMasks type_masks;
   int tiles_per_item;
-  int cull;                    // 1: capsule-vs-tile-frustum test after the screen box test
+  int cull;                    // 1: screen boxes clipped to the bounding capsule's image extent
   int grid;                    // persistent workgroups
   int n_prim, n_seg, n_dof;
 };

@@ -194,6 +194,36 @@ __device__ void schedule_items(int n_total, const Workspace& ws) {
   }
 }
 
+// Image extent of a capsule (segment q0-q1, radius r) as the hull of its two end spheres'
+// extents: the planes x = a z through the camera that touch a sphere with centre (X, Y, Z),
+// Z > r, have a = (X Z -/+ r sqrt(X^2 + Z^2 - r^2)) / (Z^2 - r^2), and likewise in y.  The
+// capsule's support along a plane normal is the larger of its end spheres', so no interior
+// point lies outside.  Writes pixel coordinates (u0, u1, v0, v1), padded by a quarter pixel
+// for the FP32 rounding; returns false when a sphere reaches the camera plane.
+__device__ bool capsule_extent(const double* q0, const double* q1, double r,
+                               const FrameSlot& fs, float* e) {
+  float amin = INFINITY, amax = -INFINITY, bmin = INFINITY, bmax = -INFINITY;
+  const float rr = (float)r;
+  for (int j = 0; j < 2; ++j) {
+    const double* q = j ? q1 : q0;
+    const float X = (float)q[0], Y = (float)q[1], Z = (float)q[2];
+    if (!(Z > 1.001f * rr + 1.0f)) return false;
+    const float den = (Z - rr) * (Z + rr);
+    const float inv = 1.0f / den;
+    const float hx = rr * sqrtf(fmaf(X, X, den)), hy = rr * sqrtf(fmaf(Y, Y, den));
+    const float xz = X * Z, yz = Y * Z;
+    amin = fminf(amin, (xz - hx) * inv);
+    amax = fmaxf(amax, (xz + hx) * inv);
+    bmin = fminf(bmin, (yz - hy) * inv);
+    bmax = fmaxf(bmax, (yz + hy) * inv);
+  }
+  e[0] = fmaf(fs.fx, amin, fs.cx) - 0.25f;
+  e[1] = fmaf(fs.fx, amax, fs.cx) + 0.25f;
+  e[2] = fmaf(fs.fy, bmin, fs.cy) - 0.25f;
+  e[3] = fmaf(fs.fy, bmax, fs.cy) + 0.25f;
+  return true;
+}
+
 // ------------------------------------------------------------------------------------
 // forward kinematics prologue: one wavefront per particle (FP64 inside)
 
@@ -401,39 +431,6 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       for (int i = 0; i < 4; ++i)
         dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
 
-      // bounding capsule (segment p0-p1, radius r) for per-tile frustum culling.  An
-      // ellipsoid with semi-axes a >= b >= c lies in the capsule along its a-axis from
-      // -(a - b) to (a - b) with radius b.
-      double q0[3], q1[3], cr;
-      if (typ == HT_SPHERE) {
-        for (int i = 0; i < 3; ++i) q0[i] = q1[i] = c[i];
-        cr = sz[0];
-      } else if (typ == HT_CYLINDER) {
-        for (int i = 0; i < 3; ++i) {
-          q0[i] = c[i];
-          q1[i] = c[i] + sz[1] * (double)rec[8 + i];
-        }
-        cr = sz[0];
-      } else {
-        int ia = 0;
-        for (int i = 1; i < 3; ++i)
-          if (sz[i] > sz[ia]) ia = i;
-        double b2 = 0.0;
-        for (int i = 0; i < 3; ++i)
-          if (i != ia) b2 = fmax(b2, sz[i]);
-        const double hl = sz[ia] - b2;
-        for (int i = 0; i < 3; ++i) {
-          q0[i] = c[i] - hl * F[i * 4 + ia];
-          q1[i] = c[i] + hl * F[i * 4 + ia];
-        }
-        cr = b2;
-      }
-      // margin for the FP32 rounding of the capsule and of the culling test
-      cr += 0.01 + 1e-6 * (fabs(c[0]) + fabs(c[1]) + fabs(c[2]));
-      float4* cap = ws.caps + ((size_t)p * n_prim + k) * 2;
-      cap[0] = make_float4((float)q0[0], (float)q0[1], (float)q0[2], (float)cr);
-      cap[1] = make_float4((float)q1[0], (float)q1[1], (float)q1[2], 0.0f);
-
       // conservative pixel box of the axis-aligned 3D box
       int4 box;
       if (!(lo3[2] > 1.0)) {
@@ -455,8 +452,50 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
         box.y = min((int)u1, fs.W - 1);
         box.z = max((int)v0, 0);
         box.w = min((int)v1, fs.H - 1);
-        if (box.x > box.y || box.z > box.w) box = make_int4(1, 0, 1, 0);
       }
+      if (a.cull && box.x <= box.y && box.z <= box.w) {
+        // tighter: the exact image extent of a bounding capsule (segment q0-q1, radius cr).
+        // An ellipsoid with semi-axes a >= b >= c lies in the capsule along its a-axis from
+        // -(a - b) to (a - b) with radius b.
+        double q0[3], q1[3], cr;
+        if (typ == HT_SPHERE) {
+          for (int i = 0; i < 3; ++i) q0[i] = q1[i] = c[i];
+          cr = sz[0];
+        } else if (typ == HT_CYLINDER) {
+          for (int i = 0; i < 3; ++i) {
+            q0[i] = c[i];
+            q1[i] = c[i] + sz[1] * (double)rec[8 + i];
+          }
+          cr = sz[0];
+        } else {
+          int ia = 0;
+          for (int i = 1; i < 3; ++i)
+            if (sz[i] > sz[ia]) ia = i;
+          double b2 = 0.0;
+          for (int i = 0; i < 3; ++i)
+            if (i != ia) b2 = fmax(b2, sz[i]);
+          const double hl = sz[ia] - b2;
+          for (int i = 0; i < 3; ++i) {
+            q0[i] = c[i] - hl * F[i * 4 + ia];
+            q1[i] = c[i] + hl * F[i * 4 + ia];
+          }
+          cr = b2;
+        }
+        cr += 0.01 + 1e-6 * (fabs(c[0]) + fabs(c[1]) + fabs(c[2]));
+        float e[4];
+        if (capsule_extent(q0, q1, cr, fs, e)) {
+          const float lim = 1.0e6f;
+          const int u0 = (int)fminf(fmaxf(floorf(e[0]), -1.0f), lim);
+          const int u1 = (int)fminf(fmaxf(ceilf(e[1]), -1.0f), lim);
+          const int v0 = (int)fminf(fmaxf(floorf(e[2]), -1.0f), lim);
+          const int v1 = (int)fminf(fmaxf(ceilf(e[3]), -1.0f), lim);
+          box.x = max(box.x, u0);
+          box.y = min(box.y, u1);
+          box.z = max(box.z, v0);
+          box.w = min(box.w, v1);
+        }
+      }
+      if (box.x > box.y || box.z > box.w) box = make_int4(1, 0, 1, 0);
       ws.boxes[(size_t)p * n_prim + k] = box;
       if (box.x <= box.y) {
         const int q = M.prim_root[k];
@@ -667,6 +706,89 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
 }
 
 // ------------------------------------------------------------------------------------
+// wave-uniform values: read once from lane 0 into scalar registers, so that the per-tile
+// bookkeeping runs on the scalar unit and holds no vector registers
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+template <class T>
+__device__ __forceinline__ T* uni(T* x) {
+  const uint64_t v = reinterpret_cast<uint64_t>(x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ FrameSlot uni(const FrameSlot& f) {
+  FrameSlot u;
+  u.W = uni(f.W);
+  u.H = uni(f.H);
+  u.TW = uni(f.TW);
+  u.TH = uni(f.TH);
+  u.sx = uni(f.sx);
+  u.sy = uni(f.sy);
+  u.sz = uni(f.sz);
+  u.cx = uni(f.cx);
+  u.cy = uni(f.cy);
+  u.fx = uni(f.fx);
+  u.fy = uni(f.fy);
+  u.bg = uni(f.bg);
+  u.set = uni(f.set);
+  u.words = uni(f.words);
+  u.tile_td = uni(f.tile_td);
+  u.tile_skin = uni(f.tile_skin);
+  u.totals = uni(f.totals);
+  return u;
+}
+
+// Walks a particle's tiles (the union of its rectangles, each row-major) in steps of the
+// number of wavefronts per workgroup, without a division per tile.
+struct TileWalk {
+  const PInfo* pi;
+  int n, ri, rx, ry, rw, rh, ox, oy;
+
+  __device__ void load(int r) {
+    const int4 rc = pi->rect[r];
+    rx = uni(rc.x);
+    ry = uni(rc.y);
+    rw = uni(rc.z);
+    rh = uni(rc.w);
+  }
+  // position at tile t of the union
+  __device__ void seek(int t) {
+    while (t >= rw * rh && ri + 1 < n) {
+      t -= rw * rh;
+      load(++ri);
+    }
+    oy = t / rw;
+    ox = t - oy * rw;
+  }
+  __device__ void start(const PInfo* p, int t) {
+    pi = p;
+    n = uni(p->n_rects);
+    ri = 0;
+    load(0);
+    seek(t);
+  }
+  __device__ void step(int s) {
+    ox += s;
+    while (ox >= rw) {
+      ox -= rw;
+      ++oy;
+    }
+    if (oy >= rh && ri + 1 < n) {
+      const int t = (oy - rh) * rw + ox;
+      load(++ri);
+      seek(t);
+    }
+  }
+  __device__ int tx() const { return rx + ox; }
+  __device__ int ty() const { return ry + oy; }
+};
+
+// ------------------------------------------------------------------------------------
 // persistent ray cast + cost terms + reduction
 
 template <bool GRAD, bool DEBUG>
@@ -676,7 +798,6 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
                                                       TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
   __shared__ int4 s_box[HT_MAX_PRIM];
-  __shared__ float4 s_cap[2 * HT_MAX_PRIM];
   __shared__ int s_item;
   __shared__ PInfo s_pi;
   __shared__ double s_td[kWavesPerBlock];
@@ -694,59 +815,34 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
   for (;;) {
     if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = uni(s_item);
     __syncthreads();
     if (item >= total) break;
-    const int p = ws.item_map[item];
+    const int p = uni(ws.item_map[item]);
     if (p != cur_p) {
       const float4* src = reinterpret_cast<const float4*>(ws.recs + (size_t)p * n_prim * kRec);
       for (int i = tid; i < n_prim * (kRec / 4); i += kBlock) s_rec[i] = src[i];
       for (int i = tid; i < n_prim; i += kBlock) s_box[i] = ws.boxes[(size_t)p * n_prim + i];
-      for (int i = tid; i < 2 * n_prim; i += kBlock)
-        s_cap[i] = ws.caps[(size_t)p * n_prim * 2 + i];
       if (tid == 0) s_pi = ws.pinfo[p];
       cur_p = p;
       __syncthreads();
-      fs = a.slots[s_pi.slot];
+      fs = uni(a.slots[uni(s_pi.slot)]);
     }
     if (GRAD) {
       for (int i = lane; i < n_seg * 6; i += kWave) s_wr[wave][i / 6][i % 6] = 0.0f;
     }
-    const int c = item - ws.item_off[p];
-    const int t_end = min((c + 1) * tpi, pi.n_tiles);
+    const int c = item - uni(ws.item_off[p]);
+    const int t_end = min((c + 1) * tpi, uni(pi.n_tiles));
     double acc_td = 0.0;   // exact: the FP32 terms are multiples of 2^-15 mm
     int acc_a = 0, acc_o = 0;
     const float* recs = reinterpret_cast<const float*>(s_rec);
 
-    for (int t = c * tpi + wave; t < t_end; t += kWavesPerBlock) {
-      // tile t of the particle: walk its rectangles (uniform branches, LDS reads at constant
-      // offsets)
-      int4 rc = pi.rect[0];
-      int tt = t;
-      if (pi.n_rects > 1 && tt >= rc.z * rc.w) {
-        tt -= rc.z * rc.w;
-        rc = pi.rect[1];
-        if (pi.n_rects > 2 && tt >= rc.z * rc.w) {
-          tt -= rc.z * rc.w;
-          rc = pi.rect[2];
-          if (pi.n_rects > 3 && tt >= rc.z * rc.w) {
-            tt -= rc.z * rc.w;
-            rc = pi.rect[3];
-          }
-        }
-      }
-      const int tx = rc.x + tt % rc.z, ty = rc.y + tt / rc.z;
+    TileWalk walk;
+    walk.start(&pi, c * tpi + wave);
+    for (int t = c * tpi + wave; t < t_end; t += kWavesPerBlock, walk.step(kWavesPerBlock)) {
+      const int tx = walk.tx(), ty = walk.ty();
       const int x0 = tx * kTile, y0 = ty * kTile;
-      // culling, one lane per primitive: screen box overlap, then the bounding capsule
-      // against the four planes through the camera that bound the tile's pixel rays
-      // (x/z in [ax0, ax1], y/z in [ay0, ay1])
-      const float inv_sz = 1.0f / fs.sz;
-      const float ax0 = ((float)x0 - fs.cx) * fs.sx * inv_sz;
-      const float ax1 = ((float)(x0 + kTile - 1) - fs.cx) * fs.sx * inv_sz;
-      const float ay0 = ((float)y0 - fs.cy) * fs.sy * inv_sz;
-      const float ay1 = ((float)(y0 + kTile - 1) - fs.cy) * fs.sy * inv_sz;
-      const float nx0 = sqrtf(fmaf(ax0, ax0, 1.0f)), nx1 = sqrtf(fmaf(ax1, ax1, 1.0f));
-      const float ny0 = sqrtf(fmaf(ay0, ay0, 1.0f)), ny1 = sqrtf(fmaf(ay1, ay1, 1.0f));
+      // culling, one lane per primitive: screen box overlap
       uint64_t mk[2];
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
@@ -755,14 +851,6 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
         if (k < n_prim) {
           const int4 b = s_box[k];
           ov = b.x <= x0 + kTile - 1 && b.y >= x0 && b.z <= y0 + kTile - 1 && b.w >= y0;
-          if (ov && a.cull) {
-            const float4 c0 = s_cap[2 * k], c1 = s_cap[2 * k + 1];
-            const float r = c0.w;
-            ov = fmaxf(fmaf(-ax0, c0.z, c0.x), fmaf(-ax0, c1.z, c1.x)) >= -r * nx0 &&
-                 fmaxf(fmaf(ax1, c0.z, -c0.x), fmaf(ax1, c1.z, -c1.x)) >= -r * nx1 &&
-                 fmaxf(fmaf(-ay0, c0.z, c0.y), fmaf(-ay0, c1.z, c1.y)) >= -r * ny0 &&
-                 fmaxf(fmaf(ay1, c0.z, -c0.y), fmaf(ay1, c1.z, -c1.y)) >= -r * ny1;
-          }
         }
         mk[half] = __ballot(ov);
       }
@@ -779,7 +867,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       const float dz = fs.sz;
       const float dd = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
       const float inv_dd = fast_rcp(dd);
-      float zmin = fs.bg > 0.0f ? fs.bg : INFINITY;
+      float tmin = INFINITY;
       int win = -1;
       float wnx = 0, wny = 0, wnz = 0, wrx = 0, wry = 0, wrz = 0;
 
@@ -796,10 +884,11 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
             if (typ == HT_SPHERE) sphere_test<GRAD>(r, dx, dy, dz, inv_dd, h);
             else if (typ == HT_CYLINDER) cylinder_test<GRAD>(r, dx, dy, dz, dd, h);
             else ellipsoid_test<GRAD>(r, dx, dy, dz, h);
-            const float z = h.t * dz;
-            // nearest entry; ties keep the lower primitive index (branch-free selects)
-            const bool take = h.ok & ((z < zmin) | ((z == zmin) & (k < win)));
-            zmin = take ? z : zmin;
+            // nearest entry in front of the camera: as unsigned integers the bit patterns of
+            // non-negative floats keep their order and negative ones (entries behind the
+            // camera) exceed +inf; exact ties keep the first tested (branch-free selects)
+            const bool take = h.ok & (__float_as_uint(h.t) < __float_as_uint(tmin));
+            tmin = take ? h.t : tmin;
             win = take ? k : win;
             if (GRAD) {
               wnx = take ? h.nx : wnx;
@@ -812,7 +901,10 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
           }
         }
       }
-      const bool hit = win >= 0;
+      // depth of the nearest entry; behind the background plane it is hidden
+      const float zmin = tmin * dz;
+      const bool hit = (win >= 0) & !(fs.bg > 0.0f && zmin >= fs.bg);
+      win = hit ? win : -1;
       const float rd = hit ? zmin : (fs.bg > 0.0f ? fs.bg : 0.0f);
       const float diff = fabsf(od - rd);
       const float td = fminf(diff, kDClamp);
