@@ -169,10 +169,9 @@ def roofline_sweep(ht, torch, totals=(256, 4096, 65536), min_ms=10.0):
             P = max(total // F, 1)
             log(f"sweep: workload {idx}, {F} x {P} particles")
             ctx.reserve(F * P, max_px)
-            sw = ctx.swarm(slots, P, lo, hi, seed=77 + total)
-            ctx.pso_init(sw)
-            x = sw["x"].clone()
-            del sw
+            rng = np.random.default_rng(77 + total)
+            u = rng.random((F, P, model["n_dof"]), dtype=np.float32)
+            x = (lo[:, None, :] + torch.from_numpy(u) * (hi - lo)[:, None, :]).to(dev)
             tpi, gpc, cull = ctx.autotune(x, slots, repeats=2)
             cost = torch.empty((F, P), device=dev, dtype=torch.float32)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -127,7 +127,7 @@ struct ht_ctx {
 
 namespace {
 
-constexpr int kMinTilesPerItem = 4;
+using ht::kMinTilesPerItem;
 
 void invalidate_graphs(ht_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -251,16 +251,12 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
     a.dbg_bg = sh.entry.bg;
   }
   a.type_masks = c->tmask;
-  // small launches (a few particles) take shorter work items so that there are about as many
-  // items as persistent workgroups; about a quarter of an ROI's tiles are touched
-  int tpi = c->lc.tiles_per_item;
-  const long long est_tiles = (long long)n_total * c->max_tiles() / 4;
-  const long long groups = (long long)c->n_cu * c->lc.groups_per_cu;
-  while (tpi > 8 && est_tiles / tpi < groups) tpi /= 2;
-  a.tiles_per_item = std::max(std::min(tpi, c->lc.tiles_per_item), kMinTilesPerItem);
+  // the work-list kernel shortens work items for launches with few tiles (tiles_per_item is
+  // their maximum); never more persistent workgroups than there can be items
+  a.tiles_per_item = c->lc.tiles_per_item;
   a.cull = c->lc.cull;
   const long long bound = (long long)n_total *
-                          ((c->max_tiles() + a.tiles_per_item - 1) / a.tiles_per_item);
+                          ((c->max_tiles() + kMinTilesPerItem - 1) / kMinTilesPerItem);
   a.grid = (int)std::max<long long>(1, std::min<long long>((long long)c->n_cu * c->lc.groups_per_cu,
                                                            bound));
   a.n_prim = c->n_prim;
@@ -412,6 +408,10 @@ ht_status build_model(const ht_model* m, ht::DevModel& d, ht::TypeMasks& tm) {
     d.prim_type[k] = t;
     d.prim_seg[k] = s;
     d.prim_root[k] = tree[s];
+    for (int i = 0; i < 3; ++i) {
+      const double z = m->prim_size[k * 3 + i];
+      d.prim_inv2[k][i] = z > 0.0 ? 1.0 / (z * z) : 0.0;
+    }
     for (int i = 0; i < 12; ++i) d.prim_frame[k][i] = m->prim_frame[k * 12 + i];
     const int need = t == HT_SPHERE ? 1 : (t == HT_CYLINDER ? 2 : 3);
     for (int i = 0; i < 3; ++i) {
@@ -419,6 +419,12 @@ ht_status build_model(const ht_model* m, ht::DevModel& d, ht::TypeMasks& tm) {
       if (i < need && !(d.prim_size[k][i] > 0.0)) return fail(HT_ERR_ARG, "primitive %d: size %d must be > 0", k, i);
     }
     tm.m[t][k / 64] |= 1ull << (k % 64);
+  }
+  {
+    int n = 0;
+    for (int t = HT_SPHERE; t <= HT_ELLIPSOID; ++t)
+      for (int k = 0; k < m->n_prim; ++k)
+        if (m->prim_type[k] == t) d.prim_order[n++] = k;
   }
   for (int j = 0; j < m->n_dof; ++j) {
     if (!(m->bounds_lo[j] <= m->bounds_hi[j])) return fail(HT_ERR_ARG, "bounds of dof %d: lo > hi", j);

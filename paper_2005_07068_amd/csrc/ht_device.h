@@ -14,6 +14,12 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;         // 4 wavefronts per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kRec = 16;            // floats per primitive record
+// Work items of the ray-cast kernel (tiles): never shorter than kMinTilesPerItem (the lower
+// bound of the configured tiles_per_item, which sizes the workspace); the work-list kernel
+// aims at kFloorTilesFwd / kFloorTilesGrad at least, capped by the configured value.
+constexpr int kMinTilesPerItem = 4;
+constexpr int kFloorTilesFwd = 8;
+constexpr int kFloorTilesGrad = 16;
 constexpr float kDMatch = 10.0f;    // d_m, mm
 constexpr float kDClamp = 40.0f;    // d_M, mm
 constexpr double kLambda = 20.0;
@@ -45,6 +51,8 @@ struct DevModel {
   int dof_trans[HT_MAX_DOF];             // 1 for the wrist translations (mm), else angle
   int n_roots;                           // independent kinematic trees (hands)
   int prim_root[HT_MAX_PRIM];            // tree of each primitive
+  int prim_order[HT_MAX_PRIM];           // primitive indices sorted by type
+  double prim_inv2[HT_MAX_PRIM][3];      // 1 / size^2 (ellipsoid semi-axes)
 };
 
 constexpr int kMaxRects = 4;             // tile rectangles per particle (one per tree)

@@ -162,35 +162,68 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
 }
 
 // ------------------------------------------------------------------------------------
-// work list: exclusive scan of the per-particle item counts, item -> particle map, queue
-// reset.  Run by one workgroup of kBlock threads.
+// work list, built by one workgroup of kBlock threads.  The tiles per work item are chosen
+// from the launch's actual tile count: about kItemsPerGroup items per persistent workgroup,
+// a multiple of the wavefronts per workgroup, at least kFloorTilesFwd (kFloorTilesGrad for
+// a gradient) and at most the configured tiles_per_item (itself >= kMinTilesPerItem, which
+// sizes the workspace).  An exclusive scan of the per-particle item counts then gives the
+// item -> particle map, and the dequeue counter is reset here (no memset: graph-capturable).
 
-__device__ void schedule_items(int n_total, const Workspace& ws) {
+constexpr int kItemsPerGroup = 1;
+
+// Inclusive scan over the workgroup; every thread gets its own prefix and the total.
+__device__ int block_scan(int* s_sum, int v, int* total) {
+  const int t = threadIdx.x;
+  s_sum[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {   // Hillis-Steele
+    const int u = t >= o ? s_sum[t - o] : 0;
+    __syncthreads();
+    s_sum[t] += u;
+    __syncthreads();
+  }
+  const int r = s_sum[t];
+  *total = s_sum[kBlock - 1];
+  __syncthreads();
+  return r;
+}
+
+__device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& ws) {
   __shared__ int s_sum[kBlock];
   const int t = threadIdx.x;
   const int chunk = (n_total + kBlock - 1) / kBlock;
   const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
+  int tiles = 0;
+  for (int i = b; i < e; ++i) tiles += ws.pinfo[i].n_tiles;
+  int total_tiles;
+  block_scan(s_sum, tiles, &total_tiles);
+  const long long target = (long long)a.grid * kItemsPerGroup;
+  long long tq = ((long long)total_tiles + target - 1) / target;
+  tq = (tq + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
+  // a gradient item also writes and its finalize re-reads a wrench per segment: longer items
+  const long long lo = a.grad ? (long long)kFloorTilesGrad : (long long)kFloorTilesFwd;
+  const int tpi = (int)max(min(lo, (long long)a.tiles_per_item), min(tq, (long long)a.tiles_per_item));
+
   int local = 0;
-  for (int i = b; i < e; ++i) local += ws.pinfo[i].n_items;
-  s_sum[t] = local;
-  __syncthreads();
-  for (int o = 1; o < kBlock; o <<= 1) {   // Hillis-Steele inclusive scan
-    const int v = t >= o ? s_sum[t - o] : 0;
-    __syncthreads();
-    s_sum[t] += v;
-    __syncthreads();
+  for (int i = b; i < e; ++i) {
+    const int n = (ws.pinfo[i].n_tiles + tpi - 1) / tpi;
+    ws.pinfo[i].n_items = n;
+    local += n;
   }
-  int off = s_sum[t] - local;
+  int total_items;
+  const int incl = block_scan(s_sum, local, &total_items);
+  int off = incl - local;
   for (int i = b; i < e; ++i) {
     ws.item_off[i] = off;
     const int n = ws.pinfo[i].n_items;
     for (int j = 0; j < n; ++j) ws.item_map[off + j] = i;
     off += n;
   }
-  if (t == kBlock - 1) {
-    ws.item_off[n_total] = s_sum[t];
-    ws.counters[1] = s_sum[t];
+  if (t == 0) {
+    ws.item_off[n_total] = total_items;
     ws.counters[0] = 0;
+    ws.counters[1] = total_items;
+    ws.counters[2] = tpi;
   }
 }
 
@@ -251,7 +284,6 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   const int p = blockIdx.x * kWavesPerBlock + w;
   const bool active = p < n_total;
   const int n_dof = a.n_dof, n_seg = a.n_seg, n_prim = a.n_prim;
-  const int tpi = a.tiles_per_item;
 
   // every angle's sine and cosine at once (one lane per pose parameter), so the tree walk
   // below is trigonometry-free
@@ -274,91 +306,110 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   const bool valid = slot_ok && finite;
   __syncthreads();
 
-  // segment transforms, level by level (parents precede children)
-  for (int level = 0; level <= M.max_depth; ++level) {
-    if (valid && lane < n_seg && M.seg_depth[lane] == level) {
-      double T[12], T0[12];
-      const int par = M.seg_parent[lane];
-      if (par < 0) {
-        const int b = M.seg_root_dof[lane];
-        const double* q = &s_h[w][b];
-        const double sx = s_sin[w][b + 3], cx = s_cos[w][b + 3];
-        const double sy = s_sin[w][b + 4], cy = s_cos[w][b + 4];
-        const double sz = s_sin[w][b + 5], cz = s_cos[w][b + 5];
-        // Rz(tz) Ry(ty) Rx(tx)
-        const double Rzy[9] = {cz * cy, -sz, cz * sy, sz * cy, cz, sz * sy, -sy, 0.0, cy};
-        T0[0] = Rzy[0];
-        T0[1] = Rzy[1] * cx + Rzy[2] * sx;
-        T0[2] = -Rzy[1] * sx + Rzy[2] * cx;
-        T0[3] = q[0];
-        T0[4] = Rzy[3];
-        T0[5] = Rzy[4] * cx + Rzy[5] * sx;
-        T0[6] = -Rzy[4] * sx + Rzy[5] * cx;
-        T0[7] = q[1];
-        T0[8] = Rzy[6];
-        T0[9] = Rzy[7] * cx + Rzy[8] * sx;
-        T0[10] = -Rzy[7] * sx + Rzy[8] * cx;
-        T0[11] = q[2];
-        // wrist dofs: translations along camera axes; rotations about Rz Ry e_x, Rz e_y, e_z
-        // through the wrist position
-        float* df = ws.dof_frame + ((size_t)p * n_dof + b) * 8;
-        for (int i = 0; i < 3; ++i) {
-          float* f = df + i * 8;
-          f[0] = 1.0f;
-          f[1] = i == 0;
-          f[2] = i == 1;
-          f[3] = i == 2;
-          f[4] = f[5] = f[6] = f[7] = 0.0f;
-        }
-        const double ax[3][3] = {{T0[0], T0[4], T0[8]}, {-sz, cz, 0.0}, {0.0, 0.0, 1.0}};
-        for (int i = 0; i < 3; ++i) {
-          float* f = df + (3 + i) * 8;
-          f[0] = 0.0f;
-          f[1] = (float)ax[i][0];
-          f[2] = (float)ax[i][1];
-          f[3] = (float)ax[i][2];
-          f[4] = (float)q[0];
-          f[5] = (float)q[1];
-          f[6] = (float)q[2];
-          f[7] = 0.0f;
-        }
-      } else {
-        for (int i = 0; i < 12; ++i) T0[i] = s_T[w][par][i];
-      }
-      mul34(T0, M.seg_off[lane], T);
+  // segment transforms: every lane composes its own segment's chain (the ancestors' local
+  // transforms, right to left, then the wrist), so no level-by-level synchronisation is
+  // needed; the tree is shallow (palm and three phalanges)
+  if (valid && lane < n_seg) {
+    double P[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};   // ancestors below the root
+    int q = M.seg_parent[lane], root = lane;
+    while (q >= 0) {
+      double L[12], Q[12];
+      for (int i = 0; i < 12; ++i) L[i] = M.seg_off[q][i];
       for (int j = 0; j < 2; ++j) {
-        const int dof = M.seg_dof[lane][j];
-        if (dof < 0) continue;
-        const double* ax = M.seg_axis[lane][j];
-        float* f = ws.dof_frame + ((size_t)p * n_dof + dof) * 8;
-        f[0] = 0.0f;
-        for (int i = 0; i < 3; ++i) {
-          f[1 + i] = (float)(T[i * 4 + 0] * ax[0] + T[i * 4 + 1] * ax[1] + T[i * 4 + 2] * ax[2]);
-          f[4 + i] = (float)T[i * 4 + 3];
-        }
-        f[7] = 0.0f;
-        post_rotate(T, ax, s_sin[w][dof], s_cos[w][dof]);
+        const int dof = M.seg_dof[q][j];
+        if (dof >= 0) post_rotate(L, M.seg_axis[q][j], s_sin[w][dof], s_cos[w][dof]);
       }
-      for (int i = 0; i < 12; ++i) s_T[w][lane][i] = T[i];
-      float* so = ws.seg_org + ((size_t)p * n_seg + lane) * 4;
-      so[0] = (float)T[3];
-      so[1] = (float)T[7];
-      so[2] = (float)T[11];
-      so[3] = 0.0f;
+      mul34(L, P, Q);
+      for (int i = 0; i < 12; ++i) P[i] = Q[i];
+      root = q;
+      q = M.seg_parent[q];
     }
-    __syncthreads();
+    // wrist: Trans(x, y, z) Rz(tz) Ry(ty) Rx(tx)
+    const int b = M.seg_root_dof[root];
+    const double* hq = &s_h[w][b];
+    const double sx = s_sin[w][b + 3], cx = s_cos[w][b + 3];
+    const double sy = s_sin[w][b + 4], cy = s_cos[w][b + 4];
+    const double sz = s_sin[w][b + 5], cz = s_cos[w][b + 5];
+    const double Rzy[9] = {cz * cy, -sz, cz * sy, sz * cy, cz, sz * sy, -sy, 0.0, cy};
+    double W0[12];
+    W0[0] = Rzy[0];
+    W0[1] = Rzy[1] * cx + Rzy[2] * sx;
+    W0[2] = -Rzy[1] * sx + Rzy[2] * cx;
+    W0[3] = hq[0];
+    W0[4] = Rzy[3];
+    W0[5] = Rzy[4] * cx + Rzy[5] * sx;
+    W0[6] = -Rzy[4] * sx + Rzy[5] * cx;
+    W0[7] = hq[1];
+    W0[8] = Rzy[6];
+    W0[9] = Rzy[7] * cx + Rzy[8] * sx;
+    W0[10] = -Rzy[7] * sx + Rzy[8] * cx;
+    W0[11] = hq[2];
+    if (root == lane) {
+      // wrist dofs: translations along camera axes; rotations about Rz Ry e_x, Rz e_y, e_z
+      // through the wrist position
+      float* df = ws.dof_frame + ((size_t)p * n_dof + b) * 8;
+      for (int i = 0; i < 3; ++i) {
+        float* f = df + i * 8;
+        f[0] = 1.0f;
+        f[1] = i == 0;
+        f[2] = i == 1;
+        f[3] = i == 2;
+        f[4] = f[5] = f[6] = f[7] = 0.0f;
+      }
+      const double ax[3][3] = {{W0[0], W0[4], W0[8]}, {-sz, cz, 0.0}, {0.0, 0.0, 1.0}};
+      for (int i = 0; i < 3; ++i) {
+        float* f = df + (3 + i) * 8;
+        f[0] = 0.0f;
+        f[1] = (float)ax[i][0];
+        f[2] = (float)ax[i][1];
+        f[3] = (float)ax[i][2];
+        f[4] = (float)hq[0];
+        f[5] = (float)hq[1];
+        f[6] = (float)hq[2];
+        f[7] = 0.0f;
+      }
+    }
+    double T0[12], T[12];
+    mul34(W0, P, T0);                 // the parent's frame (the wrist for a root)
+    mul34(T0, M.seg_off[lane], T);
+    for (int j = 0; j < 2; ++j) {
+      const int dof = M.seg_dof[lane][j];
+      if (dof < 0) continue;
+      const double* ax = M.seg_axis[lane][j];
+      float* f = ws.dof_frame + ((size_t)p * n_dof + dof) * 8;
+      f[0] = 0.0f;
+      for (int i = 0; i < 3; ++i) {
+        f[1 + i] = (float)(T[i * 4 + 0] * ax[0] + T[i * 4 + 1] * ax[1] + T[i * 4 + 2] * ax[2]);
+        f[4 + i] = (float)T[i * 4 + 3];
+      }
+      f[7] = 0.0f;
+      post_rotate(T, ax, s_sin[w][dof], s_cos[w][dof]);
+    }
+    for (int i = 0; i < 12; ++i) s_T[w][lane][i] = T[i];
+    float* so = ws.seg_org + ((size_t)p * n_seg + lane) * 4;
+    so[0] = (float)T[3];
+    so[1] = (float)T[7];
+    so[2] = (float)T[11];
+    so[3] = 0.0f;
   }
+  // collision terms of Eq. 5, one per spare lane (summed in order below)
+  __shared__ double s_kc[kWavesPerBlock][HT_MAX_KC];
+  if (valid && lane >= kWave - HT_MAX_KC && lane - (kWave - HT_MAX_KC) < M.n_kc) {
+    const int i = lane - (kWave - HT_MAX_KC);
+    s_kc[w][i] = fmax(-(s_h[w][M.kc_a[i]] - s_h[w][M.kc_b[i]]), 0.0);
+  }
+  __syncthreads();
 
-  // primitive records and screen boxes
-  int ru0[kMaxRects], ru1[kMaxRects], rv0[kMaxRects], rv1[kMaxRects];
-#pragma unroll
-  for (int r = 0; r < kMaxRects; ++r) {
-    ru0[r] = rv0[r] = INT_MAX;
-    ru1[r] = rv1[r] = INT_MIN;
-  }
+  // primitive records and screen boxes, in type order (a wave's lanes then take at most two
+  // of the three set-up paths per round); per-tree unions of the primitive boxes (u0, v0 minima; u1, v1 maxima), accumulated with
+  // LDS atomics (cheaper than sixteen wave reductions)
+  __shared__ int s_rect[kWavesPerBlock][kMaxRects][4];
+  if (lane < kMaxRects * 4) s_rect[w][lane >> 2][lane & 3] = (lane & 1) ? INT_MIN : INT_MAX;
+  __syncthreads();
   if (valid) {
     const FrameSlot fs = a.slots[slot];
-    for (int k = lane; k < n_prim; k += kWave) {
+    for (int o = lane; o < n_prim; o += kWave) {
+      const int k = M.prim_order[o];
       const int s = M.prim_seg[k];
       double F[12];
       mul34(s_T[w][s], M.prim_frame[k], F);
@@ -386,8 +437,8 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       } else if (typ == HT_CYLINDER) {
         const double r = sz[0], L = sz[1];
         double u[3] = {F[2], F[6], F[10]};
-        const double nu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        for (int i = 0; i < 3; ++i) u[i] /= nu;
+        const double inu = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        for (int i = 0; i < 3; ++i) u[i] *= inu;
         rec[3] = (float)(r * r);
         rec[7] = (float)L;
         rec[8] = (float)u[0];
@@ -404,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
         // Q = R diag(1/s^2) R^T, R = rotation part of F
         double Q[6] = {0, 0, 0, 0, 0, 0};
         for (int j = 0; j < 3; ++j) {
-          const double inv = 1.0 / (sz[j] * sz[j]);
+          const double inv = M.prim_inv2[k][j];
           const double r0 = F[0 * 4 + j], r1 = F[1 * 4 + j], r2 = F[2 * 4 + j];
           Q[0] += inv * r0 * r0;
           Q[1] += inv * r0 * r1;
@@ -498,32 +549,22 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       if (box.x > box.y || box.z > box.w) box = make_int4(1, 0, 1, 0);
       ws.boxes[(size_t)p * n_prim + k] = box;
       if (box.x <= box.y) {
-        const int q = M.prim_root[k];
-#pragma unroll
-        for (int r = 0; r < kMaxRects; ++r) {
-          if (r != q) continue;
-          ru0[r] = min(ru0[r], box.x);
-          ru1[r] = max(ru1[r], box.y);
-          rv0[r] = min(rv0[r], box.z);
-          rv1[r] = max(rv1[r], box.w);
-        }
+        int* rq = s_rect[w][M.prim_root[k]];
+        atomicMin(rq + 0, box.x);
+        atomicMax(rq + 1, box.y);
+        atomicMin(rq + 2, box.z);
+        atomicMax(rq + 3, box.w);
       }
     }
   }
-#pragma unroll
-  for (int r = 0; r < kMaxRects; ++r) {
-    ru0[r] = wave_min(ru0[r]);
-    rv0[r] = wave_min(rv0[r]);
-    ru1[r] = wave_max(ru1[r]);
-    rv1[r] = wave_max(rv1[r]);
-  }
+  __syncthreads();
   if (active && lane == 0) {
     PInfo pi{};
     pi.slot = slot_ok ? slot : -1;
     pi.valid = valid ? 1 : 0;
     double kc = 0.0;
     if (valid)
-      for (int i = 0; i < M.n_kc; ++i) kc += fmax(-(s_h[w][M.kc_a[i]] - s_h[w][M.kc_b[i]]), 0.0);
+      for (int i = 0; i < M.n_kc; ++i) kc += s_kc[w][i];
     pi.kc = (float)kc;
     // one tile rectangle per tree, as (x0, y0, x1, y1) inclusive; merge overlapping ones so
     // that no tile is visited twice
@@ -532,8 +573,9 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
     if (valid) {
 #pragma unroll
       for (int r = 0; r < kMaxRects; ++r) {
-        if (ru0[r] > ru1[r]) continue;
-        R[n++] = make_int4(ru0[r] / kTile, rv0[r] / kTile, ru1[r] / kTile, rv1[r] / kTile);
+        const int* rr = s_rect[w][r];
+        if (rr[0] > rr[1]) continue;
+        R[n++] = make_int4(rr[0] / kTile, rr[2] / kTile, rr[1] / kTile, rr[3] / kTile);
       }
     }
     bool merged = true;
@@ -558,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       pi.rect[i] = make_int4(R[i].x, R[i].y, tw, th);
       pi.n_tiles += tw * th;
     }
-    pi.n_items = (pi.n_tiles + tpi - 1) / tpi;
+    pi.n_items = 0;   // set by the work-list kernel
     ws.pinfo[p] = pi;
   }
 }
@@ -566,8 +608,8 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
 // The work list is built by its own one-workgroup launch: folding it into the kinematics
 // kernel as "the last workgroup to finish builds it" needs a device-scope fence in every
 // workgroup, which on a multi-XCD part (one L2 per XCD) costs far more than a launch.
-__global__ __launch_bounds__(kBlock) void sched_kernel(int n_total, Workspace ws) {
-  schedule_items(n_total, ws);
+__global__ __launch_bounds__(kBlock) void sched_kernel(EvalArgs a, Workspace ws) {
+  schedule_items(a, a.n_frames * a.n_particles, ws);
 }
 
 // ------------------------------------------------------------------------------------
@@ -806,8 +848,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   const int n_prim = a.n_prim, n_seg = a.n_seg;
-  const int tpi = a.tiles_per_item;
-  const int total = ws.counters[1];
+  const int tpi = uni(ws.counters[2]);
+  const int total = uni(ws.counters[1]);
   int cur_p = -1;
   FrameSlot fs{};
   const PInfo& pi = s_pi;
@@ -1116,7 +1158,7 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
                          dim3(kBlock), 0, s, a, ws);
       break;
     case kStageSched:
-      hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kBlock), 0, s, n_total, ws);
+      hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kBlock), 0, s, a, ws);
       if (dbg) {
         const size_t n = (size_t)a.n_particles * a.dbg_H * a.dbg_W;
         hipLaunchKernelGGL(debug_fill_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
