@@ -30,6 +30,36 @@ PEAK_FP32_VALU = 157.3e12      # MI355X vector FP32, FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E, B/s
 METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at equal pose error"
 
+# HBM traffic of the forward ray-cast kernel: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch, mean over the dispatches of one profiled run of the named workload), each scaled
+# by what the same counter reads for a plain device copy of known size (256 MiB: FETCH_SIZE
+# reads half the bytes read, WRITE_SIZE all the bytes written).  Keyed by the SHA-256 of the
+# kernel sources it was measured on: any later change of the kernel reports null.
+MEASURED_TRAFFIC = {
+    "d257de2533bcb5d108295f4820c271a7647466c1f4edd8567b09c9ee365c8560": {
+        "config": 4, "fetch_kib": 4653.13, "write_kib": 276.221, "fetch_scale": 2.0,
+        "write_scale": 1.0},
+}
+KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",
+                  "paper_2005_07068_amd/csrc/ht_device.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config: int):
+    """Bytes per launch from the counters above, or None if they do not apply."""
+    t = MEASURED_TRAFFIC.get(kernel_source_hash())
+    if t is None or t["config"] != config:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def load_workload(idx: int):
     from workload import CONFIGS, make_hand_model, seed_sequence
@@ -380,7 +410,8 @@ def main():
     flops_launch = flops_per_eval * particles_per_launch
     achieved = flops_launch / (avg_ms / 1e3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                "traffic": measured_traffic(args.config),
                 "kernel": "raycast_kernel<false,false>", "avg_launch_ms": avg_ms,
                 "particles_per_launch": particles_per_launch,
                 "algorithmic_flops_per_eval": flops_per_eval}

@@ -39,3 +39,17 @@ def test_joint_error_metric():
     t[:20] = np.deg2rad(2.0)
     assert abs(bench.joint_error_deg(h[:26], t[:26], 1) - 2.0) < 1e-12
     assert abs(bench.joint_error_deg(h, t, 2) - 1.0) < 1e-12
+
+
+def test_measured_traffic_only_for_the_measured_kernel(monkeypatch):
+    """The roofline traffic figure applies only to the kernel sources it was measured on."""
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.kernel_source_hash()
+    rec = {"config": 4, "fetch_kib": 100.0, "write_kib": 10.0, "fetch_scale": 2.0,
+           "write_scale": 1.0}
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", {h: rec})
+    assert bench.measured_traffic(4) == 1024.0 * (200.0 + 10.0)
+    assert bench.measured_traffic(3) is None
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", {"0" * 64: rec})
+    assert bench.measured_traffic(4) is None
