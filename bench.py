@@ -412,7 +412,9 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
                 "traffic": measured_traffic(args.config),
-                "kernel": "raycast_kernel<false,false>", "avg_launch_ms": avg_ms,
+                "kernel": "raycast_kernel<false,false,%d>" % (5 if model["prim_type"].max() > 2
+                                                              else 3),
+                "avg_launch_ms": avg_ms,
                 "particles_per_launch": particles_per_launch,
                 "algorithmic_flops_per_eval": flops_per_eval}
 

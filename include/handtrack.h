@@ -8,7 +8,8 @@
  *   - a pose h is the 26-vector of Eq. 1-3 (five fingers x (MP flexion, MP abduction, PIP,
  *     DIP), then wrist x, y, z, theta_x, theta_y, theta_z); a two-hand particle is 52-D;
  *   - the model depth image r_d(h, C) of section III.A is the exact nearest entry depth of a
- *     sphere / closed cylinder / ellipsoid hand (section II.A) along each pixel ray;
+ *     hand built from spheres, ellipsoids, closed truncated cones, closed elliptic and
+ *     circular cylinders (section II.A) along each pixel ray;
  *   - the cost is E(h, O) = D(O, h, C) + lambda_k kc(h) of Eq. 4-5 with d_m = 10 mm,
  *     d_M = 40 mm, lambda = 20, lambda_k = 10, sums over every ROI pixel;
  *   - the swarm moves by Eq. 6-7 with bounds (Tables 1-2) and the mutation of section III.B.
@@ -49,7 +50,7 @@ typedef enum {
   HT_ERR_UNSUPPORTED = -5   /* valid request outside what this build supports              */
 } ht_status;
 
-enum { HT_SPHERE = 0, HT_CYLINDER = 1, HT_ELLIPSOID = 2 };
+enum { HT_SPHERE = 0, HT_CYLINDER = 1, HT_ELLIPSOID = 2, HT_CONE = 3, HT_ECYLINDER = 4 };
 enum { HT_PTR_HOST = 0, HT_PTR_DEVICE = 1 };
 
 /* Limits of this build. */
@@ -84,6 +85,12 @@ void ht_destroy(ht_ctx* ctx);
  *   HT_CYLINDER   closed, flat caps; first cap centre = frame origin, axis = frame z,
  *                 radius = size[0], length = size[1]
  *   HT_ELLIPSOID  centre = frame origin, semi-axes size[0..2] along frame x, y, z
+ *   HT_CONE       truncated cone (the phalanges of section II.A), closed, flat caps; first
+ *                 cap centre = frame origin, axis = frame z, radius size[0] at the first cap,
+ *                 length size[1], radius size[2] at the second cap
+ *   HT_ECYLINDER  elliptic cylinder (the palm of section II.A), closed, flat caps; first cap
+ *                 centre = frame origin, axis = frame z, semi-axes size[0] along frame x and
+ *                 size[2] along frame y, length size[1]
  * kc (Eq. 5): sum over pairs of max(-(h[a] - h[b]), 0).
  * Errors: HT_ERR_ARG for counts beyond the limits, a bad parent order, a non-unit axis, a
  * dof index out of range, non-positive sizes or lo > hi. */
@@ -94,7 +101,7 @@ typedef struct {
   const double* seg_offset;      /* [n_seg][3][4] rotation | translation, mm                 */
   const double* seg_joint_axis;  /* [n_seg][2][3] unit axes in the segment frame             */
   const int32_t* seg_joint_dof;  /* [n_seg][2], -1 = no joint                                */
-  const int32_t* prim_type;      /* [n_prim] HT_SPHERE / HT_CYLINDER / HT_ELLIPSOID          */
+  const int32_t* prim_type;      /* [n_prim] HT_SPHERE .. HT_ECYLINDER                        */
   const int32_t* prim_seg;       /* [n_prim]                                                 */
   const double* prim_frame;      /* [n_prim][3][4]                                           */
   const double* prim_size;       /* [n_prim][3], mm                                          */

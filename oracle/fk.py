@@ -96,7 +96,10 @@ def primitive_frames(model: dict, h) -> np.ndarray:
 def camera_primitives(model: dict, h) -> list[dict]:
     """Each primitive in camera coordinates: type, origin p, rotation R (columns = local
     axes), sizes.  Sphere: centre p, radius size[0].  Cylinder: first cap centre p, axis R[:,2],
-    radius size[0], length size[1].  Ellipsoid: centre p, semi-axes size along R's columns."""
+    radius size[0], length size[1].  Ellipsoid: centre p, semi-axes size along R's columns.
+    Truncated cone: first cap centre p, axis R[:,2], radii size[0] (s = 0) and size[2]
+    (s = L), length size[1].  Elliptic cylinder: first cap centre p, axis R[:,2], semi-axes
+    size[0] along R[:,0] and size[2] along R[:,1], length size[1]."""
     F = primitive_frames(model, h)
     prims = []
     for k in range(model["n_prim"]):

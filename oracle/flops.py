@@ -13,6 +13,10 @@ implementation may perform and discard are not counted.
   cylinder   68  (axial part of d 5, perpendicular part 6, side quadratic 13, two side
                   roots 4, their axial slabs 4 + 4 tests, two caps 2 x 14, nearest of four
                   candidates 3, nearest-depth 1)
+  cone       78  (as the cylinder, plus the radius at the reference point 2, the k terms of
+                  the side quadratic 5, two cap radii 2, and the quadratic's A -> 0 safe
+                  roots 1)
+  elliptic cylinder  74  (map of d to the unit-radius frame 6, then the cylinder's 68)
   pixel      19  (ray direction 4, d.d 5, |o_d - r_d| 2, clamp 1, two depth tests 2, the
                   three Boolean terms 3, three accumulations 3, minus the shared 1)
 """
@@ -20,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-F_PRIM = {0: 16, 1: 68, 2: 35}
+F_PRIM = {0: 16, 1: 68, 2: 35, 3: 78, 4: 74}
 F_PIXEL = 19
 
 

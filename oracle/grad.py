@@ -111,11 +111,21 @@ def depth_gradient(model: dict, h, res, W, H, cam):
         elif typ == raycast.ELLIPSOID:
             gy = 2.0 * y / (size ** 2)[None, :]
         else:
+            # capped solids: side surface G(y) = 0 below, caps y2 = 0 and y2 = L
             surf = res["prim_surface"][k].reshape(-1)[pix]
             gy = np.zeros_like(y)
             side = surf == 0
-            gy[side, 0] = 2.0 * y[side, 0]
-            gy[side, 1] = 2.0 * y[side, 1]
+            if typ == raycast.CYLINDER:
+                gy[side, 0] = 2.0 * y[side, 0]
+                gy[side, 1] = 2.0 * y[side, 1]
+            elif typ == raycast.CONE:          # y0^2 + y1^2 - (r0 + k y2)^2
+                kk = (size[2] - size[0]) / size[1]
+                gy[side, 0] = 2.0 * y[side, 0]
+                gy[side, 1] = 2.0 * y[side, 1]
+                gy[side, 2] = -2.0 * kk * (size[0] + kk * y[side, 2])
+            else:                              # (y0 / a)^2 + (y1 / b)^2 - 1
+                gy[side, 0] = 2.0 * y[side, 0] / size[0] ** 2
+                gy[side, 1] = 2.0 * y[side, 1] / size[2] ** 2
             gy[surf == 1, 2] = -1.0
             gy[surf == 2, 2] = 1.0
         denom = np.einsum("ij,ij->i", gy, yd)

@@ -18,6 +18,13 @@ far the ray is from flipping that decision:
   cylinder   max over its three surfaces of that surface's smallest slack: the side's radial
              slack (r^2 - rho^2)/r^2 and axial slacks s/L, (L-s)/L at each side crossing,
              each cap's radial slack (r^2 - rho_cap^2)/r^2 where the ray crosses its plane.
+  truncated cone   the same with the side's slack disc / (|A| r_max^2) of its quadratic
+             A t^2 + 2 B t + C (the cylinder's radial slack when r0 = r1) and each cap's radial
+             slack against that cap's radius.
+  elliptic cylinder   the cylinder's margin in the frame where it is the unit-radius cylinder.
+
+Section II.A builds the hand from spheres, truncated cones (phalanges), ellipsoids and an
+elliptic-cylinder palm; the circular cylinder is the truncated cone with equal radii.
 """
 from __future__ import annotations
 
@@ -25,7 +32,7 @@ import numpy as np
 
 from . import fk
 
-SPHERE, CYLINDER, ELLIPSOID = 0, 1, 2
+SPHERE, CYLINDER, ELLIPSOID, CONE, ECYLINDER = 0, 1, 2, 3, 4
 
 
 def pixel_directions(W: int, H: int, cam) -> np.ndarray:
@@ -115,6 +122,57 @@ def intersect_cylinder(o, d, p0, axis, r, L):
     return t_entry, hit, margin, surface
 
 
+def intersect_cone(o, d, p0, R, r0, L, r1):
+    """Rays against the closed truncated cone whose axis is R[:, 2] from p0 (s = 0, radius r0)
+    to p0 + L R[:, 2] (s = L, radius r1), capped by flat discs.  In the cone's frame a point y
+    is inside when y0^2 + y1^2 <= (r0 + k y2)^2 with k = (r1 - r0) / L and 0 <= y2 <= L."""
+    w = (np.asarray(o, np.float64) - p0) @ R          # local ray origin
+    e = d @ R                                          # local directions [N, 3]
+    k = (r1 - r0) / L
+    rw = r0 + k * w[2]                                 # radius at the origin's axial position
+    A = e[:, 0] ** 2 + e[:, 1] ** 2 - (k * e[:, 2]) ** 2
+    B = w[0] * e[:, 0] + w[1] * e[:, 1] - k * e[:, 2] * rw
+    C = w[0] ** 2 + w[1] ** 2 - rw ** 2
+    disc = B * B - A * C
+    rmax2 = max(r0, r1) ** 2
+    cand_t, slacks = [], []
+    with np.errstate(divide="ignore", invalid="ignore"):
+        disc_slack = np.where(A != 0.0, disc / (np.abs(A) * rmax2), np.inf)
+        sq = np.sqrt(np.where(disc >= 0.0, disc, 0.0))
+        # the two side roots in a form that stays finite as A -> 0
+        q = -(B + np.where(B >= 0.0, 1.0, -1.0) * sq)
+        roots = (np.where(q != 0.0, q / A, np.inf), np.where(q != 0.0, C / q, np.inf))
+        for t in roots:
+            s_ax = w[2] + t * e[:, 2]
+            slack = np.minimum(disc_slack, np.minimum(s_ax / L, (L - s_ax) / L))
+            slack = np.where(disc >= 0.0, slack, disc_slack)
+            ok = (disc >= 0.0) & np.isfinite(t) & (slack >= 0.0) & (t > 0.0)
+            cand_t.append(np.where(ok, t, np.inf))
+            slacks.append(np.where(np.isfinite(t), slack, -np.inf))
+        for s_cap, r_cap in ((0.0, r0), (L, r1)):
+            t = np.where(e[:, 2] != 0.0, (s_cap - w[2]) / e[:, 2], np.inf)
+            rad2 = (w[0] + t * e[:, 0]) ** 2 + (w[1] + t * e[:, 1]) ** 2
+            slack = np.where(e[:, 2] != 0.0, (r_cap * r_cap - rad2) / (r_cap * r_cap), -np.inf)
+            cand_t.append(np.where((slack >= 0.0) & (t > 0.0), t, np.inf))
+            slacks.append(slack)
+    cand = np.stack(cand_t)
+    t_entry = np.min(cand, axis=0)
+    margin = np.max(np.stack(slacks), axis=0)
+    hit = np.isfinite(t_entry)
+    surface = np.array([0, 0, 1, 2])[np.argmin(cand, axis=0)]
+    return t_entry, hit, margin, surface
+
+
+def intersect_ecylinder(o, d, p0, R, a, L, b):
+    """Rays against the closed elliptic cylinder with first cap centre p0, axis R[:, 2], length
+    L and semi-axes a along R[:, 0], b along R[:, 1].  An affine map (which keeps the ray
+    parameter) takes it to the unit-radius circular cylinder."""
+    S = np.array([1.0 / a, 1.0 / b, 1.0])
+    w = ((np.asarray(o, np.float64) - p0) @ R) * S
+    e = (d @ R) * S[None, :]
+    return intersect_cylinder(w, e, np.zeros(3), np.array([0.0, 0.0, 1.0]), 1.0, L)
+
+
 def intersect_primitive(o, d, prim):
     typ, p, R, size = prim["type"], prim["p"], prim["R"], prim["size"]
     zero = np.zeros(d.shape[0], np.int64)
@@ -124,6 +182,10 @@ def intersect_primitive(o, d, prim):
         return intersect_cylinder(o, d, p, R[:, 2], size[0], size[1])
     if typ == ELLIPSOID:
         return intersect_ellipsoid(o, d, p, R, size) + (zero,)
+    if typ == CONE:
+        return intersect_cone(o, d, p, R, size[0], size[1], size[2])
+    if typ == ECYLINDER:
+        return intersect_ecylinder(o, d, p, R, size[0], size[1], size[2])
     raise ValueError(f"unknown primitive type {typ}")
 
 
@@ -132,8 +194,8 @@ def render_primitives(prims, W, H, cam, bg_depth, cam_pose=None):
 
     Returns a dict with, per pixel: ``depth`` r_d, ``hit``, ``winner`` (primitive index of the
     nearest entry, lowest index on ties, -1 on a miss), ``zmin``; and per primitive
-    ``prim_t`` [n, H, W], ``prim_hit``, ``prim_margin``, ``prim_surface`` (cylinders: entry on
-    0 the side, 1 the cap at s = 0, 2 the cap at s = L).
+    ``prim_t`` [n, H, W], ``prim_hit``, ``prim_margin``, ``prim_surface`` (cylinders, cones and
+    elliptic cylinders: entry on 0 the side, 1 the cap at s = 0, 2 the cap at s = L).
 
     Background reading: with bg_depth B > 0 the scene has a plane at depth B, a model point
     behind it is hidden, misses render B and hit = (nearest entry < B).  With B <= 0 there is

@@ -19,11 +19,14 @@ from . import fk, raycast
 def hand_centre(model: dict, h, hand: int = 0) -> np.ndarray:
     """Centre of the axis-aligned box around the bounding spheres of one hand's primitives."""
     prims = fk.camera_primitives(model, h)
-    per = handmodel.PRIM_PER_HAND
+    per = model["n_prim"] // (model["n_dof"] // handmodel.DOF_PER_HAND)
     lo, hi = np.full(3, np.inf), np.full(3, -np.inf)
     for p in prims[hand * per:(hand + 1) * per]:
         if p["type"] == raycast.CYLINDER:
             r = p["size"][0]
+            ends = [p["p"], p["p"] + p["size"][1] * p["R"][:, 2]]
+        elif p["type"] in (raycast.CONE, raycast.ECYLINDER):
+            r = max(p["size"][0], p["size"][2])
             ends = [p["p"], p["p"] + p["size"][1] * p["R"][:, 2]]
         else:
             r = float(np.max(p["size"]))

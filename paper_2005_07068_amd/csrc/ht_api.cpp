@@ -403,7 +403,7 @@ ht_status build_model(const ht_model* m, ht::DevModel& d, ht::TypeMasks& tm) {
   tm = ht::TypeMasks{};
   for (int k = 0; k < m->n_prim; ++k) {
     const int t = m->prim_type[k], s = m->prim_seg[k];
-    if (t < HT_SPHERE || t > HT_ELLIPSOID) return fail(HT_ERR_ARG, "primitive %d: bad type %d", k, t);
+    if (t < HT_SPHERE || t > HT_ECYLINDER) return fail(HT_ERR_ARG, "primitive %d: bad type %d", k, t);
     if (s < 0 || s >= m->n_seg) return fail(HT_ERR_ARG, "primitive %d: segment %d out of range", k, s);
     d.prim_type[k] = t;
     d.prim_seg[k] = s;
@@ -413,7 +413,7 @@ ht_status build_model(const ht_model* m, ht::DevModel& d, ht::TypeMasks& tm) {
       d.prim_inv2[k][i] = z > 0.0 ? 1.0 / (z * z) : 0.0;
     }
     for (int i = 0; i < 12; ++i) d.prim_frame[k][i] = m->prim_frame[k * 12 + i];
-    const int need = t == HT_SPHERE ? 1 : (t == HT_CYLINDER ? 2 : 3);
+    const int need = t == HT_SPHERE ? 1 : (t == HT_CYLINDER ? 2 : 3);   // sizes that must be > 0
     for (int i = 0; i < 3; ++i) {
       d.prim_size[k][i] = m->prim_size[k * 3 + i];
       if (i < need && !(d.prim_size[k][i] > 0.0)) return fail(HT_ERR_ARG, "primitive %d: size %d must be > 0", k, i);
@@ -422,7 +422,7 @@ ht_status build_model(const ht_model* m, ht::DevModel& d, ht::TypeMasks& tm) {
   }
   {
     int n = 0;
-    for (int t = HT_SPHERE; t <= HT_ELLIPSOID; ++t)
+    for (int t = HT_SPHERE; t <= HT_ECYLINDER; ++t)
       for (int k = 0; k < m->n_prim; ++k)
         if (m->prim_type[k] == t) d.prim_order[n++] = k;
   }

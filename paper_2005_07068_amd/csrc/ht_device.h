@@ -13,7 +13,8 @@ constexpr int kTilePx = kTile * kTile;
 constexpr int kWave = 64;
 constexpr int kBlock = 256;         // 4 wavefronts per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kRec = 16;            // floats per primitive record
+constexpr int kRec = 20;            // floats per primitive record
+constexpr int kNumTypes = 5;        // HT_SPHERE .. HT_ECYLINDER
 // Work items of the ray-cast kernel (tiles): never shorter than kMinTilesPerItem (the lower
 // bound of the configured tiles_per_item, which sizes the workspace); the work-list kernel
 // aims at kFloorTilesFwd / kFloorTilesGrad at least, capped by the configured value.
@@ -59,7 +60,7 @@ constexpr int kMaxRects = 4;             // tile rectangles per particle (one pe
 
 // Primitive index masks per type (bits for primitives 0..63 and 64..127).
 struct TypeMasks {
-  uint64_t m[3][2];
+  uint64_t m[kNumTypes][2];
 };
 
 // One observation slot.

@@ -434,35 +434,41 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
           lo3[i] = c[i] - r;
           hi3[i] = c[i] + r;
         }
-      } else if (typ == HT_CYLINDER) {
-        const double r = sz[0], L = sz[1];
+      } else if (typ == HT_CYLINDER || typ == HT_CONE) {
+        // circular cylinder (radius r0) or truncated cone (radius r0 at s = 0, r1 at s = L)
+        const double r0 = sz[0], L = sz[1], r1 = typ == HT_CONE ? sz[2] : sz[0];
         double u[3] = {F[2], F[6], F[10]};
         const double inu = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         for (int i = 0; i < 3; ++i) u[i] *= inu;
-        rec[3] = (float)(r * r);
+        rec[3] = typ == HT_CONE ? (float)r0 : (float)(r0 * r0);
         rec[7] = (float)L;
         rec[8] = (float)u[0];
         rec[9] = (float)u[1];
         rec[10] = (float)u[2];
-        rec[11] = (float)(c[0] * u[0] + c[1] * u[1] + c[2] * u[2]);
+        rec[11] = typ == HT_CONE ? (float)((r1 - r0) / L)
+                                 : (float)(c[0] * u[0] + c[1] * u[1] + c[2] * u[2]);
+        // the solid is the convex hull of its two cap discs
         for (int i = 0; i < 3; ++i) {
-          const double e = r * sqrt(fmax(0.0, 1.0 - u[i] * u[i]));
+          const double sn = sqrt(fmax(0.0, 1.0 - u[i] * u[i]));
           const double c1 = c[i] + L * u[i];
-          lo3[i] = fmin(c[i], c1) - e;
-          hi3[i] = fmax(c[i], c1) + e;
+          lo3[i] = fmin(c[i] - r0 * sn, c1 - r1 * sn);
+          hi3[i] = fmax(c[i] + r0 * sn, c1 + r1 * sn);
         }
       } else {
-        // Q = R diag(1/s^2) R^T, R = rotation part of F
+        // ellipsoid: Q = R diag(1/s^2) R^T with R the rotation part of F; elliptic cylinder:
+        // the same without the axis term, Q = ex ex^T / a^2 + ey ey^T / b^2
+        const bool ecyl = typ == HT_ECYLINDER;
+        const double inv[3] = {M.prim_inv2[k][0], ecyl ? M.prim_inv2[k][2] : M.prim_inv2[k][1],
+                               ecyl ? 0.0 : M.prim_inv2[k][2]};
         double Q[6] = {0, 0, 0, 0, 0, 0};
         for (int j = 0; j < 3; ++j) {
-          const double inv = M.prim_inv2[k][j];
           const double r0 = F[0 * 4 + j], r1 = F[1 * 4 + j], r2 = F[2 * 4 + j];
-          Q[0] += inv * r0 * r0;
-          Q[1] += inv * r0 * r1;
-          Q[2] += inv * r0 * r2;
-          Q[3] += inv * r1 * r1;
-          Q[4] += inv * r1 * r2;
-          Q[5] += inv * r2 * r2;
+          Q[0] += inv[j] * r0 * r0;
+          Q[1] += inv[j] * r0 * r1;
+          Q[2] += inv[j] * r0 * r2;
+          Q[3] += inv[j] * r1 * r1;
+          Q[4] += inv[j] * r1 * r2;
+          Q[5] += inv[j] * r2 * r2;
         }
         rec[3] = (float)Q[0];
         rec[7] = (float)Q[1];
@@ -470,16 +476,34 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
         rec[9] = (float)Q[3];
         rec[10] = (float)Q[4];
         rec[11] = (float)Q[5];
-        for (int i = 0; i < 3; ++i) {
-          const double e = sqrt((F[i * 4 + 0] * sz[0]) * (F[i * 4 + 0] * sz[0]) +
-                                (F[i * 4 + 1] * sz[1]) * (F[i * 4 + 1] * sz[1]) +
-                                (F[i * 4 + 2] * sz[2]) * (F[i * 4 + 2] * sz[2]));
-          lo3[i] = c[i] - e;
-          hi3[i] = c[i] + e;
+        if (ecyl) {
+          const double a = sz[0], L = sz[1], b = sz[2];
+          double u[3] = {F[2], F[6], F[10]};
+          const double inu = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+          for (int i = 0; i < 3; ++i) u[i] *= inu;
+          rec[16] = (float)u[0];
+          rec[17] = (float)u[1];
+          rec[18] = (float)u[2];
+          rec[19] = (float)L;
+          for (int i = 0; i < 3; ++i) {
+            const double e = sqrt((F[i * 4 + 0] * a) * (F[i * 4 + 0] * a) +
+                                  (F[i * 4 + 1] * b) * (F[i * 4 + 1] * b));
+            const double c1 = c[i] + L * u[i];
+            lo3[i] = fmin(c[i], c1) - e;
+            hi3[i] = fmax(c[i], c1) + e;
+          }
+        } else {
+          for (int i = 0; i < 3; ++i) {
+            const double e = sqrt((F[i * 4 + 0] * sz[0]) * (F[i * 4 + 0] * sz[0]) +
+                                  (F[i * 4 + 1] * sz[1]) * (F[i * 4 + 1] * sz[1]) +
+                                  (F[i * 4 + 2] * sz[2]) * (F[i * 4 + 2] * sz[2]));
+            lo3[i] = c[i] - e;
+            hi3[i] = c[i] + e;
+          }
         }
       }
       float4* dst = reinterpret_cast<float4*>(ws.recs + ((size_t)p * n_prim + k) * kRec);
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < kRec / 4; ++i)
         dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
 
       // conservative pixel box of the axis-aligned 3D box
@@ -512,12 +536,13 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
         if (typ == HT_SPHERE) {
           for (int i = 0; i < 3; ++i) q0[i] = q1[i] = c[i];
           cr = sz[0];
-        } else if (typ == HT_CYLINDER) {
+        } else if (typ == HT_CYLINDER || typ == HT_CONE || typ == HT_ECYLINDER) {
+          const float* u = rec + (typ == HT_ECYLINDER ? 16 : 8);
           for (int i = 0; i < 3; ++i) {
             q0[i] = c[i];
-            q1[i] = c[i] + sz[1] * (double)rec[8 + i];
+            q1[i] = c[i] + sz[1] * (double)u[i];
           }
-          cr = sz[0];
+          cr = typ == HT_CYLINDER ? sz[0] : fmax(sz[0], sz[2]);
         } else {
           int ia = 0;
           for (int i = 1; i < 3; ++i)
@@ -747,6 +772,131 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   }
 }
 
+// Closed truncated cone: radius R(s) = r0 + k s on 0 <= s <= L.  As for the cylinder, the
+// reference parameter t_r is the closest approach to the axis and every quantity is an offset
+// from it.  With w, p the perpendicular parts of the offset and of d, a3 the axial coordinate
+// at t_r and R0 = r0 + k a3, the side condition |w + tau p|^2 <= (R0 + k d_a tau)^2 is
+// alpha tau^2 + 2 beta tau + gamma <= 0 with alpha = A - (k d_a)^2, beta = B - k d_a R0,
+// gamma = rho^2 - R0^2.  For alpha >= 0 its solutions are the interval between the roots;
+// for alpha < 0 (a ray steeper than the cone's flank) they are the two rays outside the roots,
+// of which the slab meets at most one (the solid is convex).  The roots come from
+// q = -(beta + sign(beta) sqrt(disc)), tau = q / alpha and gamma / q, finite as alpha -> 0.
+template <bool GRAD>
+__device__ __forceinline__ void cone_test(const float* r, float dx, float dy, float dz,
+                                          float dd, Hit& h) {
+  const float ux = r[8], uy = r[9], uz = r[10], L = r[7], r0 = r[3], k = r[11];
+  const float da = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
+  const float px = fmaf(-da, ux, dx), py = fmaf(-da, uy, dy), pz = fmaf(-da, uz, dz);
+  const float A = fmaf(px, px, fmaf(py, py, pz * pz));
+  const bool par = A < 1.0e-6f * dd;
+  const float inv_da = fast_rcp(da);
+  const float t_side = fmaf(px, r[0], fmaf(py, r[1], pz * r[2])) * fast_rcp(A);
+  const float cu = fmaf(r[0], ux, fmaf(r[1], uy, r[2] * uz));
+  const float t_mid = (cu + 0.5f * L) * inv_da;
+  const float tr = par ? t_mid : t_side;
+  const float vx = fmaf(tr, dx, -r[0]) - r[4];
+  const float vy = fmaf(tr, dy, -r[1]) - r[5];
+  const float vz = fmaf(tr, dz, -r[2]) - r[6];
+  const float a3 = fmaf(vx, ux, fmaf(vy, uy, vz * uz));
+  const float wx = fmaf(-a3, ux, vx), wy = fmaf(-a3, uy, vy), wz = fmaf(-a3, uz, vz);
+  const float rho2 = fmaf(wx, wx, fmaf(wy, wy, wz * wz));
+  const float B = fmaf(wx, px, fmaf(wy, py, wz * pz));
+  const float R0 = fmaf(k, a3, r0);
+  const float kd = k * da;
+  const float alpha = fmaf(-kd, kd, A);
+  const float beta = fmaf(-kd, R0, B);
+  const float gamma = fmaf(-R0, R0, rho2);
+  const float disc = fmaf(beta, beta, -alpha * gamma);
+  const float sq = fast_sqrt(fmaxf(disc, 0.0f));
+  const float q = -(beta + copysignf(sq, beta));
+  const float ra = q / alpha, rb = gamma / q;
+  const float lo = fminf(ra, rb), hi = fmaxf(ra, rb);
+  // slab 0 <= s <= L as offsets from t_r
+  const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
+  const bool flat = da == 0.0f;
+  const bool inside = (a3 >= 0.0f) & (a3 <= L);
+  const float din = flat ? (inside ? -INFINITY : INFINITY) : fminf(d0, d1);
+  const float dout = flat ? (inside ? INFINITY : -INFINITY) : fmaxf(d0, d1);
+  const bool has = disc >= 0.0f;
+  float tin;
+  bool side;
+  if (alpha >= 0.0f) {
+    tin = fmaxf(lo, din);
+    side = lo >= din;
+    h.ok = has & (tin <= fminf(hi, dout));
+  } else {
+    // outside the roots: the piece below lo, else the piece above hi
+    const bool first = !has | (din <= fminf(dout, lo));
+    const float t2 = fmaxf(din, hi);
+    tin = first ? din : t2;
+    side = !first & (hi >= din);
+    h.ok = first ? (din <= dout) : (t2 <= dout);
+  }
+  h.t = tr + tin;
+  if (GRAD) {
+    h.rx = fmaf(tin, dx, vx);
+    h.ry = fmaf(tin, dy, vy);
+    h.rz = fmaf(tin, dz, vz);
+    // side normal: perpendicular offset minus k R(s) along the axis; caps: -/+ u
+    const float Rt = fmaf(kd, tin, R0);
+    const float sgn = da > 0.0f ? -1.0f : 1.0f;
+    h.nx = side ? fmaf(-k * Rt, ux, fmaf(tin, px, wx)) : sgn * ux;
+    h.ny = side ? fmaf(-k * Rt, uy, fmaf(tin, py, wy)) : sgn * uy;
+    h.nz = side ? fmaf(-k * Rt, uz, fmaf(tin, pz, wz)) : sgn * uz;
+  }
+}
+
+// Closed elliptic cylinder: the side is x^T Q x <= 1 for the offset x from the first cap
+// centre (Q = ex ex^T / a^2 + ey ey^T / b^2, Q u = 0), intersected with the slab 0 <= s <= L.
+// The reference parameter is the closest approach to the axis in the Q metric.
+template <bool GRAD>
+__device__ __forceinline__ void ecylinder_test(const float* r, float dx, float dy, float dz,
+                                               float dd, Hit& h) {
+  const float q00 = r[3], q01 = r[7], q02 = r[8], q11 = r[9], q12 = r[10], q22 = r[11];
+  const float ux = r[16], uy = r[17], uz = r[18], L = r[19];
+  const float qdx = fmaf(q00, dx, fmaf(q01, dy, q02 * dz));
+  const float qdy = fmaf(q01, dx, fmaf(q11, dy, q12 * dz));
+  const float qdz = fmaf(q02, dx, fmaf(q12, dy, q22 * dz));
+  const float dqd = fmaf(dx, qdx, fmaf(dy, qdy, dz * qdz));
+  const float da = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
+  const bool par = dqd < 1.0e-6f * dd * (q00 + q11 + q22);
+  const float inv = fast_rcp(dqd);
+  const float inv_da = fast_rcp(da);
+  const float cqd = fmaf(r[0], qdx, fmaf(r[1], qdy, r[2] * qdz));
+  const float cu = fmaf(r[0], ux, fmaf(r[1], uy, r[2] * uz));
+  const float tr = par ? (cu + 0.5f * L) * inv_da : cqd * inv;
+  const float vx = fmaf(tr, dx, -r[0]) - r[4];
+  const float vy = fmaf(tr, dy, -r[1]) - r[5];
+  const float vz = fmaf(tr, dz, -r[2]) - r[6];
+  const float qvx = fmaf(q00, vx, fmaf(q01, vy, q02 * vz));
+  const float qvy = fmaf(q01, vx, fmaf(q11, vy, q12 * vz));
+  const float qvz = fmaf(q02, vx, fmaf(q12, vy, q22 * vz));
+  const float vqv = fmaf(vx, qvx, fmaf(vy, qvy, vz * qvz));
+  const float B = fmaf(vx, qdx, fmaf(vy, qdy, vz * qdz));
+  const float cc = par ? 0.0f : -B * inv;
+  const float m = par ? 1.0f - vqv : fmaf(B, B * inv, 1.0f - vqv);
+  const float hs = par ? INFINITY : fast_sqrt(fmaxf(m, 0.0f) * inv);
+  const float a3 = fmaf(vx, ux, fmaf(vy, uy, vz * uz));
+  const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
+  const bool flat = da == 0.0f;
+  const bool inside = (a3 >= 0.0f) & (a3 <= L);
+  const float din = flat ? (inside ? -INFINITY : INFINITY) : fminf(d0, d1);
+  const float dout = flat ? (inside ? INFINITY : -INFINITY) : fmaxf(d0, d1);
+  const float tin = fmaxf(cc - hs, din), tout = fminf(cc + hs, dout);
+  h.ok = (m >= 0.0f) & (tin <= tout);
+  h.t = tr + tin;
+  if (GRAD) {
+    const bool cap = din > cc - hs;
+    h.rx = fmaf(tin, dx, vx);
+    h.ry = fmaf(tin, dy, vy);
+    h.rz = fmaf(tin, dz, vz);
+    const float sgn = da > 0.0f ? -1.0f : 1.0f;
+    h.nx = cap ? sgn * ux : fmaf(tin, qdx, qvx);
+    h.ny = cap ? sgn * uy : fmaf(tin, qdy, qvy);
+    h.nz = cap ? sgn * uz : fmaf(tin, qdz, qvz);
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // wave-uniform values: read once from lane 0 into scalar registers, so that the per-tile
 // bookkeeping runs on the scalar unit and holds no vector registers
@@ -833,9 +983,11 @@ struct TileWalk {
 // ------------------------------------------------------------------------------------
 // persistent ray cast + cost terms + reduction
 
-template <bool GRAD, bool DEBUG>
-// (forcing six wavefronts per SIMD spills registers and measured slower than the five the
-// natural register count allows)
+// NT: primitive types the model uses (3: spheres, cylinders, ellipsoids; kNumTypes: also
+// cones and elliptic cylinders), so a model without the latter keeps the smaller register
+// footprint.  (Forcing more wavefronts per SIMD than the natural register count allows
+// spills registers and measured slower.)
+template <bool GRAD, bool DEBUG, int NT>
 __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace ws,
                                                       TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
@@ -916,7 +1068,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
 #pragma unroll
-        for (int typ = 0; typ < 3; ++typ) {
+        for (int typ = 0; typ < NT; ++typ) {
           uint64_t m = mk[half] & tm.m[typ][half];
           while (m) {
             const int k = __builtin_ctzll(m) + half * kWave;
@@ -925,7 +1077,9 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
             Hit h;
             if (typ == HT_SPHERE) sphere_test<GRAD>(r, dx, dy, dz, inv_dd, h);
             else if (typ == HT_CYLINDER) cylinder_test<GRAD>(r, dx, dy, dz, dd, h);
-            else ellipsoid_test<GRAD>(r, dx, dy, dz, h);
+            else if (typ == HT_ELLIPSOID) ellipsoid_test<GRAD>(r, dx, dy, dz, h);
+            else if (typ == HT_CONE) cone_test<GRAD>(r, dx, dy, dz, dd, h);
+            else ecylinder_test<GRAD>(r, dx, dy, dz, dd, h);
             // nearest entry in front of the camera: as unsigned integers the bit patterns of
             // non-negative floats keep their order and negative ones (entries behind the
             // camera) exceed +inf; exact ties keep the first tested (branch-free selects)
@@ -1168,12 +1322,24 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
     case kStageRaycast: {
       const TypeMasks tm = a.type_masks;
       const dim3 grid(a.grid), block(kBlock);
-      if (a.grad) {
-        if (dbg) hipLaunchKernelGGL((raycast_kernel<true, true>), grid, block, 0, s, a, ws, tm);
-        else hipLaunchKernelGGL((raycast_kernel<true, false>), grid, block, 0, s, a, ws, tm);
+      const bool all = (tm.m[HT_CONE][0] | tm.m[HT_CONE][1] | tm.m[HT_ECYLINDER][0] |
+                        tm.m[HT_ECYLINDER][1]) != 0ull;
+      if (all) {
+        if (a.grad) {
+          if (dbg) hipLaunchKernelGGL((raycast_kernel<true, true, kNumTypes>), grid, block, 0, s, a, ws, tm);
+          else hipLaunchKernelGGL((raycast_kernel<true, false, kNumTypes>), grid, block, 0, s, a, ws, tm);
+        } else {
+          if (dbg) hipLaunchKernelGGL((raycast_kernel<false, true, kNumTypes>), grid, block, 0, s, a, ws, tm);
+          else hipLaunchKernelGGL((raycast_kernel<false, false, kNumTypes>), grid, block, 0, s, a, ws, tm);
+        }
       } else {
-        if (dbg) hipLaunchKernelGGL((raycast_kernel<false, true>), grid, block, 0, s, a, ws, tm);
-        else hipLaunchKernelGGL((raycast_kernel<false, false>), grid, block, 0, s, a, ws, tm);
+        if (a.grad) {
+          if (dbg) hipLaunchKernelGGL((raycast_kernel<true, true, 3>), grid, block, 0, s, a, ws, tm);
+          else hipLaunchKernelGGL((raycast_kernel<true, false, 3>), grid, block, 0, s, a, ws, tm);
+        } else {
+          if (dbg) hipLaunchKernelGGL((raycast_kernel<false, true, 3>), grid, block, 0, s, a, ws, tm);
+          else hipLaunchKernelGGL((raycast_kernel<false, false, 3>), grid, block, 0, s, a, ws, tm);
+        }
       }
       break;
     }

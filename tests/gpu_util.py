@@ -24,9 +24,11 @@ def torch_cuda():
     return torch
 
 
-def frame_for(cfg_idx: int, frame: int = 0, model_seed: int = 0):
+def frame_for(cfg_idx: int, frame: int = 0, model_seed: int = 0,
+              primitive_set: str = "cylinders"):
     cfg = CONFIGS[cfg_idx]
-    model = make_hand_model(seed_sequence(cfg_idx, 10_000 + model_seed), cfg.n_hands)
+    model = make_hand_model(seed_sequence(cfg_idx, 10_000 + model_seed), cfg.n_hands,
+                            primitive_set)
     fr = synth.make_frame(model, cfg, frame)
     return cfg, model, fr
 

@@ -20,8 +20,22 @@ def test_library_exports_every_declared_function():
 
 
 @pytest.mark.parametrize("n_hands", [1, 2])
-def test_model_tables_validate(n_hands):
-    binding.check_model(make_hand_model(3, n_hands))
+@pytest.mark.parametrize("prims", ["cylinders", "paper"])
+def test_model_tables_validate(n_hands, prims):
+    binding.check_model(make_hand_model(3, n_hands, prims))
+
+
+@pytest.mark.parametrize("kind,index", [("cone", 2), ("ecyl", 0), ("ecyl", 2)])
+def test_paper_primitive_sizes_validated(kind, index):
+    """A truncated cone needs both radii and the length, an elliptic cylinder both semi-axes
+    and the length, all positive."""
+    from workload import CONE, ECYLINDER
+    m = make_hand_model(4, 1, "paper")
+    m = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in m.items()}
+    k = int(np.nonzero(m["prim_type"] == (CONE if kind == "cone" else ECYLINDER))[0][0])
+    m["prim_size"][k, index] = 0.0
+    with pytest.raises(binding.HandtrackError):
+        binding.check_model(m)
 
 
 def _broken(mutate):

@@ -25,8 +25,25 @@ def _pose(model, seed):
     return h
 
 
+@pytest.fixture(scope="module")
+def paper_model():
+    return make_hand_model(22, 1, "paper")
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_analytic_matches_central_fd_on_smooth_pixels(model, seed):
+    _fd_check(model, seed)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_analytic_matches_central_fd_paper_primitives(paper_model, seed):
+    """The same with truncated-cone phalanges and the elliptic-cylinder palm."""
+    # grazing views of the tapered phalanges give depth derivatives of ~200 mm/rad with a
+    # large third derivative: a smaller step keeps the central-difference truncation small
+    _fd_check(paper_model, 10 + seed, step_rad=2e-4, step_mm=2e-3)
+
+
+def _fd_check(model, seed, step_rad=1e-3, step_mm=1e-2):
     W = H = 160
     cam = (360.0, 360.0, 79.5, 79.5)
     h_true = _pose(model, 100 + seed)
@@ -38,7 +55,8 @@ def test_analytic_matches_central_fd_on_smooth_pixels(model, seed):
     mask = grad.fd_mask(parts["render"], obs["depth"])
     assert (mask & parts["render"]["hit"]).sum() > 200
     _, g = grad.analytic_gradient(model, h, obs, pixel_mask=mask)
-    g_fd = grad.fd_gradient(model, h, obs, mask, parts["S_or"])
+    g_fd = grad.fd_gradient(model, h, obs, mask, parts["S_or"], step_rad=step_rad,
+                            step_mm=step_mm)
     scale = np.max(np.abs(g_fd))
     assert scale > 0
     # central differences with 1e-3 rad / 1e-2 mm steps: truncation error well below 5e-5

@@ -6,7 +6,7 @@ It holds no kinematics, no ray casting and no cost arithmetic, so that the produ
 the oracle can both consume the same inputs without sharing any of the method's code.
 """
 from .handmodel import (  # noqa: F401
-    DOF_PER_HAND, SEG_PER_HAND, PRIM_PER_HAND, SPHERE, CYLINDER, ELLIPSOID,
-    make_hand_model, finger_dof, WRIST_DOF,
+    DOF_PER_HAND, SEG_PER_HAND, PRIM_PER_HAND, PRIM_PER_HAND_PAPER, SPHERE, CYLINDER,
+    ELLIPSOID, CONE, ECYLINDER, make_hand_model, finger_dof, WRIST_DOF,
 )
 from .configs import CONFIGS, WorkloadConfig, camera_for_roi, seed_sequence  # noqa: F401

@@ -17,15 +17,26 @@ flexion turns a phalanx from +y towards +z; positive MP abduction turns a finger
 thumb (so the abduction axis is -z), which matches the signs of Table 1 where the ring and
 little finger ranges are non-positive.
 
-Primitive table: type (sphere, closed flat-capped circular cylinder, ellipsoid), segment,
-a local rigid frame (3x4 in the segment frame) and three sizes:
-  sphere     centre = frame origin, size = (r, 0, 0)
-  cylinder   first cap centre = frame origin, axis = frame z, size = (r, L, 0)
-  ellipsoid  centre = frame origin, semi-axes (a, b, c) along frame x, y, z
-The paper's hand (section II.A) uses truncated cones and an elliptic-cylinder palm; this
-table keeps its structure (palm body capped by two ellipsoids, three phalanges and four
-joint/tip spheres per finger, ellipsoidal thumb metacarpal) with 16 spheres, 16 cylinders and
-8 ellipsoids per hand, radii in [6, 12] mm and lengths in [20, 45] mm drawn from a seed.
+Primitive table: type, segment, a local rigid frame (3x4 in the segment frame) and three
+sizes:
+  sphere             centre = frame origin, size = (r, 0, 0)
+  cylinder           closed, flat caps; first cap centre = frame origin, axis = frame z,
+                     size = (r, L, 0)
+  ellipsoid          centre = frame origin, semi-axes (a, b, c) along frame x, y, z
+  truncated cone     closed, flat caps; first cap centre = frame origin, axis = frame z,
+                     size = (r0, L, r1): radius r0 at the first cap, r1 at the second
+  elliptic cylinder  closed, flat caps; first cap centre = frame origin, axis = frame z,
+                     size = (a, L, b): semi-axes a along frame x and b along frame y
+
+Two primitive sets share the kinematic tree:
+  "cylinders" (40 per hand: 16 spheres, 16 circular cylinders, 8 ellipsoids) - the workloads'
+      hand: palm body cylinder capped by two ellipsoids, thenar ellipsoid, forearm stub,
+      per finger a knuckle ellipsoid (thumb: ellipsoidal metacarpal), three phalanx
+      cylinders and joint / tip spheres;
+  "paper" (38 per hand, section II.A): the palm is an elliptic cylinder capped at both ends by
+      ellipsoids; every finger has three truncated-cone phalanges and four spheres (three
+      joints and the tip), except that the thumb's largest phalanx is an ellipsoid.
+Radii lie in [5, 14] mm and lengths in [20, 50] mm, drawn from a seed.
 """
 from __future__ import annotations
 
@@ -33,9 +44,10 @@ import numpy as np
 
 DOF_PER_HAND = 26
 SEG_PER_HAND = 16
-PRIM_PER_HAND = 40
+PRIM_PER_HAND = 40                 # the "cylinders" set
+PRIM_PER_HAND_PAPER = 38           # the "paper" set
 WRIST_DOF = 20
-SPHERE, CYLINDER, ELLIPSOID = 0, 1, 2
+SPHERE, CYLINDER, ELLIPSOID, CONE, ECYLINDER = 0, 1, 2, 3, 4
 
 # Table 1 (degrees): rows thumb, index, middle, ring, little; columns MPx, MPz, PIP, DIP.
 TABLE1_DEG = np.array([
@@ -154,17 +166,74 @@ def _one_hand(rng: np.random.Generator):
     return segs, prims
 
 
-def make_hand_model(seed, n_hands: int = 1) -> dict:
+def _one_hand_paper(rng: np.random.Generator):
+    """Tables of one hand with the primitive set of section II.A (38 primitives)."""
+    segs = []
+    prims = []
+    Yk = 52.0                           # knuckle line
+    segs.append((-1, _frame(), []))     # 0: palm (root)
+
+    # palm: elliptic cylinder across the hand (axis +x), its cross-section a (thickness, along
+    # z) by b (along the fingers, y), capped at both ends by ellipsoids of the same section
+    a_p = float(rng.uniform(10.0, 13.0))
+    b_p = float(rng.uniform(24.0, 30.0))
+    L_p = float(rng.uniform(38.0, 48.0))
+    y_p = Yk - b_p + 4.0
+    # _ALONG_X: frame z = hand +x, frame x = hand -z, frame y = hand +y
+    prims.append((ECYLINDER, 0, _frame(_ALONG_X, (-L_p / 2, y_p, 0.0)), (a_p, L_p, b_p)))
+    for side in (-1.0, 1.0):
+        prims.append((ELLIPSOID, 0, _frame(None, (side * L_p / 2, y_p, 0.0)),
+                      (float(rng.uniform(8.0, 12.0)), b_p, a_p)))
+
+    abd_axis = np.array([0.0, 0.0, -1.0])
+    flex_axis = np.array([1.0, 0.0, 0.0])
+    bases = {0: (L_p / 2 + 4.0, y_p - 10.0, 0.0), 1: (24.0, Yk, 0.0), 2: (8.0, Yk, 0.0),
+             3: (-8.0, Yk, 0.0), 4: (-24.0, Yk, 0.0)}
+    thumb_rot = _rz(-np.pi / 4) @ _ry(-np.pi / 3)
+    for f in range(5):
+        L = sorted([float(rng.uniform(20.0, 45.0)) for _ in range(3)], reverse=True)
+        r1 = float(rng.uniform(8.0, 11.0))
+        rad = [r1, max(5.0, 0.9 * r1), max(5.0, 0.8 * r1), max(5.0, 0.7 * r1)]
+        s1 = len(segs)
+        R0 = thumb_rot if f == 0 else None
+        segs.append((0, _frame(R0, bases[f]),
+                     [(abd_axis, finger_dof(f, 1)), (flex_axis, finger_dof(f, 0))]))
+        segs.append((s1, _frame(None, (0.0, L[0], 0.0)), [(flex_axis, finger_dof(f, 2))]))
+        segs.append((s1 + 1, _frame(None, (0.0, L[1], 0.0)), [(flex_axis, finger_dof(f, 3))]))
+        # joint spheres at the three segment origins and the fingertip
+        for j in range(3):
+            prims.append((SPHERE, s1 + j, _frame(), (rad[j], 0.0, 0.0)))
+        prims.append((SPHERE, s1 + 2, _frame(None, (0.0, L[2], 0.0)), (rad[3], 0.0, 0.0)))
+        # phalanges: truncated cones tapering from joint to joint (thumb: its largest phalanx
+        # is an ellipsoid)
+        for j in range(3):
+            if f == 0 and j == 0:
+                prims.append((ELLIPSOID, s1, _frame(None, (0.0, L[0] / 2, 0.0)),
+                              (rad[0], L[0] / 2, max(5.0, 0.85 * rad[0]))))
+            else:
+                prims.append((CONE, s1 + j, _frame(_ALONG_Y), (rad[j], L[j], rad[j + 1])))
+    assert len(segs) == SEG_PER_HAND and len(prims) == PRIM_PER_HAND_PAPER
+    return segs, prims
+
+
+def make_hand_model(seed, n_hands: int = 1, primitive_set: str = "cylinders") -> dict:
     """Build the model tables for ``n_hands`` identical hands (two-hand particles are 52-D).
 
-    ``seed`` is anything ``numpy.random.default_rng`` accepts.  All returned arrays are
-    contiguous; float tables are float64.
+    ``seed`` is anything ``numpy.random.default_rng`` accepts; ``primitive_set`` is
+    "cylinders" (40 primitives per hand) or "paper" (38, section II.A).  All returned arrays
+    are contiguous; float tables are float64.
     """
     if n_hands not in (1, 2):
         raise ValueError("n_hands must be 1 or 2")
     rng = np.random.default_rng(seed)
-    segs, prims = _one_hand(rng)
-    n_seg, n_prim, n_dof = SEG_PER_HAND * n_hands, PRIM_PER_HAND * n_hands, DOF_PER_HAND * n_hands
+    if primitive_set == "cylinders":
+        segs, prims = _one_hand(rng)
+    elif primitive_set == "paper":
+        segs, prims = _one_hand_paper(rng)
+    else:
+        raise ValueError(f"unknown primitive set {primitive_set!r}")
+    per = len(prims)
+    n_seg, n_prim, n_dof = SEG_PER_HAND * n_hands, per * n_hands, DOF_PER_HAND * n_hands
     m = {
         "n_dof": n_dof, "n_seg": n_seg, "n_prim": n_prim,
         "seg_parent": np.full(n_seg, -1, np.int32),
@@ -182,7 +251,7 @@ def make_hand_model(seed, n_hands: int = 1) -> dict:
     }
     lo, hi = joint_bounds_one_hand()
     for hnd in range(n_hands):
-        so, po, do = hnd * SEG_PER_HAND, hnd * PRIM_PER_HAND, hnd * DOF_PER_HAND
+        so, po, do = hnd * SEG_PER_HAND, hnd * per, hnd * DOF_PER_HAND
         for i, (parent, off, joints) in enumerate(segs):
             m["seg_parent"][so + i] = -1 if parent < 0 else parent + so
             m["seg_offset"][so + i] = off
