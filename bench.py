@@ -67,7 +67,7 @@ def load_workload(idx: int):
     d = np.load(os.path.join(ROOT, "workload", "data", f"config{idx}.npz"))
     frames = [{"depth": d[f"depth_{f}"], "skin": d[f"skin_{f}"], "cam": tuple(d["cam"][f]),
                "bg": float(d["bg"]), "h_true": d["h_true"][f]} for f in range(cfg.n_frames)]
-    model = make_hand_model(seed_sequence(idx, 10_000), cfg.n_hands)
+    model = make_hand_model(seed_sequence(idx, 10_000), cfg.n_hands, cfg.primitive_set)
     return cfg, model, frames, float(d["flops_per_eval"]), int(d["flops_sample"])
 
 
@@ -172,6 +172,65 @@ def pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16, P=
                      "mean_final_cost": float(np.mean(costs))}
     out["seeds"] = seeds
     return out
+
+
+def track_sequence(ht, torch, idx=6, stop_factor=None):
+    """Tracking over the stored sequence: frame t's swarm starts in the box around frame t-1's
+    global best (frame 0: around its true pose), all frames enqueued back to back (one graph
+    replay per frame, no host synchronisation in between).  With ``stop_factor`` the stop rule
+    is on with stop_cost = stop_factor x the median cost of the true poses."""
+    from workload.handmodel import init_halfwidth
+    cfg, model, frames, _, _ = load_workload(idx)
+    dev = torch.device("cuda:0")
+    ctx = ht.Context(0)
+    ctx.set_model(model)
+    for t, fr in enumerate(frames):
+        ctx.set_observation(t, fr["depth"], fr["skin"], fr["cam"], fr["bg"])
+    T, P, G, D = cfg.n_frames, cfg.n_particles, cfg.n_generations, model["n_dof"]
+    ctx.reserve(P, max(fr["depth"].size for fr in frames))
+    h_true = np.stack([fr["h_true"] for fr in frames])
+    stop_cost = 0.0
+    if stop_factor:
+        e_true = np.concatenate([ctx.eval(torch.tensor(h_true[t:t + 1], dtype=torch.float32,
+                                                       device=dev),
+                                          torch.tensor([t], dtype=torch.int32, device=dev))
+                                 .cpu().numpy() for t in range(T)])
+        stop_cost = float(stop_factor * np.median(e_true))
+    hw = torch.tensor(init_halfwidth(D, cfg.init_angle_deg, cfg.init_trans_mm),
+                      dtype=torch.float32, device=dev)
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    lo = torch.tensor(h_true[:1] - hw.cpu().numpy(), dtype=torch.float32)
+    sw = ctx.swarm(slots, P, lo, lo.clone(), seed=606)
+    params = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, stop_cost=stop_cost)
+    start = torch.tensor(h_true[:1], dtype=torch.float32, device=dev)
+    out = torch.zeros((T, D), dtype=torch.float32, device=dev)
+    gens = torch.zeros(T, dtype=torch.int32, device=dev)
+
+    def run_sequence():
+        center = start
+        for t in range(T):
+            sw["frame_slots"].fill_(t)
+            ctx.box_around(center, hw, sw["init_lo"], sw["init_hi"])
+            ctx.pso_run_graph(sw, params, G)
+            out[t].copy_(sw["gbest_x"][0])
+            gens[t].copy_(sw["gen"][0])
+            center = out[t:t + 1]
+
+    run_sequence()                      # capture + warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run_sequence()
+    e1.record()
+    torch.cuda.synchronize()
+    est = out.cpu().numpy().astype(np.float64)
+    err = [joint_error_deg(est[t], h_true[t], 1) for t in range(T)]
+    ctx.close()
+    return {"frames": T, "particles": P, "max_generations": G, "stop_cost": stop_cost,
+            "ms_per_frame": e0.elapsed_time(e1) / T,
+            "mean_generations": float(gens.float().mean().item()),
+            "mean_joint_error_deg": float(np.mean(err)), "max_joint_error_deg": float(np.max(err)),
+            "last_frame_error_deg": float(err[-1])}
 
 
 def roofline_sweep(ht, torch, totals=(256, 4096, 65536), min_ms=10.0):
@@ -298,7 +357,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=4, choices=[1, 3, 4])
+    ap.add_argument("--config", type=int, default=4, choices=[1, 3, 4, 5])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-study", action="store_true",
                     help="skip the plain-versus-refined swarm comparison")
@@ -306,6 +365,8 @@ def main():
                     help="add the swarm-constants / mutation ablation (plain swarm)")
     ap.add_argument("--sweep", action="store_true",
                     help="forward-only roofline sweep over particle counts (own JSON line)")
+    ap.add_argument("--track", action="store_true",
+                    help="tracking over the stored 30-frame sequence (own JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -318,14 +379,21 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if args.copy_calibration or args.sweep:
+    if args.copy_calibration or args.sweep or args.track:
         import torch
 
         import paper_2005_07068_amd as ht
         if args.copy_calibration:
             print(json.dumps(copy_calibration(torch, args.copy_calibration)), flush=True)
-        else:
+        elif args.sweep:
             print(json.dumps({"roofline_sweep": roofline_sweep(ht, torch)}), flush=True)
+        else:
+            log("tracking the 30-frame sequence, stop rule off")
+            plain = track_sequence(ht, torch)
+            log("tracking the 30-frame sequence, stop rule on")
+            stop = track_sequence(ht, torch, stop_factor=1.02)
+            print(json.dumps({"tracking": {"fixed_generations": plain, "stop_rule": stop}}),
+                  flush=True)
         return
 
     from workload.handmodel import init_halfwidth

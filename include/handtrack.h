@@ -171,7 +171,10 @@ ht_status ht_eval_particles_grad(ht_ctx* ctx, int n_frames, const int32_t* frame
 /* Swarm state, all device memory owned by the caller, float32 unless noted:
  *   x, v, pbest_x [F][P][n_dof]; pbest_cost, cost [F][P]; gbest_x [F][n_dof];
  *   gbest_cost [F]; gen: int32 [F] generation counters; frame_slots: int32 [F];
- *   init_lo, init_hi [F][n_dof]: box of the initial positions (ht_pso_init). */
+ *   init_lo, init_hi [F][n_dof]: box of the initial positions (ht_pso_init);
+ *   stop_gen: int32 [F] or NULL, needed for the stop rule (ht_pso_params.stop_cost): 0 while
+ *   a frame runs, else the generation count at which its best cost fell below stop_cost;
+ *   from then on nothing of that frame's swarm changes (its particles are not evaluated). */
 typedef struct {
   int32_t n_frames, n_particles;
   const int32_t* frame_slots;
@@ -179,19 +182,24 @@ typedef struct {
   int32_t* gen;
   const float *init_lo, *init_hi;
   uint64_t seed;
+  int32_t* stop_gen;
 } ht_swarm;
 
 /* Swarm constants.  Plain PSO of the paper: c1 = 2.8, c2 = 1.3, w = 2/|2 - psi -
  * sqrt(psi^2 - 4 psi)| (psi = c1 + c2), mutate_every = 3, mutate_frac = 0.5.  refine_topk > 0
  * adds gradient refinement (not in the paper) of the refine_topk lowest-cost particles:
  * refine_steps normalised steepest-descent steps in the eta-scaled space (eta_rot rad for
- * angles, eta_trans mm for translations), halving the step up to 3 times until E drops. */
+ * angles, eta_trans mm for translations), halving the step up to 3 times until E drops.
+ * stop_cost > 0: the stop rule of section III.B (the paper stops at E < 1.0): after a
+ * generation's evaluation, a frame whose best cost is below stop_cost keeps its personal and
+ * global bests of that generation and stops (swarm.stop_gen must then be set); 0: never. */
 typedef struct {
   float w, c1, c2;
   int32_t mutate_every;
   float mutate_frac;
   int32_t refine_topk, refine_steps;
   float eta_rot, eta_trans;
+  float stop_cost;
 } ht_pso_params;
 
 /* Initialise: x ~ U[init_lo, init_hi] clamped to the joint limits (Philox4x32-10, stream 1),
@@ -213,6 +221,16 @@ ht_status ht_pso_step(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_params* p
  * hip_stream.  Requires ht_reserve to cover the swarm.  HT_ERR_HIP if capture fails. */
 ht_status ht_pso_run_graph(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_params* params,
                            int n_generations, void* hip_stream);
+
+/* Initial-position box for tracking (section II: a frame's search starts around the previous
+ * frame's solution): per frame f and pose parameter d, with c = center clamped to the model
+ * bounds, lo = max(c - halfwidth[d], bound_lo[d]) and hi = min(c + halfwidth[d],
+ * bound_hi[d]).  center: device float32 [n_frames][n_dof] (e.g. a swarm's gbest_x);
+ * halfwidth: device float32 [n_dof] (>= 0); lo, hi: device float32 [n_frames][n_dof] (e.g.
+ * the swarm's init_lo / init_hi, then ht_pso_init or ht_pso_run_graph).  Enqueue only;
+ * graph-capturable.  Errors: HT_ERR_ARG for NULL pointers or n_frames out of 0..2^22. */
+ht_status ht_pso_box_around(ht_ctx* ctx, int n_frames, const float* center,
+                            const float* halfwidth, float* lo, float* hi, void* hip_stream);
 
 /* Launch shape of the batched persistent ray-cast kernel.  tiles_per_item is shortened
  * automatically for launches too small to give every compute unit a work item. */

@@ -15,6 +15,14 @@ P (position and cost) and the global best G.  One generation, as read here:
     joint limits (Tables 1-2) is clamped to the limit and its velocity zeroed;
  5. the generation counter advances.
 
+Stop rule (section III.B stops at E < 1.0): with stop_cost > 0, a frame whose global best
+after step 2 is below stop_cost keeps that generation's personal and global bests, skips
+steps 3-4, records the generation count in ``stop_gen`` and is left unchanged afterwards.
+
+Tracking (section II: the observation is a video; each frame's search starts from the
+previous frame's solution): the initial box of frame t is c -/+ halfwidth clipped to the
+joint limits, with c the previous frame's global best clipped to the limits (``box_around``).
+
 The constriction factor of section III.B is w = 2 / |2 - psi - sqrt(psi^2 - 4 psi)| with
 psi = c1 + c2.  Random numbers come from ``philox`` (see its docstring for the counters).
 
@@ -44,6 +52,7 @@ class PsoParams:
     refine_steps: int = 0
     eta_rot: float = 0.02
     eta_trans: float = 2.0
+    stop_cost: float = 0.0
 
 
 def constriction(c1: float, c2: float) -> float:
@@ -65,6 +74,7 @@ def init_state(init_lo, init_hi, n_particles: int, seed: int) -> dict:
         "x": x, "v": np.zeros((F, P, D)), "pbest_x": x.copy(),
         "pbest_cost": np.full((F, P), np.inf), "gbest_x": x[:, 0].copy(),
         "gbest_cost": np.full(F, np.inf), "gen": np.zeros(F, np.int64),
+        "stop_gen": np.zeros(F, np.int64),
     }
 
 
@@ -83,7 +93,11 @@ def update(state: dict, costs, params: PsoParams, lo, hi, mutate_mask, seed: int
     lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
     mmask = np.asarray(mutate_mask).astype(bool)
     dims = np.arange(D)
+    if "stop_gen" not in s:
+        s["stop_gen"] = np.zeros(F, np.int64)
     for f in range(F):
+        if s["stop_gen"][f] != 0:
+            continue
         k = int(s["gen"][f])
         better = costs[f] < s["pbest_cost"][f]
         s["pbest_cost"][f][better] = costs[f][better]
@@ -91,6 +105,10 @@ def update(state: dict, costs, params: PsoParams, lo, hi, mutate_mask, seed: int
         g = int(np.argmin(s["pbest_cost"][f]))
         s["gbest_cost"][f] = s["pbest_cost"][f][g]
         s["gbest_x"][f] = s["pbest_x"][f][g]
+        if params.stop_cost > 0.0 and s["gbest_cost"][f] < params.stop_cost:
+            s["gen"][f] = k + 1
+            s["stop_gen"][f] = k + 1
+            continue
         gparts = f * P + np.arange(P)
         mutated = np.zeros(P, bool)
         if params.mutate_every > 0 and (k + 1) % params.mutate_every == 0:
@@ -150,6 +168,12 @@ def refine_particle(model, obs, x, E, params: PsoParams, lo, hi):
     return x, E
 
 
+def box_around(center, halfwidth, lo, hi):
+    """Initial box of a tracked frame: c -/+ halfwidth within [lo, hi], c = clip(center)."""
+    c = np.clip(np.asarray(center, np.float64), lo, hi)
+    return np.maximum(c - halfwidth, lo), np.minimum(c + halfwidth, hi)
+
+
 def run(model, obs, init_lo, init_hi, n_particles, n_generations, params: PsoParams, seed):
     """A whole single-frame PSO run (FP64, slow); returns (state, gbest cost per generation)."""
     lo, hi = model["bounds_lo"], model["bounds_hi"]
@@ -163,4 +187,6 @@ def run(model, obs, init_lo, init_hi, n_particles, n_generations, params: PsoPar
                                                          params, lo, hi)
         st = update(st, c, params, lo, hi, model["mutate_mask"], seed)
         history.append(float(st["gbest_cost"][0]))
+        if st["stop_gen"][0] != 0:
+            break
     return st, history

@@ -85,6 +85,26 @@ def make_frame(model: dict, cfg, frame: int) -> dict:
     return {"depth": depth, "skin": skin, "cam": cam, "bg": BACKGROUND_MM, "h_true": h}
 
 
+def make_sequence(model: dict, cfg) -> list[dict]:
+    """A tracked sequence: frame 0 as ``make_frame``; each later true pose is a random-walk
+    step (``workload.handmodel.pose_walk_step``) of the previous one, rendered and observed
+    with the same noise model."""
+    W, H = cfg.frame_roi(0)
+    cam = camera_for_roi(W, H, cfg.full_frame)
+    frames = [make_frame(model, cfg, 0)]
+    walk = np.random.default_rng(seed_sequence(cfg.idx, 3_000_000))
+    h = frames[0]["h_true"]
+    for t in range(1, cfg.n_frames):
+        h = handmodel.pose_walk_step(walk, h, model["kc_pairs"], model["bounds_lo"],
+                                     model["bounds_hi"], cfg.seq_step_deg, cfg.seq_step_mm)
+        res = raycast.render(model, h, W, H, cam, BACKGROUND_MM)
+        rng = np.random.default_rng(seed_sequence(cfg.idx, t, 2))
+        depth, skin = observe(res, rng, cfg.noise_sigma_mm, cfg.dropout_p, cfg.skin_flip_p)
+        frames.append({"depth": depth, "skin": skin, "cam": cam, "bg": BACKGROUND_MM,
+                       "h_true": h})
+    return frames
+
+
 def clean_observation(model: dict, h, W, H, cam, bg=BACKGROUND_MM) -> dict:
     """Noise-free, dropout-free, flip-free float64 observation of pose h (for pins)."""
     res = raycast.render(model, h, W, H, cam, bg)

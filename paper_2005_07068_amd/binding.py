@@ -52,7 +52,7 @@ class Swarm(C.Structure):
         ("x", C.c_void_p), ("v", C.c_void_p), ("pbest_x", C.c_void_p), ("pbest_cost", C.c_void_p),
         ("gbest_x", C.c_void_p), ("gbest_cost", C.c_void_p), ("cost", C.c_void_p),
         ("gen", C.c_void_p), ("init_lo", C.c_void_p), ("init_hi", C.c_void_p),
-        ("seed", C.c_uint64),
+        ("seed", C.c_uint64), ("stop_gen", C.c_void_p),
     ]
 
 
@@ -60,7 +60,7 @@ class PsoParams(C.Structure):
     _fields_ = [("w", C.c_float), ("c1", C.c_float), ("c2", C.c_float),
                 ("mutate_every", C.c_int32), ("mutate_frac", C.c_float),
                 ("refine_topk", C.c_int32), ("refine_steps", C.c_int32),
-                ("eta_rot", C.c_float), ("eta_trans", C.c_float)]
+                ("eta_rot", C.c_float), ("eta_trans", C.c_float), ("stop_cost", C.c_float)]
 
 
 class LaunchConfig(C.Structure):
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH):
     lib.ht_pso_init.argtypes = [P, C.POINTER(Swarm), P]
     lib.ht_pso_step.argtypes = [P, C.POINTER(Swarm), C.POINTER(PsoParams), P]
     lib.ht_pso_run_graph.argtypes = [P, C.POINTER(Swarm), C.POINTER(PsoParams), I, P]
+    lib.ht_pso_box_around.argtypes = [P, I, P, P, P, P, P]
     lib.ht_get_launch_config.argtypes = [P, C.POINTER(LaunchConfig)]
     lib.ht_set_launch_config.argtypes = [P, C.POINTER(LaunchConfig)]
     lib.ht_autotune.argtypes = [P, I, P, I, P, P, I, C.POINTER(LaunchConfig), P]
@@ -129,10 +130,15 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def torch_float32():
+    import torch
+    return torch.float32
+
+
 def pso_params(w=0.72, c1=2.05, c2=2.05, mutate_every=3, mutate_frac=0.5, refine_topk=0,
-               refine_steps=0, eta_rot=0.02, eta_trans=2.0) -> PsoParams:
+               refine_steps=0, eta_rot=0.02, eta_trans=2.0, stop_cost=0.0) -> PsoParams:
     return PsoParams(w, c1, c2, mutate_every, mutate_frac, refine_topk, refine_steps, eta_rot,
-                     eta_trans)
+                     eta_trans, stop_cost)
 
 
 def model_struct(m: dict):
@@ -274,11 +280,12 @@ class Context:
             "gen": torch.zeros((F,), device=dev, dtype=torch.int32),
             "init_lo": init_lo.to(dev, torch.float32).reshape(F, D).contiguous(),
             "init_hi": init_hi.to(dev, torch.float32).reshape(F, D).contiguous(),
+            "stop_gen": torch.zeros((F,), device=dev, dtype=torch.int32),
         }
         s = Swarm(F, n_particles, _ptr(t["frame_slots"]), _ptr(t["x"]), _ptr(t["v"]),
                   _ptr(t["pbest_x"]), _ptr(t["pbest_cost"]), _ptr(t["gbest_x"]),
                   _ptr(t["gbest_cost"]), _ptr(t["cost"]), _ptr(t["gen"]), _ptr(t["init_lo"]),
-                  _ptr(t["init_hi"]), C.c_uint64(seed))
+                  _ptr(t["init_hi"]), C.c_uint64(seed), _ptr(t["stop_gen"]))
         t["_struct"] = s
         return t
 
@@ -288,6 +295,19 @@ class Context:
     def pso_step(self, sw, params: PsoParams):
         _check(self.lib.ht_pso_step(self.handle, C.byref(sw["_struct"]), C.byref(params),
                                     _stream()))
+
+    def box_around(self, center, halfwidth, lo, hi):
+        """lo, hi <- the model-bounded box center -/+ halfwidth (all float32 cuda tensors:
+        center, lo, hi [F, n_dof]; halfwidth [n_dof])."""
+        F = int(center.shape[0]) if center.dim() == 2 else 1
+        for t in (center, halfwidth, lo, hi):
+            if not (t.is_cuda and t.dtype == torch_float32() and t.is_contiguous()):
+                raise ValueError("box_around takes contiguous float32 cuda tensors")
+        if halfwidth.numel() != self.n_dof or center.numel() != F * self.n_dof or \
+                lo.numel() != F * self.n_dof or hi.numel() != F * self.n_dof:
+            raise ValueError("box_around: shape mismatch")
+        _check(self.lib.ht_pso_box_around(self.handle, F, _ptr(center), _ptr(halfwidth), _ptr(lo),
+                                          _ptr(hi), _stream()))
 
     def pso_run_graph(self, sw, params: PsoParams, n_generations: int):
         _check(self.lib.ht_pso_run_graph(self.handle, C.byref(sw["_struct"]), C.byref(params),

@@ -228,7 +228,7 @@ namespace ht {
 // Evaluation shared by ht_eval_particles, ht_eval_particles_grad and the swarm step.
 ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_particles,
                     const float* poses, float* cost, float* grad, const uint8_t* pixel_mask,
-                    const ht_debug* dbg, hipStream_t s) {
+                    const ht_debug* dbg, hipStream_t s, const int32_t* frame_stop = nullptr) {
   const int n_total = n_frames * n_particles;
   if (n_total == 0) return HT_OK;
   ht_status st = ensure_workspace(c, n_total, c->max_tiles(), grad != nullptr, s);
@@ -243,6 +243,7 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.cost = cost;
   a.grad = grad;
   a.pixel_mask = pixel_mask;
+  a.frame_stop = frame_stop;
   if (dbg) {
     a.dbg = *dbg;
     const SlotHost& sh = c->slots[dbg->slot];
@@ -639,6 +640,10 @@ ht_status check_params(const ht_swarm* sw, const ht_pso_params* p) {
   if (p->refine_topk > 0 && p->refine_steps > 0 &&
       !(p->eta_rot > 0.0f && p->eta_trans > 0.0f && std::isfinite(p->eta_rot) && std::isfinite(p->eta_trans)))
     return fail(HT_ERR_ARG, "eta_rot and eta_trans must be positive");
+  if (!(p->stop_cost >= 0.0f && std::isfinite(p->stop_cost)))
+    return fail(HT_ERR_ARG, "stop_cost must be finite and >= 0");
+  if (p->stop_cost > 0.0f && !sw->stop_gen && sw->n_frames * sw->n_particles > 0)
+    return fail(HT_ERR_ARG, "stop_cost > 0 needs the swarm's stop_gen buffer");
   return HT_OK;
 }
 
@@ -670,7 +675,8 @@ ht_status ensure_refine(ht_ctx* c, int n_ref, hipStream_t s) {
 ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, hipStream_t s) {
   const int F = sw.n_frames, P = sw.n_particles, D = c->n_dof;
   if (F * P == 0) return HT_OK;
-  ht_status st = ht::eval_impl(c, F, sw.frame_slots, P, sw.x, sw.cost, nullptr, nullptr, nullptr, s);
+  ht_status st = ht::eval_impl(c, F, sw.frame_slots, P, sw.x, sw.cost, nullptr, nullptr, nullptr, s,
+                               sw.stop_gen);
   if (st != HT_OK) return st;
   const int K = p.refine_topk;
   if (K > 0 && p.refine_steps > 0) {
@@ -678,12 +684,13 @@ ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, h
     if ((st = ensure_refine(c, n_ref, s)) != HT_OK) return st;
     HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_select(sw, K, D, c->r_sel, c->r_x, c->r_cost, c->r_active, s); }));
     for (int step = 0; step < p.refine_steps; ++step) {
-      st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s);
+      st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s,
+                         sw.stop_gen);
       if (st != HT_OK) return st;
       HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_propose(c->d_model, n_ref, D, p.eta_rot, p.eta_trans, c->r_x,
                                        c->r_grad, c->r_active, c->r_cand, s); }));
       st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, nullptr, nullptr,
-                         nullptr, s);
+                         nullptr, s, sw.stop_gen);
       if (st != HT_OK) return st;
       HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_accept(n_ref, D, c->r_x, c->r_cost, c->r_cand, c->r_ccost,
                                       c->r_active, s); }));
@@ -716,6 +723,20 @@ ht_status ht_pso_init(ht_ctx* c, const ht_swarm* sw, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HT_HIP(traced(c, HT_K_PSO, sw->n_frames * sw->n_particles, s,
                 [&] { return ht::launch_pso_init(c->d_model, *sw, c->n_dof, s); }));
+  return HT_OK;
+}
+
+ht_status ht_pso_box_around(ht_ctx* c, int n_frames, const float* center, const float* halfwidth,
+                            float* lo, float* hi, void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if (n_frames < 0 || n_frames > (1 << 22)) return fail(HT_ERR_ARG, "n_frames %d out of range", n_frames);
+  if (n_frames == 0) return HT_OK;
+  if (!center || !halfwidth || !lo || !hi) return fail(HT_ERR_ARG, "box buffer is NULL");
+  DeviceGuard g(c->device);
+  HT_HIP(ht::launch_box_around(c->d_model, n_frames, c->n_dof, center, halfwidth, lo, hi,
+                               (hipStream_t)stream));
   return HT_OK;
 }
 

@@ -87,7 +87,8 @@ struct PInfo {
   int slot;                   // observation slot (-1: unset slot)
   float kc;                   // collision term of Eq. 5
   int valid;                  // 0: non-finite pose or unset slot
-  int pad[2];
+  int skip;                   // 1: the particle's frame has stopped: nothing is written
+  int pad;
 };
 
 struct Partial {
@@ -121,6 +122,7 @@ struct EvalArgs {
   float* cost;
   float* grad;                 // NULL for forward only
   const uint8_t* pixel_mask;   // gradient mask of frame 0, may be NULL
+  const int* frame_stop;       // [n_frames] stop flags of a swarm, may be NULL
   ht_debug dbg;                // pointers may be NULL
   int dbg_W, dbg_H;
   float dbg_bg;
@@ -138,6 +140,8 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
 enum { kStageFk = 0, kStageSched = 1, kStageRaycast = 2, kStageFinalize = 3, kNumStages = 4 };
 hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s);
 hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s);
+hipError_t launch_box_around(const DevModel* model, int n_frames, int n_dof, const float* center,
+                             const float* halfwidth, float* lo, float* hi, hipStream_t s);
 hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht_pso_params& p,
                              int n_dof, int* flags, hipStream_t s);
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,

@@ -303,7 +303,9 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   int slot = -1;
   if (active) slot = a.frame_slots[p / a.n_particles];
   const bool slot_ok = active && slot >= 0 && slot < HT_MAX_SLOTS && a.slots[slot].set;
-  const bool valid = slot_ok && finite;
+  // a particle of a stopped frame (tracking stop rule) is neither cast nor written
+  const bool skip = active && a.frame_stop && a.frame_stop[p / a.n_particles] != 0;
+  const bool valid = slot_ok && finite && !skip;
   __syncthreads();
 
   // segment transforms: every lane composes its own segment's chain (the ancestors' local
@@ -587,6 +589,7 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
     PInfo pi{};
     pi.slot = slot_ok ? slot : -1;
     pi.valid = valid ? 1 : 0;
+    pi.skip = skip ? 1 : 0;
     double kc = 0.0;
     if (valid)
       for (int i = 0; i < M.n_kc; ++i) kc += s_kc[w][i];
@@ -1219,6 +1222,7 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace 
   const int n_total = a.n_frames * a.n_particles;
   if (p >= n_total) return;
   const PInfo pi = ws.pinfo[p];
+  if (pi.skip) return;
   a.cost[p] = pi.valid ? assemble_cost(a, ws, pi, p, nullptr) : (pi.slot < 0 ? NAN : INFINITY);
 }
 
@@ -1234,6 +1238,7 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   const int p = blockIdx.x, t = threadIdx.x;
   const PInfo pi = ws.pinfo[p];
   const int n_dof = a.n_dof, n_seg = a.n_seg;
+  if (pi.skip) return;
   if (!pi.valid) {
     if (t == 0) a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
     for (int j = t; j < n_dof; j += kBlock) a.grad[(size_t)p * n_dof + j] = 0.0f;

@@ -43,7 +43,9 @@ __device__ __forceinline__ uint4 draw(uint64_t seed, int dim, int gpart, int gen
 
 __device__ __forceinline__ float cost_key(float c) { return isnan(c) ? INFINITY : c; }
 
-constexpr int kFlagImproved = 1, kFlagMutated = 2;
+// per-particle flags from part 1 to part 2 of a generation: personal best improved, mutated,
+// the frame stopped in this generation (bests kept, no move), the frame had stopped before
+constexpr int kFlagImproved = 1, kFlagMutated = 2, kFlagStop = 4, kFlagFrozen = 8;
 constexpr int kPsoBlock = 1024;
 
 int threads_for(int n) { return n >= kPsoBlock ? kPsoBlock : ((n + kWave - 1) / kWave) * kWave; }
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(kBlock) void pso_init_kernel(const DevModel* __rest
       if (gp % P == 0) {
         sw.gbest_cost[f] = INFINITY;
         sw.gen[f] = 0;
+        if (sw.stop_gen) sw.stop_gen[f] = 0;
       }
     }
   }
@@ -122,6 +125,30 @@ hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof,
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(pso_init_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, s, model, sw, n_dof);
+  return hipGetLastError();
+}
+
+// tracking box: clamp(center) -/+ halfwidth within the model bounds, one thread per entry
+__global__ __launch_bounds__(kBlock) void box_around_kernel(const DevModel* __restrict__ M,
+                                                            int n, int n_dof,
+                                                            const float* __restrict__ center,
+                                                            const float* __restrict__ hw,
+                                                            float* __restrict__ lo,
+                                                            float* __restrict__ hi) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int d = i % n_dof;
+  const float c = fminf(fmaxf(center[i], M->lo[d]), M->hi[d]);
+  lo[i] = fmaxf(c - hw[d], M->lo[d]);
+  hi[i] = fminf(c + hw[d], M->hi[d]);
+}
+
+hipError_t launch_box_around(const DevModel* model, int n_frames, int n_dof, const float* center,
+                             const float* halfwidth, float* lo, float* hi, hipStream_t s) {
+  const int n = n_frames * n_dof;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(box_around_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     model, n, n_dof, center, halfwidth, lo, hi);
   return hipGetLastError();
 }
 
@@ -143,6 +170,10 @@ __global__ __launch_bounds__(kPsoBlock) void pso_best_kernel(ht_swarm sw, ht_pso
   const int lane = tid & (kWave - 1), wv = tid / kWave;
   const int gen = sw.gen[f];
   const size_t base = (size_t)f * P;
+  if (sw.stop_gen && sw.stop_gen[f] != 0) {   // stopped earlier: nothing changes
+    for (int i = tid; i < P; i += blockDim.x) flags[base + i] = kFlagFrozen;
+    return;
+  }
 
   for (int i = tid; i < P; i += blockDim.x) {
     const float c = cost_key(sw.cost[base + i]);
@@ -204,15 +235,22 @@ __global__ __launch_bounds__(kPsoBlock) void pso_best_kernel(ht_swarm sw, ht_pso
     sw.gbest_x[(size_t)f * n_dof + d] =
         g_improved ? sw.x[(base + g) * n_dof + d] : sw.pbest_x[(base + g) * n_dof + d];
 
+  // stop rule: the best cost is below the threshold after this generation's evaluation
+  const bool stop = sw.stop_gen && prm.stop_cost > 0.0f && s_pb[g] < prm.stop_cost;
   const bool mutate_gen = prm.mutate_every > 0 && (gen + 1) % prm.mutate_every == 0;
   const int n_mut = (int)floorf((float)P * prm.mutate_frac);
-  if (mutate_gen && n_mut > 0) {
+  if (stop) {
+    for (int i = tid; i < P; i += blockDim.x) flags[base + i] |= kFlagStop;
+  } else if (mutate_gen && n_mut > 0) {
     // the worst n_mut by current cost are the last positions of the ascending sort
     sort_costs(sw.cost + base, P, n_pad, s_key, s_idx);
     for (int r = P - n_mut + tid; r < P; r += blockDim.x) flags[base + s_idx[r]] |= kFlagMutated;
   }
   __syncthreads();
-  if (tid == 0) sw.gen[f] = gen + 1;
+  if (tid == 0) {
+    sw.gen[f] = gen + 1;
+    if (stop) sw.stop_gen[f] = gen + 1;
+  }
 }
 
 // generation update, part 2: one thread per (frame, particle, dimension)
@@ -228,12 +266,14 @@ __global__ __launch_bounds__(kBlock) void pso_move_kernel(const DevModel* __rest
   const int f = gp / P;
   const int gen = sw.gen[f] - 1;            // part 1 already advanced the counter
   const int fl = flags[gp];
+  if (fl & kFlagFrozen) return;
   const float xd = sw.x[i];
   float pb = sw.pbest_x[i];
   if (fl & kFlagImproved) {
     pb = xd;
     sw.pbest_x[i] = xd;
   }
+  if (fl & kFlagStop) return;
   const float lo = M->lo[d], hi = M->hi[d];
   if (fl & kFlagMutated) {
     if (M->mutate[d]) {
@@ -366,6 +406,7 @@ __global__ __launch_bounds__(kBlock) void refine_gather_kernel(ht_swarm sw, int 
   if (e >= (size_t)sw.n_frames * K * n_dof) return;
   const int r = (int)(e / n_dof), d = (int)(e % n_dof);
   const int f = r / K;
+  if (sw.stop_gen && sw.stop_gen[f] != 0) return;
   const size_t gp = (size_t)f * sw.n_particles + sel[r];
   sw.x[gp * n_dof + d] = rx[e];
   if (d == 0) sw.cost[gp] = rcost[r];

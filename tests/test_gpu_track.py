@@ -1,0 +1,119 @@
+"""GPU checks of tracking (search box around the previous frame's best) and of the stop
+rule of section III.B, through the C ABI."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import paper_2005_07068_amd as ht
+from gpu_util import frame_for, make_ctx, torch_cuda
+from oracle import synth
+from workload import CONFIGS, make_hand_model, seed_sequence
+from workload.handmodel import init_halfwidth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_box_around_matches_float32_formula():
+    torch = torch_cuda()
+    model = make_hand_model(seed_sequence(1, 10_000))
+    ctx = make_ctx(model, [])
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(3)
+    F, D = 5, 26
+    lo_b = model["bounds_lo"].astype(np.float32)
+    hi_b = model["bounds_hi"].astype(np.float32)
+    center = (lo_b + rng.uniform(-0.3, 1.3, (F, D)) * (hi_b - lo_b)).astype(np.float32)
+    hw = init_halfwidth(D, 10.0, 20.0).astype(np.float32)
+    lo = torch.empty((F, D), device=dev)
+    hi = torch.empty((F, D), device=dev)
+    ctx.box_around(torch.tensor(center, device=dev), torch.tensor(hw, device=dev), lo, hi)
+    c = np.minimum(np.maximum(center, lo_b), hi_b)
+    assert np.array_equal(lo.cpu().numpy(), np.maximum(c - hw, lo_b))
+    assert np.array_equal(hi.cpu().numpy(), np.minimum(c + hw, hi_b))
+
+
+def _two_frame_swarm(ctx, model, frames, dev, seed=41):
+    import torch
+    h = np.stack([fr["h_true"] for fr in frames])
+    d = init_halfwidth(model["n_dof"], 10.0, 20.0)
+    slots = torch.arange(len(frames), dtype=torch.int32, device=dev)
+    return ctx.swarm(slots, 32, torch.tensor(h - d, dtype=torch.float32),
+                     torch.tensor(h + d, dtype=torch.float32), seed=seed)
+
+
+def test_stop_rule_freezes_only_the_frame_below_the_threshold():
+    torch = torch_cuda()
+    dev = torch.device("cuda:0")
+    cfg, model, fr0 = frame_for(3, 0)
+    _, _, fr1 = frame_for(3, 1)
+    ctx = make_ctx(model, [fr0, fr1])
+    ctx.reserve(64, max(fr0["depth"].size, fr1["depth"].size))
+    sw = _two_frame_swarm(ctx, model, [fr0, fr1], dev)
+    ctx.pso_init(sw)
+    x0 = sw["x"].clone()
+    ctx.pso_step(sw, ht.pso_params())
+    g1 = sw["gbest_cost"].cpu().numpy()
+    pb1 = sw["pbest_cost"].clone()
+    a = int(np.argmin(g1))                      # the frame that will stop
+    b = 1 - a
+    stop_cost = float(g1[a]) + 1e-3 * float(g1[b] - g1[a])
+    assert g1[a] < stop_cost < g1[b]
+    params = ht.pso_params(stop_cost=stop_cost)
+    # eager generations
+    ctx.pso_init(sw)
+    for _ in range(5):
+        ctx.pso_step(sw, params)
+    eager = {k: sw[k].clone() for k in ("x", "v", "pbest_x", "pbest_cost", "gbest_x",
+                                        "gbest_cost", "gen", "stop_gen")}
+    st = {k: v.cpu().numpy() for k, v in eager.items()}
+    assert st["stop_gen"][a] == 1 and st["gen"][a] == 1
+    # the other frame runs until it also falls below the threshold, if it does
+    if st["stop_gen"][b] == 0:
+        assert st["gen"][b] == 5
+    else:
+        assert 1 < st["stop_gen"][b] == st["gen"][b] and st["gbest_cost"][b] < stop_cost
+    # the stopped frame kept generation 1's bests and never moved
+    assert np.array_equal(st["x"][a], x0[a].cpu().numpy())
+    assert np.array_equal(st["pbest_cost"][a], pb1[a].cpu().numpy())
+    assert st["gbest_cost"][a] == g1[a]
+    assert np.array_equal(st["v"][a], np.zeros_like(st["v"][a]))
+    # the other frame ran on
+    assert not np.array_equal(st["x"][b], x0[b].cpu().numpy())
+    # a graph replay of the same run is identical
+    ctx.pso_run_graph(sw, params, 5)
+    torch.cuda.synchronize()
+    for k, v in eager.items():
+        assert torch.equal(sw[k], v), k
+
+
+def test_tracking_a_moving_hand():
+    torch = torch_cuda()
+    dev = torch.device("cuda:0")
+    cfg = dataclasses.replace(CONFIGS[6], idx=61, n_frames=6, roi=(128, 128))
+    model = make_hand_model(seed_sequence(61, 10_000))
+    frames = synth.make_sequence(model, cfg)
+    ctx = make_ctx(model, frames)
+    ctx.reserve(64, 128 * 128)
+    D = model["n_dof"]
+    hw_np = init_halfwidth(D, 10.0, 20.0).astype(np.float32)
+    hw = torch.tensor(hw_np, device=dev)
+    h0 = torch.tensor(frames[0]["h_true"][None], dtype=torch.float32, device=dev)
+    sw = ctx.swarm(torch.zeros(1, dtype=torch.int32, device=dev), 64, h0.cpu(), h0.cpu(),
+                   seed=7)
+    params = ht.pso_params(w=0.7298, c1=2.8, c2=1.3)
+    center = h0
+    lo_b = model["bounds_lo"].astype(np.float32)
+    hi_b = model["bounds_hi"].astype(np.float32)
+    errs = []
+    for t, fr in enumerate(frames):
+        sw["frame_slots"].fill_(t)
+        ctx.box_around(center, hw, sw["init_lo"], sw["init_hi"])
+        c = np.minimum(np.maximum(center.cpu().numpy(), lo_b), hi_b)
+        assert np.array_equal(sw["init_lo"].cpu().numpy(), np.maximum(c - hw_np, lo_b))
+        ctx.pso_run_graph(sw, params, 20)
+        center = sw["gbest_x"].clone()
+        est = center.cpu().numpy()[0].astype(np.float64)
+        errs.append(np.degrees(np.mean(np.abs(est[:20] - fr["h_true"][:20]))))
+    print("tracking errors (deg)", np.round(errs, 2))
+    assert np.mean(errs) < 8.0 and max(errs) < 12.0

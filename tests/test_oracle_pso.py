@@ -104,3 +104,54 @@ def test_sphere_function_converges_and_gbest_monotone():
         hist.append(st["gbest_cost"][0])
     assert np.all(np.diff(hist) <= 0.0)
     assert hist[0] > 10.0 and hist[-1] < 1e-3
+
+
+def test_stop_rule_keeps_bests_and_freezes_the_frame():
+    """Section III.B stop rule: the generation whose global best falls below the threshold
+    records its personal / global bests, moves nobody, and nothing changes afterwards; a frame
+    above the threshold runs on."""
+    rng = np.random.default_rng(4)
+    F, P, D = 2, 6, 5
+    st = _state(F, P, D, rng)
+    lo, hi = np.full(D, -1.0), np.full(D, 1.0)
+    c = np.array([[0.5, 0.2, 0.9, 0.4, 0.3, 0.8], [5.0, 6.0, 7.0, 8.0, 9.0, 4.0]])
+    p = pso.PsoParams(w=0.7, c1=1.5, c2=1.5, mutate_every=1, stop_cost=1.0)
+    s1 = pso.update(st, c, p, lo, hi, np.ones(D), seed=1)
+    # frame 0 stopped in generation 1: bests recorded, positions and velocities untouched
+    assert s1["stop_gen"][0] == 1 and s1["gen"][0] == 1
+    assert s1["gbest_cost"][0] == 0.2 and np.array_equal(s1["gbest_x"][0], st["x"][0, 1])
+    assert np.array_equal(s1["pbest_cost"][0], c[0])
+    assert np.array_equal(s1["x"][0], st["x"][0]) and np.array_equal(s1["v"][0], st["v"][0])
+    # frame 1 is above the threshold: it moved
+    assert s1["stop_gen"][1] == 0 and not np.array_equal(s1["x"][1], st["x"][1])
+    # a later generation leaves frame 0 exactly as it was, even with better costs
+    s2 = pso.update(s1, np.zeros((F, P)), p, lo, hi, np.ones(D), seed=1)
+    for k in ("x", "v", "pbest_x", "pbest_cost"):
+        assert np.array_equal(s2[k][0], s1[k][0])
+    assert s2["gbest_cost"][0] == 0.2 and s2["gen"][0] == 1
+    # and frame 1 now stops (cost 0 < 1)
+    assert s2["stop_gen"][1] == 2
+
+
+def test_tracking_box_and_moving_minimum():
+    """The tracking box is c -/+ halfwidth inside the limits with c the clipped previous best;
+    tracking a drifting quadratic minimum stays close to it in every frame."""
+    lo, hi = np.array([-1.0, 0.0, 5.0]), np.array([1.0, 2.0, 9.0])
+    a, b = pso.box_around(np.array([0.9, -3.0, 7.0]), np.array([0.5, 0.5, 10.0]), lo, hi)
+    assert np.array_equal(a, [0.4, 0.0, 5.0]) and np.array_equal(b, [1.0, 0.5, 9.0])
+    D, P = 6, 32
+    lo, hi = np.full(D, -10.0), np.full(D, 10.0)
+    hw = np.full(D, 1.0)
+    rng = np.random.default_rng(2)
+    target = rng.uniform(-2, 2, D)
+    center = target.copy()
+    p = pso.PsoParams(w=pso.constriction(2.8, 1.3), c1=2.8, c2=1.3, mutate_every=0)
+    for t in range(8):
+        target = target + 0.3 * rng.uniform(-1, 1, D)          # the minimum drifts
+        bl, bh = pso.box_around(center, hw, lo, hi)
+        st = pso.init_state(bl[None], bh[None], P, seed=10 + t)
+        for _ in range(40):
+            c = np.sum((st["x"] - target) ** 2, axis=2)
+            st = pso.update(st, c, p, lo, hi, np.zeros(D), seed=10 + t)
+        center = st["gbest_x"][0]
+        assert np.max(np.abs(center - target)) < 0.05

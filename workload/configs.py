@@ -1,4 +1,4 @@
-"""The five synthetic workloads and their seed / camera recipes (data only).
+"""The synthetic workloads and their seed / camera recipes (data only).
 
 Camera: pinhole with fx = fy = f, principal point at the ROI centre ((W-1)/2, (H-1)/2), so
 pixel ray directions (u - cx, v - cy, f) are exact binary fractions; f = 2.25 * min(W, H)
@@ -43,6 +43,12 @@ class WorkloadConfig:
     init_angle_deg: float = 10.0
     init_trans_mm: float = 20.0
     hand_x_mm: tuple[float, ...] = field(default=(0.0,))
+    primitive_set: str = "cylinders"     # or "paper" (section II.A: cones, elliptic palm)
+    # a tracked sequence (frames are consecutive video frames of one moving hand) instead of
+    # independent frames; per-frame random-walk steps of the true pose
+    sequence: bool = False
+    seq_step_deg: float = 3.0
+    seq_step_mm: float = 4.0
     # observation noise model
     noise_sigma_mm: float = 2.0
     dropout_p: float = 0.05
@@ -65,4 +71,12 @@ CONFIGS = {
     4: WorkloadConfig(4, "hybrid640x480", 1, (640, 480), n_hands=2, n_particles=1024,
                       n_generations=20, full_frame=True, refine_topk=32, refine_steps=3,
                       hand_x_mm=(-120.0, 120.0)),
+    # a 30-frame tracked sequence (15 fps-like motion), one hand at 320x240, with the paper's
+    # swarm constants (c1 = 2.8, c2 = 1.3 and the constriction factor)
+    6: WorkloadConfig(6, "track320x240", 30, (320, 240), n_particles=64, n_generations=30,
+                      sequence=True, w=0.7298437881, c1=2.8, c2=1.3),
+    # workload 4 with the paper's own primitive set (38 per hand)
+    5: WorkloadConfig(5, "hybrid640x480_paper", 1, (640, 480), n_hands=2, n_particles=1024,
+                      n_generations=20, full_frame=True, refine_topk=32, refine_steps=3,
+                      hand_x_mm=(-120.0, 120.0), primitive_set="paper"),
 }

@@ -310,6 +310,19 @@ def perturbed_particles(rng: np.random.Generator, h_true, n: int, angle_deg: flo
     return a + rng.uniform(size=(n, h_true.size)) * (b - a)
 
 
+def pose_walk_step(rng: np.random.Generator, h, kc_pairs, lo, hi, step_deg: float,
+                   step_mm: float) -> np.ndarray:
+    """One step of a smooth random walk of a true pose (a tracked hand between two frames):
+    every angle moves by U(-step_deg, step_deg) degrees and every wrist translation by
+    U(-step_mm, step_mm) mm, within [lo, hi]; the abductions stay ordered (kc = 0)."""
+    h = np.asarray(h, np.float64)
+    delta = init_halfwidth(h.size, step_deg, step_mm)
+    out = np.clip(h + rng.uniform(-1.0, 1.0, h.size) * delta, lo, hi)
+    for a, b in kc_pairs:
+        out[b] = min(out[b], out[a])
+    return out
+
+
 def init_halfwidth(n_dof: int, angle_deg: float, trans_mm: float) -> np.ndarray:
     delta = np.full(n_dof, np.deg2rad(angle_deg))
     for hnd in range(n_dof // DOF_PER_HAND):

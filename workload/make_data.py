@@ -1,4 +1,4 @@
-"""Write the seeded synthetic observations of the five workloads to workload/data/*.npz.
+"""Write the seeded synthetic observations of the workloads to workload/data/*.npz.
 
 Every stored value comes from the CPU oracle: a seeded true pose per frame is rendered by the
 oracle and the noise model of the workloads is applied (the simulation protocol of section
@@ -29,11 +29,12 @@ def model_seed(idx: int):
 
 def make(idx: int, flop_samples: int = 8) -> str:
     cfg = CONFIGS[idx]
-    model = make_hand_model(model_seed(idx), cfg.n_hands)
+    model = make_hand_model(model_seed(idx), cfg.n_hands, cfg.primitive_set)
     out = {}
     cams, hs = [], []
+    seq = synth.make_sequence(model, cfg) if cfg.sequence else None
     for f in range(cfg.n_frames):
-        fr = synth.make_frame(model, cfg, f)
+        fr = seq[f] if seq is not None else synth.make_frame(model, cfg, f)
         out[f"depth_{f}"] = fr["depth"]
         out[f"skin_{f}"] = fr["skin"]
         cams.append(fr["cam"])
