@@ -133,6 +133,32 @@ ht_status ht_set_observation(ht_ctx* ctx, int frame_slot, int W, int H, const ui
                              const uint8_t* skin, ht_camera cam, float bg_depth_mm,
                              int ptr_kind, void* hip_stream);
 
+/* Observation preprocessing (section II.B: the hand is extracted from the RGB-D frame by
+ * skin-colour detection and depth segmentation; the paper names no method, this is the
+ * library's, in exact integer arithmetic):
+ *   skin: Cb = 128 + ((-43 R - 85 G + 128 B + 128) >> 8), Cr = 128 + ((128 R - 107 G - 21 B
+ *         + 128) >> 8) (BT.601 chroma, >> = floor division by 256), skin iff cb_lo <= Cb <=
+ *         cb_hi and cr_lo <= Cr <= cr_hi;
+ *   band: z0 = the smallest defined depth (> 0) among skin pixels; in band iff
+ *         z0 <= depth <= z0 + band_mm;
+ *   out:  skin_out = skin and in band; depth_out = depth in band, 0 where depth is 0, else
+ *         bg_depth_mm (segmented away = background).  No skin pixel with a defined depth:
+ *         skin_out = 0 and every defined depth becomes bg_depth_mm.
+ * Defaults: cb 77..127, cr 133..173, band 150 mm.  rgb: device uint8 [H][W][3]; depth,
+ * depth_out: device uint16 [H][W]; skin_out: device uint8 [H][W]; the outputs may feed
+ * ht_set_observation (HT_PTR_DEVICE).  Enqueue only (graph-capturable once the context has
+ * run it once at this or a larger size: the first call may allocate a small scratch array).
+ * Errors: HT_ERR_ARG for NULL pointers, W or H outside 1..HT_MAX_ROI, a bad box or band. */
+typedef struct {
+  int32_t cb_lo, cb_hi, cr_lo, cr_hi;
+  int32_t band_mm;
+  float bg_depth_mm;
+} ht_seg_params;
+
+ht_status ht_preprocess_rgbd(ht_ctx* ctx, int W, int H, const uint8_t* rgb,
+                             const uint16_t* depth, const ht_seg_params* params,
+                             uint16_t* depth_out, uint8_t* skin_out, void* hip_stream);
+
 /* Pre-allocate the workspace for up to `max_particles` particles in total (all frames of one
  * call) over observations of up to `max_pixels` pixels each, so that later calls allocate
  * nothing (required for graph capture).  HT_ERR_OOM on failure. */

@@ -63,6 +63,11 @@ class PsoParams(C.Structure):
                 ("eta_rot", C.c_float), ("eta_trans", C.c_float), ("stop_cost", C.c_float)]
 
 
+class SegParams(C.Structure):
+    _fields_ = [("cb_lo", C.c_int32), ("cb_hi", C.c_int32), ("cr_lo", C.c_int32),
+                ("cr_hi", C.c_int32), ("band_mm", C.c_int32), ("bg_depth_mm", C.c_float)]
+
+
 class LaunchConfig(C.Structure):
     _fields_ = [("tiles_per_item", C.c_int32), ("groups_per_cu", C.c_int32), ("cull", C.c_int32)]
 
@@ -102,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.ht_pso_step.argtypes = [P, C.POINTER(Swarm), C.POINTER(PsoParams), P]
     lib.ht_pso_run_graph.argtypes = [P, C.POINTER(Swarm), C.POINTER(PsoParams), I, P]
     lib.ht_pso_box_around.argtypes = [P, I, P, P, P, P, P]
+    lib.ht_preprocess_rgbd.argtypes = [P, I, I, P, P, C.POINTER(SegParams), P, P, P]
     lib.ht_get_launch_config.argtypes = [P, C.POINTER(LaunchConfig)]
     lib.ht_set_launch_config.argtypes = [P, C.POINTER(LaunchConfig)]
     lib.ht_autotune.argtypes = [P, I, P, I, P, P, I, C.POINTER(LaunchConfig), P]
@@ -295,6 +301,25 @@ class Context:
     def pso_step(self, sw, params: PsoParams):
         _check(self.lib.ht_pso_step(self.handle, C.byref(sw["_struct"]), C.byref(params),
                                     _stream()))
+
+    def preprocess_rgbd(self, rgb, depth, bg_depth_mm: float, box=(77, 127, 133, 173),
+                        band_mm: int = 150):
+        """Skin-colour and depth segmentation of an RGB-D frame.  rgb: uint8 cuda tensor
+        [H, W, 3]; depth: 16-bit cuda tensor [H, W] holding the uint16 depths (torch.uint16,
+        or int16 with the same bits).  Returns (depth_out like depth, skin_out uint8)."""
+        import torch
+        if rgb.dim() != 3 or rgb.shape[2] != 3 or rgb.dtype != torch.uint8 or not rgb.is_cuda:
+            raise ValueError("rgb must be a uint8 cuda tensor [H, W, 3]")
+        H, W = int(rgb.shape[0]), int(rgb.shape[1])
+        if tuple(depth.shape) != (H, W) or depth.element_size() != 2 or not depth.is_cuda:
+            raise ValueError("depth must be a 16-bit cuda tensor [H, W]")
+        rgb, depth = rgb.contiguous(), depth.contiguous()
+        d_out = torch.empty((H, W), device=rgb.device, dtype=depth.dtype)
+        s_out = torch.empty((H, W), device=rgb.device, dtype=torch.uint8)
+        p = SegParams(*box, int(band_mm), float(bg_depth_mm))
+        _check(self.lib.ht_preprocess_rgbd(self.handle, W, H, _ptr(rgb), _ptr(depth), C.byref(p),
+                                           _ptr(d_out), _ptr(s_out), _stream()))
+        return d_out, s_out
 
     def box_around(self, center, halfwidth, lo, hi):
         """lo, hi <- the model-bounded box center -/+ halfwidth (all float32 cuda tensors:

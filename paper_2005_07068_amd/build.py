@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhandtrack.so")
-SOURCES = ["ht_api.cpp", "ht_kernels.hip", "ht_pso.hip"]
+SOURCES = ["ht_api.cpp", "ht_kernels.hip", "ht_pso.hip", "ht_preprocess.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

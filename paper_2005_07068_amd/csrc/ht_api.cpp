@@ -107,6 +107,8 @@ struct ht_ctx {
   int cap_ref = 0;
   int* pso_flags = nullptr;   // [cap_flags] per-particle improved / mutated flags
   int cap_flags = 0;
+  int* seg_partial = nullptr; // [cap_seg] per-block minima of the preprocessing
+  int cap_seg = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
   // tracing of eager launches
   struct ProfRec {
@@ -327,6 +329,7 @@ void ht_destroy(ht_ctx* c) {
   dfree(c->r_active);
   dfree(c->r_slots);
   dfree(c->pso_flags);
+  dfree(c->seg_partial);
   dfree(c->d_slots);
   dfree(c->d_model);
   delete c;
@@ -723,6 +726,32 @@ ht_status ht_pso_init(ht_ctx* c, const ht_swarm* sw, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HT_HIP(traced(c, HT_K_PSO, sw->n_frames * sw->n_particles, s,
                 [&] { return ht::launch_pso_init(c->d_model, *sw, c->n_dof, s); }));
+  return HT_OK;
+}
+
+ht_status ht_preprocess_rgbd(ht_ctx* c, int W, int H, const uint8_t* rgb, const uint16_t* depth,
+                             const ht_seg_params* p, uint16_t* depth_out, uint8_t* skin_out,
+                             void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c, false);
+  if (st != HT_OK) return st;
+  if (W < 1 || H < 1 || W > HT_MAX_ROI || H > HT_MAX_ROI)
+    return fail(HT_ERR_ARG, "W, H = %d, %d out of 1..%d", W, H, HT_MAX_ROI);
+  if (!rgb || !depth || !p || !depth_out || !skin_out) return fail(HT_ERR_ARG, "NULL buffer");
+  if (p->cb_lo > p->cb_hi || p->cr_lo > p->cr_hi || p->band_mm < 0 ||
+      !(p->bg_depth_mm >= 0.0f && p->bg_depth_mm <= 65535.0f))
+    return fail(HT_ERR_ARG, "bad segmentation parameters");
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = ht::preprocess_partials(W, H);
+  if (nb > c->cap_seg) {
+    if (capturing(s)) return fail(HT_ERR_STATE, "preprocessing scratch too small during capture");
+    HT_HIP(hipDeviceSynchronize());
+    dfree(c->seg_partial);
+    HT_HIP(hipMalloc(&c->seg_partial, (size_t)nb * sizeof(int)));
+    c->cap_seg = nb;
+  }
+  HT_HIP(ht::launch_preprocess(W, H, rgb, depth, *p, c->seg_partial, depth_out, skin_out, s));
   return HT_OK;
 }
 

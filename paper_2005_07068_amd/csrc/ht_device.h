@@ -140,6 +140,10 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
 enum { kStageFk = 0, kStageSched = 1, kStageRaycast = 2, kStageFinalize = 3, kNumStages = 4 };
 hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s);
 hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s);
+int preprocess_partials(int W, int H);
+hipError_t launch_preprocess(int W, int H, const uint8_t* rgb, const uint16_t* depth,
+                             const ht_seg_params& p, int* partial, uint16_t* depth_out,
+                             uint8_t* skin_out, hipStream_t s);
 hipError_t launch_box_around(const DevModel* model, int n_frames, int n_dof, const float* center,
                              const float* halfwidth, float* lo, float* hi, hipStream_t s);
 hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht_pso_params& p,
