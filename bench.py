@@ -91,7 +91,7 @@ def plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=8)
     ref_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, refine_topk=cfg.refine_topk,
                           refine_steps=cfg.refine_steps)
     P, G = cfg.n_particles, cfg.n_generations
-    per_gen = F * P + F * cfg.refine_steps * 5 * cfg.refine_topk
+    per_gen = F * P + F * cfg.refine_topk * (1 + 4 * cfg.refine_steps)
     out = {"plain": {"particles": 64, "generations": 30, "err": [], "ms": []},
            "refined": {"particles": P, "generations": G, "err": [], "ms": [],
                        "evals_to_plain_err": []}}
@@ -446,7 +446,8 @@ def main():
         tuned = {"tiles_per_item": tpi, "groups_per_cu": gpc, "cull": cull,
                  "source": "autotuner"}
 
-    evals_per_step = F * P * G + F * G * S * (K + 4 * K)
+    # per generation: the swarm, the refined particles' gradient, 4 candidates per step
+    evals_per_step = F * P * G + F * G * (K + 4 * K * S) if K else F * P * G
     log(f"launch shape {tuned}; capturing and warming up")
     for _ in range(args.warmup):
         ctx.pso_run_graph(sw, params, G)

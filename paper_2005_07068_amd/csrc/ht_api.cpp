@@ -101,6 +101,7 @@ struct ht_ctx {
   float* r_grad = nullptr;    // [cap_ref][n_dof]
   float* r_cand = nullptr;    // [4 * cap_ref][n_dof]
   float* r_ccost = nullptr;   // [4 * cap_ref]
+  float* r_cgrad = nullptr;   // [4 * cap_ref][n_dof] gradients of the candidates
   int* r_sel = nullptr;       // [cap_ref]
   int* r_active = nullptr;    // [cap_ref]
   int* r_slots = nullptr;     // [4 * cap_ref] frame slot of each refined particle
@@ -325,6 +326,7 @@ void ht_destroy(ht_ctx* c) {
   dfree(c->r_grad);
   dfree(c->r_cand);
   dfree(c->r_ccost);
+  dfree(c->r_cgrad);
   dfree(c->r_sel);
   dfree(c->r_active);
   dfree(c->r_slots);
@@ -660,6 +662,7 @@ ht_status ensure_refine(ht_ctx* c, int n_ref, hipStream_t s) {
   dfree(c->r_grad);
   dfree(c->r_cand);
   dfree(c->r_ccost);
+  dfree(c->r_cgrad);
   dfree(c->r_sel);
   dfree(c->r_active);
   const size_t D = c->n_dof;
@@ -668,6 +671,7 @@ ht_status ensure_refine(ht_ctx* c, int n_ref, hipStream_t s) {
   HT_HIP(hipMalloc(&c->r_grad, (size_t)n_ref * D * sizeof(float)));
   HT_HIP(hipMalloc(&c->r_cand, (size_t)4 * n_ref * D * sizeof(float)));
   HT_HIP(hipMalloc(&c->r_ccost, (size_t)4 * n_ref * sizeof(float)));
+  HT_HIP(hipMalloc(&c->r_cgrad, (size_t)4 * n_ref * D * sizeof(float)));
   HT_HIP(hipMalloc(&c->r_sel, (size_t)n_ref * sizeof(int)));
   HT_HIP(hipMalloc(&c->r_active, (size_t)n_ref * sizeof(int)));
   c->cap_ref = n_ref;
@@ -686,17 +690,21 @@ ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, h
     const int n_ref = F * K;
     if ((st = ensure_refine(c, n_ref, s)) != HT_OK) return st;
     HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_select(sw, K, D, c->r_sel, c->r_x, c->r_cost, c->r_active, s); }));
+    // the gradient at the start; afterwards each step's candidates are evaluated with their
+    // gradients (except in the last step), so the accepted candidate brings its own
+    st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s,
+                       sw.stop_gen);
+    if (st != HT_OK) return st;
     for (int step = 0; step < p.refine_steps; ++step) {
-      st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s,
-                         sw.stop_gen);
-      if (st != HT_OK) return st;
+      const bool last = step + 1 == p.refine_steps;
+      float* cgrad = last ? nullptr : c->r_cgrad;
       HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_propose(c->d_model, n_ref, D, p.eta_rot, p.eta_trans, c->r_x,
                                        c->r_grad, c->r_active, c->r_cand, s); }));
-      st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, nullptr, nullptr,
+      st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, cgrad, nullptr,
                          nullptr, s, sw.stop_gen);
       if (st != HT_OK) return st;
       HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_accept(n_ref, D, c->r_x, c->r_cost, c->r_cand, c->r_ccost,
-                                      c->r_active, s); }));
+                                      c->r_active, cgrad, c->r_grad, s); }));
     }
     HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_gather(sw, K, D, c->r_sel, c->r_x, c->r_cost, s); }));
   }

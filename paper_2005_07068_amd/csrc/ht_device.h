@@ -154,7 +154,8 @@ hipError_t launch_refine_propose(const DevModel* model, int n_ref, int n_dof, fl
                                  float eta_trans, const float* rx, const float* grad,
                                  const int* active, float* cand, hipStream_t s);
 hipError_t launch_refine_accept(int n_ref, int n_dof, float* rx, float* rcost, const float* cand,
-                                const float* ccost, int* active, hipStream_t s);
+                                const float* ccost, int* active, const float* cgrad,
+                                float* grad, hipStream_t s);
 hipError_t launch_refine_gather(const ht_swarm& sw, int K, int n_dof, const int* sel,
                                 const float* rx, const float* rcost, hipStream_t s);
 

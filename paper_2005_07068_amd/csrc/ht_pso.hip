@@ -377,12 +377,17 @@ __global__ __launch_bounds__(kBlock) void refine_propose_kernel(const DevModel* 
   }
 }
 
+// accept the longest of the four steps that lowers E (the first, in halving order); with
+// cgrad, the candidates' gradients were evaluated with their costs and the accepted one's
+// becomes the particle's gradient for the next step
 __global__ __launch_bounds__(kBlock) void refine_accept_kernel(int n_ref, int n_dof,
                                                                float* __restrict__ rx,
                                                                float* __restrict__ rcost,
                                                                const float* __restrict__ cand,
                                                                const float* __restrict__ ccost,
-                                                               int* __restrict__ active) {
+                                                               int* __restrict__ active,
+                                                               const float* __restrict__ cgrad,
+                                                               float* __restrict__ grad) {
   const int lane = threadIdx.x & (kWave - 1);
   const int r = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (r >= n_ref || !active[r]) return;
@@ -394,7 +399,11 @@ __global__ __launch_bounds__(kBlock) void refine_accept_kernel(int n_ref, int n_
     if (lane == 0) active[r] = 0;
     return;
   }
-  if (lane < n_dof) rx[(size_t)r * n_dof + lane] = cand[((size_t)r * 4 + pick) * n_dof + lane];
+  const size_t src = ((size_t)r * 4 + pick) * n_dof + lane;
+  if (lane < n_dof) {
+    rx[(size_t)r * n_dof + lane] = cand[src];
+    if (cgrad) grad[(size_t)r * n_dof + lane] = cgrad[src];
+  }
   if (lane == 0) rcost[r] = ccost[(size_t)r * 4 + pick];
 }
 
@@ -430,9 +439,11 @@ hipError_t launch_refine_propose(const DevModel* model, int n_ref, int n_dof, fl
 }
 
 hipError_t launch_refine_accept(int n_ref, int n_dof, float* rx, float* rcost, const float* cand,
-                                const float* ccost, int* active, hipStream_t s) {
+                                const float* ccost, int* active, const float* cgrad,
+                                float* grad, hipStream_t s) {
   hipLaunchKernelGGL(refine_accept_kernel, dim3((n_ref + kWavesPerBlock - 1) / kWavesPerBlock),
-                     dim3(kBlock), 0, s, n_ref, n_dof, rx, rcost, cand, ccost, active);
+                     dim3(kBlock), 0, s, n_ref, n_dof, rx, rcost, cand, ccost, active, cgrad,
+                     grad);
   return hipGetLastError();
 }
 
