@@ -39,6 +39,35 @@ __device__ __forceinline__ int wave_sum(int v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
+// Wavefront total on the vector unit: DPP moves within each 16-lane row (quad permutations,
+// then row rotations by 4 and 8), then the four row sums read from lanes 0, 16, 32, 48 and
+// added in a fixed order.  Deterministic; the result is wave-uniform.  (__shfl_xor lowers to
+// ds_bpermute, an LDS round trip per step.)
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float wave_total(float v) {
+  v += __int_as_float(dpp<0xB1>(__float_as_int(v)));    // quad_perm [1, 0, 3, 2]
+  v += __int_as_float(dpp<0x4E>(__float_as_int(v)));    // quad_perm [2, 3, 0, 1]
+  v += __int_as_float(dpp<0x124>(__float_as_int(v)));   // row_ror:4
+  v += __int_as_float(dpp<0x128>(__float_as_int(v)));   // row_ror:8
+  const int b = __float_as_int(v);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(b, 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(b, 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(b, 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(b, 48));
+  return (r0 + r1) + (r2 + r3);
+}
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  int x = (int)v;
+  x |= dpp<0xB1>(x);
+  x |= dpp<0x4E>(x);
+  x |= dpp<0x124>(x);
+  x |= dpp<0x128>(x);
+  return (uint32_t)(__builtin_amdgcn_readlane(x, 0) | __builtin_amdgcn_readlane(x, 16) |
+                    __builtin_amdgcn_readlane(x, 32) | __builtin_amdgcn_readlane(x, 48));
+}
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
@@ -1144,19 +1173,19 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
         }
         const float fx = kap * wnx, fy = kap * wny, fz = kap * wnz;
         // segments present in this tile, reduced one at a time (uniform loop)
-        uint32_t segmask = act ? (1u << seg) : 0u;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) segmask |= (uint32_t)__shfl_xor((int)segmask, o);
+        uint32_t segmask = wave_or(act ? (1u << seg) : 0u);
         while (segmask) {
           const int s = __builtin_ctz(segmask);
           segmask &= segmask - 1;
           const bool mine = seg == s;
           const float vals[6] = {mine ? mx : 0.f, mine ? my : 0.f, mine ? mz : 0.f,
                                  mine ? fx : 0.f, mine ? fy : 0.f, mine ? fz : 0.f};
+          float sum[6];
 #pragma unroll
-          for (int q = 0; q < 6; ++q) {
-            const float sum = wave_sum(vals[q]);
-            if (lane == 0) s_wr[wave][s][q] += sum;
+          for (int q = 0; q < 6; ++q) sum[q] = wave_total(vals[q]);
+          if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s_wr[wave][s][q] += sum[q];
           }
         }
       }
