@@ -1038,11 +1038,21 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
   FrameSlot fs{};
   const PInfo& pi = s_pi;
 
+  // the first item of every workgroup is its own index; later ones come from the dequeue
+  // counter (offset by the grid size), so the launch does not start with one atomic per
+  // workgroup on a single address (which stalls the memory channel that holds it)
+  bool first = true;
   for (;;) {
-    if (tid == 0) s_item = atomicAdd(&ws.counters[0], 1);
-    __syncthreads();
-    const int item = uni(s_item);
-    __syncthreads();
+    int item;
+    if (first) {
+      item = blockIdx.x;
+      first = false;
+    } else {
+      if (tid == 0) s_item = (int)gridDim.x + atomicAdd(&ws.counters[0], 1);
+      __syncthreads();
+      item = uni(s_item);
+      __syncthreads();
+    }
     if (item >= total) break;
     const int p = uni(ws.item_map[item]);
     if (p != cur_p) {
