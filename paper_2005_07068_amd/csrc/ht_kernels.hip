@@ -1231,38 +1231,56 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 // ------------------------------------------------------------------------------------
 // finalize: combine partials in item order, Eq. 4-5, and the kinematic adjoint
 
-// Eq. 4-5 from the particle's partials, summed in item order (FP64).
-__device__ inline float assemble_cost(const EvalArgs& a, const Workspace& ws, const PInfo& pi,
-                                      int p, long long* s_or_out) {
-  const FrameSlot& fs = a.slots[pi.slot];
-  double S_d = fs.totals[0];
-  long long S_and = 0, S_or = (long long)fs.totals[1];
-  const int b = ws.item_off[p], e = b + pi.n_items;
-  for (int i = b; i < e; ++i) {
+// S_d, S_and, S_or of a particle: the ROI's background totals plus its items' partials,
+// summed by the lanes of one wavefront.  Every depth term is a multiple of 2^-15 mm, so the
+// FP64 sums are exact and equal to any other summation order.
+__device__ inline void wave_partial_sums(const FrameSlot& fs, const Workspace& ws, int b, int e,
+                                         int lane, double& S_d, long long& S_and,
+                                         long long& S_or) {
+  double d = 0.0;
+  int sa = 0, so = 0;
+  for (int i = b + lane; i < e; i += kWave) {
     const Partial pr = ws.partial[i];
-    S_d += pr.td;
-    S_and += pr.a;
-    S_or += pr.o;
+    d += pr.td;
+    sa += pr.a;
+    so += pr.o;
   }
+  d = wave_sum(d);
+  sa = wave_sum(sa);
+  so = wave_sum(so);
+  S_d = fs.totals[0] + d;
+  S_and = sa;
+  S_or = (long long)fs.totals[1] + so;
+}
+
+// Eq. 4-5 from the sums (FP64).
+__device__ inline float cost_from_sums(double S_d, long long S_and, long long S_or, float kc) {
   double D;
   if (S_or == 0) {
     D = kLambda;
   } else {
-    D = S_d / (double)S_or +
-        kLambda * (1.0 - 2.0 * (double)S_and / (double)(S_and + S_or));
+    D = S_d / (double)S_or + kLambda * (1.0 - 2.0 * (double)S_and / (double)(S_and + S_or));
   }
-  if (s_or_out) *s_or_out = S_or;
-  return (float)(D + kLambdaK * (double)pi.kc);
+  return (float)(D + kLambdaK * (double)kc);
 }
 
-// Forward: one thread per particle.
+// Forward: one wavefront per particle.
 __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace ws) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int p = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int n_total = a.n_frames * a.n_particles;
   if (p >= n_total) return;
   const PInfo pi = ws.pinfo[p];
   if (pi.skip) return;
-  a.cost[p] = pi.valid ? assemble_cost(a, ws, pi, p, nullptr) : (pi.slot < 0 ? NAN : INFINITY);
+  if (!pi.valid) {
+    if (lane == 0) a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
+    return;
+  }
+  double S_d;
+  long long S_and, S_or;
+  const int b = ws.item_off[p];
+  wave_partial_sums(a.slots[pi.slot], ws, b, b + pi.n_items, lane, S_d, S_and, S_or);
+  if (lane == 0) a.cost[p] = cost_from_sums(S_d, S_and, S_or, pi.kc);
 }
 
 // Gradient: one workgroup per particle.  Threads (segment, component) sum the per-item
@@ -1274,6 +1292,7 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   __shared__ double s_W[HT_MAX_SEG * 6];
   __shared__ double s_part[kWavesPerBlock][HT_MAX_SEG * 6];
   __shared__ double s_inv_or;
+  __shared__ float s_org[HT_MAX_SEG * 4];
   const int p = blockIdx.x, t = threadIdx.x;
   const PInfo pi = ws.pinfo[p];
   const int n_dof = a.n_dof, n_seg = a.n_seg;
@@ -1284,32 +1303,49 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
     return;
   }
   const int b = ws.item_off[p], e = b + pi.n_items;
-  // wave q sums items b+q, b+q+4, ...; lane l sums values l, l+64, l+128; then the four
-  // partial sums are added in a fixed order
+  // segment origins staged for the adjoint below
+  for (int i = t; i < n_seg * 4; i += kBlock) s_org[i] = ws.seg_org[(size_t)p * n_seg * 4 + i];
+  // wave q sums items b+q, b+q+4, ... (two at a time, loads first); lane l sums values l,
+  // l+64, l+128; then the four partial sums are added in a fixed order
   const int nv = n_seg * 6, lane = t & (kWave - 1), q = t >> 6;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int i = b + q; i < e; i += kWavesPerBlock) {
-    const float* src = ws.wrench + (size_t)i * nv;
+  for (int i = b + q; i < e; i += 2 * kWavesPerBlock) {
+    const bool two = i + kWavesPerBlock < e;
+    const float* s0 = ws.wrench + (size_t)i * nv;
+    const float* s1 = s0 + (size_t)kWavesPerBlock * nv;
+    float v0[3], v1[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      if (lane + k * kWave < nv) acc[k] += (double)src[lane + k * kWave];
+    for (int k = 0; k < 3; ++k) {
+      const bool in = lane + k * kWave < nv;
+      v0[k] = in ? s0[lane + k * kWave] : 0.0f;
+      v1[k] = in && two ? s1[lane + k * kWave] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      acc[k] += (double)v0[k];
+      if (two) acc[k] += (double)v1[k];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     if (lane + k * kWave < nv) s_part[q][lane + k * kWave] = acc[k];
+  if (q == 0) {
+    double S_d;
+    long long S_and, S_or;
+    wave_partial_sums(a.slots[pi.slot], ws, b, e, lane, S_d, S_and, S_or);
+    if (lane == 0) {
+      a.cost[p] = cost_from_sums(S_d, S_and, S_or, pi.kc);
+      s_inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
+    }
+  }
   __syncthreads();
   if (t < nv) s_W[t] = ((s_part[0][t] + s_part[1][t]) + s_part[2][t]) + s_part[3][t];
-  if (t == kBlock - 1) {
-    long long S_or = 0;
-    a.cost[p] = assemble_cost(a, ws, pi, p, &S_or);
-    s_inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
-  }
   __syncthreads();
   const DevModel& M = *a.model;
   if (t < n_dof) {
     const int j = t;
     const float* f = ws.dof_frame + ((size_t)p * n_dof + j) * 8;
-    const float* org = ws.seg_org + (size_t)p * n_seg * 4;
+    const float* org = s_org;
     const uint32_t desc = M.dof_desc[j];
     const bool trans = f[0] != 0.0f;
     const double ax = f[1], ay = f[2], az = f[3];
@@ -1391,7 +1427,7 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
       if (a.grad)
         hipLaunchKernelGGL(finalize_grad_kernel, dim3(n_total), dim3(kBlock), 0, s, a, ws);
       else
-        hipLaunchKernelGGL(finalize_kernel, dim3((n_total + kBlock - 1) / kBlock),
+        hipLaunchKernelGGL(finalize_kernel, dim3((n_total + kWavesPerBlock - 1) / kWavesPerBlock),
                            dim3(kBlock), 0, s, a, ws);
       break;
     default:
