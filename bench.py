@@ -36,8 +36,8 @@ METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at 
 # reads half the bytes read, WRITE_SIZE all the bytes written).  Keyed by the SHA-256 of the
 # kernel sources it was measured on: any later change of the kernel reports null.
 MEASURED_TRAFFIC = {
-    "d257de2533bcb5d108295f4820c271a7647466c1f4edd8567b09c9ee365c8560": {
-        "config": 4, "fetch_kib": 4653.13, "write_kib": 276.221, "fetch_scale": 2.0,
+    "58e66ac6ed86c2e5bf67b70a3aa8eaa7b0c32199888912591434c24974855993": {
+        "config": 4, "fetch_kib": 12422.252, "write_kib": 314.223, "fetch_scale": 2.0,
         "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",
