@@ -695,18 +695,26 @@ ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, h
     st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s,
                        sw.stop_gen);
     if (st != HT_OK) return st;
-    for (int step = 0; step < p.refine_steps; ++step) {
-      const bool last = step + 1 == p.refine_steps;
-      float* cgrad = last ? nullptr : c->r_cgrad;
-      HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_propose(c->d_model, n_ref, D, p.eta_rot, p.eta_trans, c->r_x,
-                                       c->r_grad, c->r_active, c->r_cand, s); }));
-      st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, cgrad, nullptr,
+    // step s: candidates from the current positions and gradients (fused with accepting the
+    // previous step's), their evaluation (with gradients but in the last step), and after the
+    // last step the accept fused with writing the refined particles back into the swarm
+    for (int step = 0; step <= p.refine_steps; ++step) {
+      const bool accept = step > 0, propose = step < p.refine_steps;
+      const bool gather = step == p.refine_steps;
+      // the gradients of the candidates being accepted now (evaluated in step - 1)
+      const float* cgrad_in = accept && step < p.refine_steps ? c->r_cgrad : nullptr;
+      HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] {
+        return ht::launch_refine_update(c->d_model, sw, K, D, p.eta_rot, p.eta_trans, accept,
+                                        propose, gather, c->r_sel, c->r_x, c->r_cost,
+                                        c->r_active, c->r_cand, c->r_ccost, cgrad_in, c->r_grad,
+                                        s);
+      }));
+      if (!propose) break;
+      float* cgrad_out = step + 1 < p.refine_steps ? c->r_cgrad : nullptr;
+      st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, cgrad_out, nullptr,
                          nullptr, s, sw.stop_gen);
       if (st != HT_OK) return st;
-      HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_accept(n_ref, D, c->r_x, c->r_cost, c->r_cand, c->r_ccost,
-                                      c->r_active, cgrad, c->r_grad, s); }));
     }
-    HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_gather(sw, K, D, c->r_sel, c->r_x, c->r_cost, s); }));
   }
   if (F * P > c->cap_flags) {
     if (capturing(s)) return fail(HT_ERR_STATE, "swarm flags too small during capture");

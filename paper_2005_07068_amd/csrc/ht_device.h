@@ -150,13 +150,10 @@ hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht
                              int n_dof, int* flags, hipStream_t s);
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
                                 float* rcost, int* active, hipStream_t s);
-hipError_t launch_refine_propose(const DevModel* model, int n_ref, int n_dof, float eta_rot,
-                                 float eta_trans, const float* rx, const float* grad,
-                                 const int* active, float* cand, hipStream_t s);
-hipError_t launch_refine_accept(int n_ref, int n_dof, float* rx, float* rcost, const float* cand,
-                                const float* ccost, int* active, const float* cgrad,
-                                float* grad, hipStream_t s);
-hipError_t launch_refine_gather(const ht_swarm& sw, int K, int n_dof, const int* sel,
-                                const float* rx, const float* rcost, hipStream_t s);
+hipError_t launch_refine_update(const DevModel* model, const ht_swarm& sw, int K, int n_dof,
+                                float eta_rot, float eta_trans, bool accept, bool propose,
+                                bool gather, const int* sel, float* rx, float* rcost,
+                                int* active, float* cand, const float* ccost,
+                                const float* cgrad, float* grad, hipStream_t s);
 
 }  // namespace ht

@@ -344,81 +344,81 @@ __global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, i
   }
 }
 
-// one wavefront per refined particle, one lane per dimension
-__global__ __launch_bounds__(kBlock) void refine_propose_kernel(const DevModel* __restrict__ M,
-                                                                int n_ref, int n_dof,
-                                                                float eta_rot, float eta_trans,
-                                                                const float* __restrict__ rx,
-                                                                const float* __restrict__ grad,
-                                                                const int* __restrict__ active,
-                                                                float* __restrict__ cand) {
+// One refinement update, one wavefront per refined particle and one lane per dimension:
+//   accept  - take the longest of the four steps that lowers E (the first in halving order);
+//             with cgrad the candidates' gradients were evaluated with their costs and the
+//             accepted one's becomes the particle's gradient; no step lowers E: the particle
+//             stops refining;
+//   propose - four candidates x - eta * (g_s / max|g_s|) / 2^j, j = 0..3, g_s = eta * dE/dh,
+//             clamped to the bounds (a stopped particle proposes its own position four times);
+//   gather  - write the refined positions and costs back into the swarm.
+struct RefineOp {
+  int accept, propose, gather;
+};
+
+__global__ __launch_bounds__(kBlock) void refine_update_kernel(
+    const DevModel* __restrict__ M, int n_ref, int n_dof, float eta_rot, float eta_trans,
+    RefineOp op, ht_swarm sw, int K, const int* __restrict__ sel, float* __restrict__ rx,
+    float* __restrict__ rcost, int* __restrict__ active, float* __restrict__ cand,
+    const float* __restrict__ ccost, const float* __restrict__ cgrad, float* __restrict__ grad) {
   const int lane = threadIdx.x & (kWave - 1);
   const int r = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (r >= n_ref) return;
   const bool on = lane < n_dof;
   const int d = on ? lane : 0;
-  const float eta = M->dof_trans[d] ? eta_trans : eta_rot;
-  const float x = on ? rx[(size_t)r * n_dof + d] : 0.0f;
-  const float gs = on ? eta * grad[(size_t)r * n_dof + d] : 0.0f;
-  float gmax = fabsf(gs);
-  bool fin = isfinite(gs);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o));
-  fin = __ballot(!fin) == 0ull;
-  const bool ok = active[r] != 0 && fin && gmax > 0.0f;
-  if (!on) return;
-  for (int j = 0; j < 4; ++j) {
-    float xn = x;
-    if (ok) {
-      const float step = eta * (gs / gmax) * ldexpf(1.0f, -j);
-      xn = fminf(fmaxf(x - step, M->lo[d]), M->hi[d]);
+  const size_t xi = (size_t)r * n_dof + d;
+  bool act = active[r] != 0;
+  float x = on ? rx[xi] : 0.0f;
+  float c = rcost[r];
+  float g = on ? grad[xi] : 0.0f;
+  if (op.accept && act) {
+    int pick = -1;
+    for (int j = 3; j >= 0; --j)
+      if (ccost[(size_t)r * 4 + j] < c) pick = j;
+    if (pick < 0) {
+      act = false;
+      if (lane == 0) active[r] = 0;
+    } else {
+      const size_t src = ((size_t)r * 4 + pick) * n_dof + d;
+      c = ccost[(size_t)r * 4 + pick];
+      if (on) {
+        x = cand[src];
+        rx[xi] = x;
+        if (cgrad) {
+          g = cgrad[src];
+          grad[xi] = g;
+        }
+      }
+      if (lane == 0) rcost[r] = c;
     }
-    cand[((size_t)r * 4 + j) * n_dof + d] = xn;
   }
-}
-
-// accept the longest of the four steps that lowers E (the first, in halving order); with
-// cgrad, the candidates' gradients were evaluated with their costs and the accepted one's
-// becomes the particle's gradient for the next step
-__global__ __launch_bounds__(kBlock) void refine_accept_kernel(int n_ref, int n_dof,
-                                                               float* __restrict__ rx,
-                                                               float* __restrict__ rcost,
-                                                               const float* __restrict__ cand,
-                                                               const float* __restrict__ ccost,
-                                                               int* __restrict__ active,
-                                                               const float* __restrict__ cgrad,
-                                                               float* __restrict__ grad) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int r = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (r >= n_ref || !active[r]) return;
-  const float c0 = rcost[r];
-  int pick = -1;
-  for (int j = 3; j >= 0; --j)
-    if (ccost[(size_t)r * 4 + j] < c0) pick = j;
-  if (pick < 0) {
-    if (lane == 0) active[r] = 0;
-    return;
+  if (op.propose) {
+    const float eta = M->dof_trans[d] ? eta_trans : eta_rot;
+    const float gs = on ? eta * g : 0.0f;
+    float gmax = fabsf(gs);
+    bool fin = isfinite(gs);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o));
+    fin = __ballot(!fin) == 0ull;
+    const bool ok = act && fin && gmax > 0.0f;
+    if (on) {
+      for (int j = 0; j < 4; ++j) {
+        float xn = x;
+        if (ok) {
+          const float step = eta * (gs / gmax) * ldexpf(1.0f, -j);
+          xn = fminf(fmaxf(x - step, M->lo[d]), M->hi[d]);
+        }
+        cand[((size_t)r * 4 + j) * n_dof + d] = xn;
+      }
+    }
   }
-  const size_t src = ((size_t)r * 4 + pick) * n_dof + lane;
-  if (lane < n_dof) {
-    rx[(size_t)r * n_dof + lane] = cand[src];
-    if (cgrad) grad[(size_t)r * n_dof + lane] = cgrad[src];
+  if (op.gather) {
+    const int f = r / K;
+    if (sw.stop_gen && sw.stop_gen[f] != 0) return;
+    const size_t gp = (size_t)f * sw.n_particles + sel[r];
+    if (on) sw.x[gp * n_dof + d] = x;
+    if (lane == 0) sw.cost[gp] = c;
   }
-  if (lane == 0) rcost[r] = ccost[(size_t)r * 4 + pick];
-}
-
-__global__ __launch_bounds__(kBlock) void refine_gather_kernel(ht_swarm sw, int K, int n_dof,
-                                                               const int* __restrict__ sel,
-                                                               const float* __restrict__ rx,
-                                                               const float* __restrict__ rcost) {
-  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= (size_t)sw.n_frames * K * n_dof) return;
-  const int r = (int)(e / n_dof), d = (int)(e % n_dof);
-  const int f = r / K;
-  if (sw.stop_gen && sw.stop_gen[f] != 0) return;
-  const size_t gp = (size_t)f * sw.n_particles + sel[r];
-  sw.x[gp * n_dof + d] = rx[e];
-  if (d == 0) sw.cost[gp] = rcost[r];
 }
 
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
@@ -429,29 +429,16 @@ hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, 
   return hipGetLastError();
 }
 
-hipError_t launch_refine_propose(const DevModel* model, int n_ref, int n_dof, float eta_rot,
-                                 float eta_trans, const float* rx, const float* grad,
-                                 const int* active, float* cand, hipStream_t s) {
-  hipLaunchKernelGGL(refine_propose_kernel, dim3((n_ref + kWavesPerBlock - 1) / kWavesPerBlock),
-                     dim3(kBlock), 0, s, model, n_ref, n_dof, eta_rot, eta_trans, rx, grad,
-                     active, cand);
-  return hipGetLastError();
-}
-
-hipError_t launch_refine_accept(int n_ref, int n_dof, float* rx, float* rcost, const float* cand,
-                                const float* ccost, int* active, const float* cgrad,
-                                float* grad, hipStream_t s) {
-  hipLaunchKernelGGL(refine_accept_kernel, dim3((n_ref + kWavesPerBlock - 1) / kWavesPerBlock),
-                     dim3(kBlock), 0, s, n_ref, n_dof, rx, rcost, cand, ccost, active, cgrad,
-                     grad);
-  return hipGetLastError();
-}
-
-hipError_t launch_refine_gather(const ht_swarm& sw, int K, int n_dof, const int* sel,
-                                const float* rx, const float* rcost, hipStream_t s) {
-  const size_t n = (size_t)sw.n_frames * K * n_dof;
-  hipLaunchKernelGGL(refine_gather_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, s, sw, K, n_dof, sel, rx, rcost);
+hipError_t launch_refine_update(const DevModel* model, const ht_swarm& sw, int K, int n_dof,
+                                float eta_rot, float eta_trans, bool accept, bool propose,
+                                bool gather, const int* sel, float* rx, float* rcost,
+                                int* active, float* cand, const float* ccost,
+                                const float* cgrad, float* grad, hipStream_t s) {
+  const int n_ref = sw.n_frames * K;
+  const RefineOp op{accept ? 1 : 0, propose ? 1 : 0, gather ? 1 : 0};
+  hipLaunchKernelGGL(refine_update_kernel, dim3((n_ref + kWavesPerBlock - 1) / kWavesPerBlock),
+                     dim3(kBlock), 0, s, model, n_ref, n_dof, eta_rot, eta_trans, op, sw, K, sel,
+                     rx, rcost, active, cand, ccost, cgrad, grad);
   return hipGetLastError();
 }
 
