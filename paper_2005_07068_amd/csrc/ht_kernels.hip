@@ -200,25 +200,32 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
 
 constexpr int kItemsPerGroup = 1;
 
-// Inclusive scan over the workgroup; every thread gets its own prefix and the total.
+// Inclusive scan over the workgroup; every thread gets its own prefix and the total: a scan
+// within each wavefront by lane shifts, then the wavefront totals through LDS (two barriers
+// instead of two per doubling step).
 __device__ int block_scan(int* s_sum, int v, int* total) {
-  const int t = threadIdx.x;
-  s_sum[t] = v;
-  __syncthreads();
-  for (int o = 1; o < kBlock; o <<= 1) {   // Hillis-Steele
-    const int u = t >= o ? s_sum[t - o] : 0;
-    __syncthreads();
-    s_sum[t] += u;
-    __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if (lane >= o) v += u;
   }
-  const int r = s_sum[t];
-  *total = s_sum[kBlock - 1];
+  if (lane == kWave - 1) s_sum[wv] = v;
   __syncthreads();
-  return r;
+  int before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < kWavesPerBlock; ++q) {
+    const int w = s_sum[q];
+    before += q < wv ? w : 0;
+    all += w;
+  }
+  __syncthreads();
+  *total = all;
+  return v + before;
 }
 
 __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& ws) {
-  __shared__ int s_sum[kBlock];
+  __shared__ int s_sum[kWavesPerBlock];
   const int t = threadIdx.x;
   const int chunk = (n_total + kBlock - 1) / kBlock;
   const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);

@@ -344,6 +344,95 @@ __global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, i
   }
 }
 
+// Select for up to 1024 particles and K <= 64 without a full sort: every wavefront sorts its
+// 64 (cost, index) pairs with a bitonic network across its lanes, then sorted lists are merged
+// pairwise in rounds keeping the first K (an element's rank in the union of two sorted lists
+// is its own position plus the number of the other list's elements before it; the keys are
+// unique, so the ranks are distinct).  The K lowest, ties by lower index, as the full sort.
+__device__ __forceinline__ bool key_before(float ka, int ia, float kb, int ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+__device__ __forceinline__ int count_before(const float* xk, const int* xi, int n, float k,
+                                            int i) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (key_before(xk[mid], xi[mid], k, i)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kPsoBlock) void refine_select_small_kernel(
+    ht_swarm sw, int K, int n_dof, int* __restrict__ sel, float* __restrict__ rx,
+    float* __restrict__ rcost, int* __restrict__ active) {
+  __shared__ float s_k[2][kPsoBlock / kWave][kWave];
+  __shared__ int s_i[2][kPsoBlock / kWave][kWave];
+  const int P = sw.n_particles, f = blockIdx.x;
+  const size_t base = (size_t)f * P;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  int nl = blockDim.x / kWave;                  // sorted lists
+  // 1. bitonic sort of each wavefront's 64 entries (padding: +inf, indices past P)
+  const int e = w * kWave + lane;
+  float k = e < P ? cost_key(sw.cost[base + e]) : INFINITY;
+  int i = e;
+  for (int size = 2; size <= kWave; size <<= 1) {
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      const float pk = __shfl_xor(k, j);
+      const int pi = __shfl_xor(i, j);
+      const bool up = (lane & size) == 0, lower = (lane & j) == 0;
+      const bool take = lower == up ? key_before(pk, pi, k, i) : key_before(k, i, pk, pi);
+      if (take) {
+        k = pk;
+        i = pi;
+      }
+    }
+  }
+  s_k[0][w][lane] = k;
+  s_i[0][w][lane] = i;
+  __syncthreads();
+  // 2. pairwise merges keeping the first K of each union
+  int cur = 0;
+  while (nl > 1) {
+    const int pairs = nl >> 1;
+    if (w < pairs && lane < K) {
+      const float* ak = s_k[cur][2 * w];
+      const int* ai = s_i[cur][2 * w];
+      const float* bk = s_k[cur][2 * w + 1];
+      const int* bi = s_i[cur][2 * w + 1];
+      const int ra = lane + count_before(bk, bi, K, ak[lane], ai[lane]);
+      const int rb = lane + count_before(ak, ai, K, bk[lane], bi[lane]);
+      if (ra < K) {
+        s_k[cur ^ 1][w][ra] = ak[lane];
+        s_i[cur ^ 1][w][ra] = ai[lane];
+      }
+      if (rb < K) {
+        s_k[cur ^ 1][w][rb] = bk[lane];
+        s_i[cur ^ 1][w][rb] = bi[lane];
+      }
+    }
+    if ((nl & 1) && w == pairs && lane < K) {    // odd list passes through
+      s_k[cur ^ 1][w][lane] = s_k[cur][nl - 1][lane];
+      s_i[cur ^ 1][w][lane] = s_i[cur][nl - 1][lane];
+    }
+    __syncthreads();
+    nl = pairs + (nl & 1);
+    cur ^= 1;
+  }
+  // 3. the K best
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    const size_t q = (size_t)f * K + r;
+    sel[q] = s_i[cur][0][r];
+    rcost[q] = s_k[cur][0][r];
+    active[q] = 1;
+  }
+  for (int x = threadIdx.x; x < K * n_dof; x += blockDim.x) {
+    const int r = x / n_dof, d = x % n_dof;
+    rx[((size_t)f * K + r) * n_dof + d] = sw.x[(base + s_i[cur][0][r]) * n_dof + d];
+  }
+}
+
 // One refinement update, one wavefront per refined particle and one lane per dimension:
 //   accept  - take the longest of the four steps that lowers E (the first in halving order);
 //             with cgrad the candidates' gradients were evaluated with their costs and the
@@ -423,6 +512,12 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(
 
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
                                 float* rcost, int* active, hipStream_t s) {
+  if (sw.n_particles <= kPsoBlock && K <= kWave) {
+    hipLaunchKernelGGL(refine_select_small_kernel, dim3(sw.n_frames),
+                       dim3(threads_for(sw.n_particles)), 0, s, sw, K, n_dof, sel, rx, rcost,
+                       active);
+    return hipGetLastError();
+  }
   const int n_pad = pow2_at_least(sw.n_particles);
   hipLaunchKernelGGL(refine_select_kernel, dim3(sw.n_frames), dim3(threads_for(sw.n_particles)),
                      (size_t)n_pad * 8, s, sw, K, n_dof, n_pad, sel, rx, rcost, active);
