@@ -88,7 +88,7 @@ struct PInfo {
   float kc;                   // collision term of Eq. 5
   int valid;                  // 0: non-finite pose or unset slot
   int skip;                   // 1: the particle's frame has stopped: nothing is written
-  int pad;
+  int kc_mask;                // collision pairs with a positive term (bit i: pair i)
 };
 
 struct Partial {

@@ -627,9 +627,15 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
     pi.valid = valid ? 1 : 0;
     pi.skip = skip ? 1 : 0;
     double kc = 0.0;
-    if (valid)
-      for (int i = 0; i < M.n_kc; ++i) kc += s_kc[w][i];
+    int kc_mask = 0;
+    if (valid) {
+      for (int i = 0; i < M.n_kc; ++i) {
+        kc += s_kc[w][i];
+        kc_mask |= s_kc[w][i] > 0.0 ? 1 << i : 0;
+      }
+    }
     pi.kc = (float)kc;
+    pi.kc_mask = kc_mask;
     // one tile rectangle per tree, as (x0, y0, x1, y1) inclusive; merge overlapping ones so
     // that no tile is visited twice
     int4 R[kMaxRects];
@@ -1300,6 +1306,7 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   __shared__ double s_part[kWavesPerBlock][HT_MAX_SEG * 6];
   __shared__ double s_inv_or;
   __shared__ float s_org[HT_MAX_SEG * 4];
+  __shared__ int s_kca[HT_MAX_KC], s_kcb[HT_MAX_KC];
   const int p = blockIdx.x, t = threadIdx.x;
   const PInfo pi = ws.pinfo[p];
   const int n_dof = a.n_dof, n_seg = a.n_seg;
@@ -1310,8 +1317,12 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
     return;
   }
   const int b = ws.item_off[p], e = b + pi.n_items;
-  // segment origins staged for the adjoint below
+  // segment origins and collision pairs staged for the adjoint below
   for (int i = t; i < n_seg * 4; i += kBlock) s_org[i] = ws.seg_org[(size_t)p * n_seg * 4 + i];
+  if (t < HT_MAX_KC) {
+    s_kca[t] = t < a.model->n_kc ? a.model->kc_a[t] : -1;
+    s_kcb[t] = t < a.model->n_kc ? a.model->kc_b[t] : -1;
+  }
   // wave q sums items b+q, b+q+4, ... (two at a time, loads first); lane l sums values l,
   // l+64, l+128; then the four partial sums are added in a fixed order
   const int nv = n_seg * 6, lane = t & (kWave - 1), q = t >> 6;
@@ -1345,15 +1356,24 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
       s_inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
     }
   }
+  // this thread's pose parameter: its descendant mask and camera-frame axis / point, loaded
+  // before the barriers
+  const int j = t;
+  uint32_t desc = 0;
+  float fr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (j < n_dof) {
+    desc = a.model->dof_desc[j];
+    const float4* f4 = reinterpret_cast<const float4*>(ws.dof_frame + ((size_t)p * n_dof + j) * 8);
+    const float4 f0 = f4[0], f1 = f4[1];
+    fr[0] = f0.x; fr[1] = f0.y; fr[2] = f0.z; fr[3] = f0.w;
+    fr[4] = f1.x; fr[5] = f1.y; fr[6] = f1.z; fr[7] = f1.w;
+  }
   __syncthreads();
   if (t < nv) s_W[t] = ((s_part[0][t] + s_part[1][t]) + s_part[2][t]) + s_part[3][t];
   __syncthreads();
-  const DevModel& M = *a.model;
-  if (t < n_dof) {
-    const int j = t;
-    const float* f = ws.dof_frame + ((size_t)p * n_dof + j) * 8;
+  if (j < n_dof) {
+    const float* f = fr;
     const float* org = s_org;
-    const uint32_t desc = M.dof_desc[j];
     const bool trans = f[0] != 0.0f;
     const double ax = f[1], ay = f[2], az = f[3];
     double g = 0.0;
@@ -1373,13 +1393,11 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
       }
     }
     g *= s_inv_or;
-    // collision term of Eq. 5
-    const float* h = a.poses + (size_t)p * n_dof;
-    for (int i = 0; i < M.n_kc; ++i) {
-      if ((double)h[M.kc_a[i]] - (double)h[M.kc_b[i]] < 0.0) {
-        if (M.kc_a[i] == j) g -= kLambdaK;
-        if (M.kc_b[i] == j) g += kLambdaK;
-      }
+    // collision term of Eq. 5: the pairs whose term is positive (recorded by the kinematics)
+    for (int m = pi.kc_mask; m; m &= m - 1) {
+      const int i = __builtin_ctz(m);
+      if (s_kca[i] == j) g -= kLambdaK;
+      if (s_kcb[i] == j) g += kLambdaK;
     }
     a.grad[(size_t)p * n_dof + j] = (float)g;
   }

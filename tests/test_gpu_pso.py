@@ -111,3 +111,25 @@ def test_refinement_never_raises_the_cost():
     assert np.any(c1[top] < c0[top])
     others = np.setdiff1d(np.arange(64), top)
     assert np.array_equal(c1[others], c0[others])
+
+
+@pytest.mark.parametrize("P,K", [(100, 40), (1000, 64), (100, 80)])
+def test_refinement_selects_exactly_the_k_lowest(P, K):
+    """The refined set is the K lowest current costs (ties: lower index), for a particle count
+    that is not a multiple of the wavefront, the largest fast-path K and the full-sort path;
+    duplicated positions create exact cost ties."""
+    torch, ctx, model, fr, sw, lo, hi = _setup(P=P)
+    ctx.pso_init(sw)
+    plain = ht.pso_params(mutate_every=0)
+    ctx.pso_step(sw, plain)
+    # duplicate some positions so that their costs tie exactly
+    x = sw["x"].clone()
+    x[0, 1::7] = x[0, 0]
+    sw["x"].copy_(x)
+    c0 = ctx.eval(x[0], sw["frame_slots"]).cpu().numpy()
+    ctx.pso_step(sw, ht.pso_params(mutate_every=0, refine_topk=K, refine_steps=1))
+    c1 = sw["cost"].cpu().numpy()[0]
+    top = np.array(sorted(range(P), key=lambda i: (c0[i], i))[:K])
+    others = np.setdiff1d(np.arange(P), top)
+    assert np.array_equal(c1[others], c0[others])
+    assert np.all(c1[top] <= c0[top])
