@@ -81,63 +81,134 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=8):
+def _errors_per_generation(ctx, sw, params, G, h_true, n_hands):
+    """Eager generations (outside any timing) and the mean joint error after each."""
+    ctx.pso_init(sw)
+    errs = []
+    for _ in range(G):
+        ctx.pso_step(sw, params)
+        errs.append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
+                                    n_hands))
+    return errs
+
+
+def plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16,
+                     target_deg=5.0):
     """Plain swarm (the paper's 64 particles x 30 generations) against the workload's
-    gradient-refined swarm on the same frame(s): final mean joint error, ms per frame (graph
-    replay) and, for the refined swarm, the evaluations it needs to reach the plain swarm's
-    final error (mean over seeds)."""
+    gradient-refined swarm on the same frame(s), over seeds: final joint error, ms per frame
+    (graph replay), the evaluations each needs to reach a mean joint error of ``target_deg``
+    and those the refined swarm needs to reach the plain swarm's final error."""
     F = slots.numel()
     plain_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2)
     ref_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, refine_topk=cfg.refine_topk,
                           refine_steps=cfg.refine_steps)
     P, G = cfg.n_particles, cfg.n_generations
-    per_gen = F * P + F * cfg.refine_topk * (1 + 4 * cfg.refine_steps)
-    out = {"plain": {"particles": 64, "generations": 30, "err": [], "ms": []},
-           "refined": {"particles": P, "generations": G, "err": [], "ms": [],
+    per_gen = {"plain": F * 64,
+               "refined": F * P + F * cfg.refine_topk * (1 + 4 * cfg.refine_steps)}
+    out = {"plain": {"particles": 64, "generations": 30, "err": [], "ms": [], "to_target": []},
+           "refined": {"particles": P, "generations": G, "err": [], "ms": [], "to_target": [],
                        "evals_to_plain_err": []}}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for s in range(seeds):
-        sw = ctx.swarm(slots, 64, lo, hi, seed=1000 + s)
-        ctx.pso_run_graph(sw, plain_p, 30)
-        torch.cuda.synchronize()
-        e0.record()
-        ctx.pso_run_graph(sw, plain_p, 30)
-        e1.record()
-        torch.cuda.synchronize()
-        plain_err = joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
-                                    cfg.n_hands)
-        out["plain"]["err"].append(plain_err)
-        out["plain"]["ms"].append(e0.elapsed_time(e1) / F)
-        sw = ctx.swarm(slots, P, lo, hi, seed=1000 + s)
-        ctx.pso_run_graph(sw, ref_p, G)
-        torch.cuda.synchronize()
-        e0.record()
-        ctx.pso_run_graph(sw, ref_p, G)
-        e1.record()
-        torch.cuda.synchronize()
-        out["refined"]["ms"].append(e0.elapsed_time(e1) / F)
-        # per-generation error of the refined swarm (eager steps, outside any timing)
-        ctx.pso_init(sw)
-        reach = None
-        for g in range(G):
-            ctx.pso_step(sw, ref_p)
-            err = joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
-                                  cfg.n_hands)
-            if reach is None and err <= plain_err:
-                reach = (g + 1) * per_gen
-        out["refined"]["err"].append(err)
-        out["refined"]["evals_to_plain_err"].append(reach)
-    summary = {}
+        finals = {}
+        for kind, n, gens, params in (("plain", 64, 30, plain_p), ("refined", P, G, ref_p)):
+            sw = ctx.swarm(slots, n, lo, hi, seed=1000 + s)
+            ctx.pso_run_graph(sw, params, gens)
+            torch.cuda.synchronize()
+            e0.record()
+            ctx.pso_run_graph(sw, params, gens)
+            e1.record()
+            torch.cuda.synchronize()
+            out[kind]["ms"].append(e0.elapsed_time(e1) / F)
+            errs = _errors_per_generation(ctx, sw, params, gens, h_true, cfg.n_hands)
+            finals[kind] = errs
+            out[kind]["err"].append(errs[-1])
+            hit = next((g for g, e in enumerate(errs) if e <= target_deg), None)
+            out[kind]["to_target"].append(None if hit is None else (hit + 1) * per_gen[kind])
+        plain_err = finals["plain"][-1]
+        hit = next((g for g, e in enumerate(finals["refined"]) if e <= plain_err), None)
+        out["refined"]["evals_to_plain_err"].append(None if hit is None
+                                                    else (hit + 1) * per_gen["refined"])
+    summary = {"seeds": seeds, "target_joint_error_deg": target_deg}
     for k, v in out.items():
+        reached = [r for r in v["to_target"] if r is not None]
         summary[k] = {"particles": v["particles"], "generations": v["generations"],
                       "mean_joint_error_deg": float(np.mean(v["err"])),
-                      "ms_per_frame": float(np.mean(v["ms"]))}
+                      "median_joint_error_deg": float(np.median(v["err"])),
+                      "ms_per_frame": float(np.mean(v["ms"])),
+                      "seeds_reaching_target": len(reached),
+                      "mean_evals_to_target": float(np.mean(reached)) if reached else None}
     reached = [r for r in out["refined"]["evals_to_plain_err"] if r is not None]
     summary["refined"]["seeds_reaching_plain_error"] = len(reached)
     summary["refined"]["mean_evals_to_plain_error"] = float(np.mean(reached)) if reached else None
     summary["plain"]["evals"] = 64 * 30
-    summary["seeds"] = seeds
     return summary
+
+
+def plain_seed_study(ctx, ht, torch, cfg, slots, lo, hi, h_true, seeds=32, reps=100):
+    """The plain swarm of the workload over seeds (final joint error, mean and median) and
+    the median of ``reps`` timed graph replays."""
+    params = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2)
+    errs = []
+    for s in range(seeds):
+        sw = ctx.swarm(slots, cfg.n_particles, lo, hi, seed=2000 + s)
+        ctx.pso_run_graph(sw, params, cfg.n_generations)
+        errs.append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
+                                    cfg.n_hands))
+    torch.cuda.synchronize()
+    times = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(reps):
+        ev[0].record()
+        ctx.pso_run_graph(sw, params, cfg.n_generations)
+        ev[1].record()
+        torch.cuda.synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    return {"seeds": seeds, "mean_joint_error_deg": float(np.mean(errs)),
+            "median_joint_error_deg": float(np.median(errs)),
+            "replays": reps, "median_ms_per_run": float(np.median(times))}
+
+
+def eval_throughput(ht, torch, idx=2, reps=50):
+    """Evaluation alone on the 320x240 one-hand workload: its particles (drawn like an
+    initial swarm) evaluated forward and with gradients, each looped in a captured graph."""
+    from workload.handmodel import init_halfwidth
+    cfg, model, frames, flops_per_eval, _ = load_workload(idx)
+    fr = frames[0]
+    dev = torch.device("cuda:0")
+    ctx = ht.Context(0)
+    ctx.set_model(model)
+    ctx.set_observation(0, fr["depth"], fr["skin"], fr["cam"], fr["bg"])
+    P = cfg.n_particles
+    ctx.reserve(P, fr["depth"].size)
+    d = init_halfwidth(model["n_dof"], cfg.init_angle_deg, cfg.init_trans_mm)
+    rng = np.random.default_rng(31)
+    x = torch.tensor((fr["h_true"] - d + rng.random((1, P, model["n_dof"])) * 2 * d),
+                     dtype=torch.float32, device=dev)
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    tpi, gpc, cull = ctx.autotune(x, slots, repeats=2)
+    cost = torch.empty((1, P), device=dev)
+    out = {"workload": cfg.name, "particles": P, "launch": [tpi, gpc, cull]}
+    for kind in ("forward", "gradient"):
+        f = (lambda: ctx.eval(x, slots, cost)) if kind == "forward" else \
+            (lambda: ctx.eval_grad(x, slots))
+        f()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                f()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out[kind] = {"us_per_call": us, "evals_per_s": P / (us / 1e6)}
+    ctx.close()
+    return out
 
 
 def pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16, P=64, G=30):
@@ -357,7 +428,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=4, choices=[1, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-study", action="store_true",
                     help="skip the plain-versus-refined swarm comparison")
@@ -379,6 +450,13 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.config == 2:
+        import torch
+
+        import paper_2005_07068_amd as ht
+        log("forward and gradient evaluation throughput, 320x240")
+        print(json.dumps({"evaluation": eval_throughput(ht, torch)}), flush=True)
+        return
     if args.copy_calibration or args.sweep or args.track:
         import torch
 
@@ -509,6 +587,9 @@ def main():
                         "avg_ms": v["ms"] / v["launches"] if v["launches"] else 0.0}
                     for k, v in stats.items()},
     }
+    if K == 0 and not args.no_study:
+        log("plain swarm over seeds")
+        line["seed_study"] = plain_seed_study(ctx, ht, torch, cfg, slots, lo, hi, h_true)
     if K > 0 and not args.no_study:
         log("plain versus gradient-refined swarm over seeds")
         line["plain_vs_refined"] = plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi,
