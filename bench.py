@@ -81,36 +81,51 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def _errors_per_generation(ctx, sw, params, G, h_true, n_hands):
-    """Eager generations (outside any timing) and the mean joint error after each."""
+def _trace_generations(ctx, sw, params, G, h_true, n_hands):
+    """Eager generations (outside any timing): the joint error and the gbest cost (mean over
+    frames) after each."""
     ctx.pso_init(sw)
-    errs = []
+    errs, costs = [], []
     for _ in range(G):
         ctx.pso_step(sw, params)
         errs.append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
                                     n_hands))
-    return errs
+        costs.append(float(sw["gbest_cost"].cpu().numpy().mean()))
+    return errs, costs
+
+
+def _first_staying(values, bound):
+    """First index from which every later value is <= bound, or None."""
+    hit = None
+    for g, v in enumerate(values):
+        if v <= bound:
+            hit = g if hit is None else hit
+        else:
+            hit = None
+    return hit
 
 
 def plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16,
                      target_deg=5.0):
     """Plain swarm (the paper's 64 particles x 30 generations) against the workload's
-    gradient-refined swarm on the same frame(s), over seeds: final joint error, ms per frame
-    (graph replay), the evaluations each needs to reach a mean joint error of ``target_deg``
-    and those the refined swarm needs to reach the plain swarm's final error."""
+    gradient-refined swarm on the same frame(s), over seeds: final joint error and gbest cost
+    (beside the cost of the true pose), ms per frame (graph replay), the evaluations after
+    which the joint error stays at or below ``target_deg``, and those the refined swarm needs
+    to reach the plain swarm's final cost."""
     F = slots.numel()
     plain_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2)
     ref_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, refine_topk=cfg.refine_topk,
                           refine_steps=cfg.refine_steps)
     P, G = cfg.n_particles, cfg.n_generations
-    per_gen = {"plain": F * 64,
-               "refined": F * P + F * cfg.refine_topk * (1 + 4 * cfg.refine_steps)}
-    out = {"plain": {"particles": 64, "generations": 30, "err": [], "ms": [], "to_target": []},
-           "refined": {"particles": P, "generations": G, "err": [], "ms": [], "to_target": [],
-                       "evals_to_plain_err": []}}
+    per_gen = {"plain": 64,
+               "refined": P + cfg.refine_topk * (1 + 4 * cfg.refine_steps)}
+    true_cost = float(ctx.eval(torch.tensor(h_true[:, None, :], dtype=torch.float32,
+                                            device=slots.device), slots).cpu().numpy().mean())
+    out = {k: {"err": [], "cost": [], "ms": [], "to_target": []} for k in ("plain", "refined")}
+    out["refined"]["evals_to_plain_cost"] = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for s in range(seeds):
-        finals = {}
+        traces = {}
         for kind, n, gens, params in (("plain", 64, 30, plain_p), ("refined", P, G, ref_p)):
             sw = ctx.swarm(slots, n, lo, hi, seed=1000 + s)
             ctx.pso_run_graph(sw, params, gens)
@@ -120,41 +135,50 @@ def plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16
             e1.record()
             torch.cuda.synchronize()
             out[kind]["ms"].append(e0.elapsed_time(e1) / F)
-            errs = _errors_per_generation(ctx, sw, params, gens, h_true, cfg.n_hands)
-            finals[kind] = errs
+            errs, costs = _trace_generations(ctx, sw, params, gens, h_true, cfg.n_hands)
+            traces[kind] = costs
             out[kind]["err"].append(errs[-1])
-            hit = next((g for g, e in enumerate(errs) if e <= target_deg), None)
+            out[kind]["cost"].append(costs[-1])
+            hit = _first_staying(errs, target_deg)
             out[kind]["to_target"].append(None if hit is None else (hit + 1) * per_gen[kind])
-        plain_err = finals["plain"][-1]
-        hit = next((g for g, e in enumerate(finals["refined"]) if e <= plain_err), None)
-        out["refined"]["evals_to_plain_err"].append(None if hit is None
-                                                    else (hit + 1) * per_gen["refined"])
-    summary = {"seeds": seeds, "target_joint_error_deg": target_deg}
+        hit = next((g for g, c in enumerate(traces["refined"]) if c <= traces["plain"][-1]),
+                   None)
+        out["refined"]["evals_to_plain_cost"].append(None if hit is None
+                                                     else (hit + 1) * per_gen["refined"])
+    summary = {"seeds": seeds, "target_joint_error_deg": target_deg,
+               "cost_at_true_pose": true_cost, "evals_counted": "per frame"}
     for k, v in out.items():
         reached = [r for r in v["to_target"] if r is not None]
-        summary[k] = {"particles": v["particles"], "generations": v["generations"],
+        summary[k] = {"particles": 64 if k == "plain" else P,
+                      "generations": 30 if k == "plain" else G,
+                      "evals": per_gen[k] * (30 if k == "plain" else G),
                       "mean_joint_error_deg": float(np.mean(v["err"])),
                       "median_joint_error_deg": float(np.median(v["err"])),
+                      "mean_final_cost": float(np.mean(v["cost"])),
                       "ms_per_frame": float(np.mean(v["ms"])),
-                      "seeds_reaching_target": len(reached),
-                      "mean_evals_to_target": float(np.mean(reached)) if reached else None}
-    reached = [r for r in out["refined"]["evals_to_plain_err"] if r is not None]
-    summary["refined"]["seeds_reaching_plain_error"] = len(reached)
-    summary["refined"]["mean_evals_to_plain_error"] = float(np.mean(reached)) if reached else None
-    summary["plain"]["evals"] = 64 * 30
+                      "seeds_staying_within_target": len(reached),
+                      "mean_evals_to_stay_within_target":
+                          float(np.mean(reached)) if reached else None}
+    reached = [r for r in out["refined"]["evals_to_plain_cost"] if r is not None]
+    summary["refined"]["seeds_reaching_plain_cost"] = len(reached)
+    summary["refined"]["mean_evals_to_plain_cost"] = float(np.mean(reached)) if reached else None
     return summary
 
 
 def plain_seed_study(ctx, ht, torch, cfg, slots, lo, hi, h_true, seeds=32, reps=100):
-    """The plain swarm of the workload over seeds (final joint error, mean and median) and
-    the median of ``reps`` timed graph replays."""
+    """The plain swarm of the workload over seeds (final joint error, mean and median; final
+    gbest cost beside the cost of the true pose) and the median of ``reps`` timed graph
+    replays."""
     params = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2)
-    errs = []
+    errs, costs = [], []
     for s in range(seeds):
         sw = ctx.swarm(slots, cfg.n_particles, lo, hi, seed=2000 + s)
         ctx.pso_run_graph(sw, params, cfg.n_generations)
         errs.append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
                                     cfg.n_hands))
+        costs.append(float(sw["gbest_cost"].cpu().numpy().mean()))
+    true_cost = float(ctx.eval(torch.tensor(h_true[:, None, :], dtype=torch.float32,
+                                            device=slots.device), slots).cpu().numpy().mean())
     torch.cuda.synchronize()
     times = []
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -166,6 +190,7 @@ def plain_seed_study(ctx, ht, torch, cfg, slots, lo, hi, h_true, seeds=32, reps=
         times.append(ev[0].elapsed_time(ev[1]))
     return {"seeds": seeds, "mean_joint_error_deg": float(np.mean(errs)),
             "median_joint_error_deg": float(np.median(errs)),
+            "mean_final_cost": float(np.mean(costs)), "cost_at_true_pose": true_cost,
             "replays": reps, "median_ms_per_run": float(np.median(times))}
 
 

@@ -53,3 +53,13 @@ def test_measured_traffic_only_for_the_measured_kernel(monkeypatch):
     assert bench.measured_traffic(3) is None
     monkeypatch.setattr(bench, "MEASURED_TRAFFIC", {"0" * 64: rec})
     assert bench.measured_traffic(4) is None
+
+
+def test_first_staying_index():
+    """Evaluations to a target count from the generation after which the error stays below it."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench._first_staying([6.0, 4.0, 6.0, 4.5, 4.0], 5.0) == 3
+    assert bench._first_staying([4.0, 4.0], 5.0) == 0
+    assert bench._first_staying([4.0, 6.0], 5.0) is None
+    assert bench._first_staying([], 5.0) is None
