@@ -224,13 +224,28 @@ __device__ int block_scan(int* s_sum, int v, int* total) {
   return v + before;
 }
 
+// Tile counts of particles [i0, i0 + kSchedBatch) clipped to e, loaded together so that their
+// latencies overlap (the records were written by every XCD, so each load misses this L2).
+constexpr int kSchedBatch = 8;
+
+__device__ __forceinline__ void load_tiles(const Workspace& ws, int i0, int e,
+                                           int (&v)[kSchedBatch]) {
+#pragma unroll
+  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? ws.pinfo[i0 + j].n_tiles : 0;
+}
+
 __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& ws) {
   __shared__ int s_sum[kWavesPerBlock];
   const int t = threadIdx.x;
   const int chunk = (n_total + kBlock - 1) / kBlock;
   const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
   int tiles = 0;
-  for (int i = b; i < e; ++i) tiles += ws.pinfo[i].n_tiles;
+  for (int i0 = b; i0 < e; i0 += kSchedBatch) {
+    int v[kSchedBatch];
+    load_tiles(ws, i0, e, v);
+#pragma unroll
+    for (int j = 0; j < kSchedBatch; ++j) tiles += v[j];
+  }
   int total_tiles;
   block_scan(s_sum, tiles, &total_tiles);
   const long long target = (long long)a.grid * kItemsPerGroup;
@@ -241,19 +256,28 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   const int tpi = (int)max(min(lo, (long long)a.tiles_per_item), min(tq, (long long)a.tiles_per_item));
 
   int local = 0;
-  for (int i = b; i < e; ++i) {
-    const int n = (ws.pinfo[i].n_tiles + tpi - 1) / tpi;
-    ws.pinfo[i].n_items = n;
-    local += n;
+  for (int i0 = b; i0 < e; i0 += kSchedBatch) {
+    int v[kSchedBatch];
+    load_tiles(ws, i0, e, v);
+#pragma unroll
+    for (int j = 0; j < kSchedBatch; ++j) local += (v[j] + tpi - 1) / tpi;
   }
   int total_items;
   const int incl = block_scan(s_sum, local, &total_items);
   int off = incl - local;
-  for (int i = b; i < e; ++i) {
-    ws.item_off[i] = off;
-    const int n = ws.pinfo[i].n_items;
-    for (int j = 0; j < n; ++j) ws.item_map[off + j] = i;
-    off += n;
+  for (int i0 = b; i0 < e; i0 += kSchedBatch) {
+    int v[kSchedBatch];
+    load_tiles(ws, i0, e, v);
+#pragma unroll
+    for (int j = 0; j < kSchedBatch; ++j) {
+      const int i = i0 + j;
+      if (i >= e) break;
+      const int n = (v[j] + tpi - 1) / tpi;
+      ws.pinfo[i].n_items = n;
+      ws.item_off[i] = off;
+      for (int q = 0; q < n; ++q) ws.item_map[off + q] = i;
+      off += n;
+    }
   }
   if (t == 0) {
     ws.item_off[n_total] = total_items;
@@ -296,30 +320,56 @@ __device__ bool capsule_extent(const double* q0, const double* q1, double r,
 // ------------------------------------------------------------------------------------
 // forward kinematics prologue: one wavefront per particle (FP64 inside)
 
+// One primitive's model data (in type order: slot o holds primitive prim_order[o]).
+struct PrimIn {
+  int k, seg, type, root;
+  double frame[12];
+  double size[3];
+  double inv2[3];
+};
+
+__device__ __forceinline__ void load_prim(const DevModel* __restrict__ G, int o, PrimIn& q) {
+  const int k = G->prim_order[o];
+  q.k = k;
+  q.seg = G->prim_seg[k];
+  q.type = G->prim_type[k];
+  q.root = G->prim_root[k];
+  for (int i = 0; i < 12; ++i) q.frame[i] = G->prim_frame[k][i];
+  for (int i = 0; i < 3; ++i) {
+    q.size[i] = G->prim_size[k][i];
+    q.inv2[i] = G->prim_inv2[k][i];
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   __shared__ double s_T[kWavesPerBlock][HT_MAX_SEG][12];
   __shared__ double s_h[kWavesPerBlock][HT_MAX_DOF];
   __shared__ double s_sin[kWavesPerBlock][HT_MAX_DOF], s_cos[kWavesPerBlock][HT_MAX_DOF];
-  // the model tables, staged by one coalesced copy (the tree walk and the primitive set-up
-  // would otherwise wait on long chains of dependent global loads)
-  __shared__ __align__(16) DevModel s_model;
+  // the kinematic tables (everything before the primitive tables), staged by one coalesced
+  // copy: the tree walk would otherwise wait on long chains of dependent global loads.  The
+  // primitive tables are read from global memory by the lane that sets a primitive up,
+  // issued at the start so that their latency overlaps the trigonometry and the tree walk.
+  constexpr int kSegBytes = ((int)offsetof(DevModel, prim_type) + 15) / 16 * 16;
+  static_assert(kSegBytes <= (int)sizeof(DevModel), "copy stays inside the model");
+  __shared__ __align__(16) unsigned char s_model[kSegBytes];
   {
-    static_assert(sizeof(DevModel) % 4 == 0, "model copy in 4-byte words");
     const uint4* src4 = reinterpret_cast<const uint4*>(a.model);
-    uint4* dst4 = reinterpret_cast<uint4*>(&s_model);
-    const int n4 = (int)(sizeof(DevModel) / 16);
-    for (int i = threadIdx.x; i < n4; i += kBlock) dst4[i] = src4[i];
-    const uint32_t* src1 = reinterpret_cast<const uint32_t*>(a.model);
-    uint32_t* dst1 = reinterpret_cast<uint32_t*>(&s_model);
-    for (int i = n4 * 4 + threadIdx.x; i < (int)(sizeof(DevModel) / 4); i += kBlock)
-      dst1[i] = src1[i];
+    uint4* dst4 = reinterpret_cast<uint4*>(s_model);
+    for (int i = threadIdx.x; i < kSegBytes / 16; i += kBlock) dst4[i] = src4[i];
   }
-  const DevModel& M = s_model;
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  // only the members before prim_type may be read through M
+  const DevModel& M = *reinterpret_cast<const DevModel*>(s_model);
+  const DevModel* __restrict__ G = a.model;
+  // the wavefront index as a scalar, so that everything per particle below is wave-uniform
+  // (scalar instructions and branches)
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n_total = a.n_frames * a.n_particles;
   const int p = blockIdx.x * kWavesPerBlock + w;
   const bool active = p < n_total;
   const int n_dof = a.n_dof, n_seg = a.n_seg, n_prim = a.n_prim;
+  PrimIn pin0;
+  if (active && lane < n_prim) load_prim(G, lane, pin0);
 
   // every angle's sine and cosine at once (one lane per pose parameter), so the tree walk
   // below is trigonometry-free
@@ -434,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   __shared__ double s_kc[kWavesPerBlock][HT_MAX_KC];
   if (valid && lane >= kWave - HT_MAX_KC && lane - (kWave - HT_MAX_KC) < M.n_kc) {
     const int i = lane - (kWave - HT_MAX_KC);
-    s_kc[w][i] = fmax(-(s_h[w][M.kc_a[i]] - s_h[w][M.kc_b[i]]), 0.0);
+    s_kc[w][i] = fmax(-(s_h[w][G->kc_a[i]] - s_h[w][G->kc_b[i]]), 0.0);
   }
   __syncthreads();
 
@@ -447,17 +497,19 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   if (valid) {
     const FrameSlot fs = a.slots[slot];
     for (int o = lane; o < n_prim; o += kWave) {
-      const int k = M.prim_order[o];
-      const int s = M.prim_seg[k];
+      PrimIn pin;
+      if (o == lane) pin = pin0;
+      else load_prim(G, o, pin);
+      const int k = pin.k;
+      const int s = pin.seg;
       double F[12];
-      mul34(s_T[w][s], M.prim_frame[k], F);
-      const double* sz = M.prim_size[k];
-      const int typ = M.prim_type[k];
+      mul34(s_T[w][s], pin.frame, F);
+      const double* sz = pin.size;
+      const int typ = pin.type;
       float rec[kRec];
       for (int i = 0; i < kRec; ++i) rec[i] = 0.0f;
       const double c[3] = {F[3], F[7], F[11]};
       const double* T = s_T[w][s];
-      double lo3[3], hi3[3];
       split(c[0], rec[0], rec[4]);
       split(c[1], rec[1], rec[5]);
       split(c[2], rec[2], rec[6]);
@@ -465,19 +517,14 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       rec[13] = (float)(c[1] - T[7]);
       rec[14] = (float)(c[2] - T[11]);
       rec[15] = __int_as_float(s);
+      // the frame's columns are unit vectors to FP64 rounding, so the axis needs no
+      // normalisation
+      const double u[3] = {F[2], F[6], F[10]};
       if (typ == HT_SPHERE) {
-        const double r = sz[0];
-        rec[3] = (float)(r * r);
-        for (int i = 0; i < 3; ++i) {
-          lo3[i] = c[i] - r;
-          hi3[i] = c[i] + r;
-        }
+        rec[3] = (float)(sz[0] * sz[0]);
       } else if (typ == HT_CYLINDER || typ == HT_CONE) {
         // circular cylinder (radius r0) or truncated cone (radius r0 at s = 0, r1 at s = L)
         const double r0 = sz[0], L = sz[1], r1 = typ == HT_CONE ? sz[2] : sz[0];
-        double u[3] = {F[2], F[6], F[10]};
-        const double inu = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        for (int i = 0; i < 3; ++i) u[i] *= inu;
         rec[3] = typ == HT_CONE ? (float)r0 : (float)(r0 * r0);
         rec[7] = (float)L;
         rec[8] = (float)u[0];
@@ -485,19 +532,12 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
         rec[10] = (float)u[2];
         rec[11] = typ == HT_CONE ? (float)((r1 - r0) / L)
                                  : (float)(c[0] * u[0] + c[1] * u[1] + c[2] * u[2]);
-        // the solid is the convex hull of its two cap discs
-        for (int i = 0; i < 3; ++i) {
-          const double sn = sqrt(fmax(0.0, 1.0 - u[i] * u[i]));
-          const double c1 = c[i] + L * u[i];
-          lo3[i] = fmin(c[i] - r0 * sn, c1 - r1 * sn);
-          hi3[i] = fmax(c[i] + r0 * sn, c1 + r1 * sn);
-        }
       } else {
         // ellipsoid: Q = R diag(1/s^2) R^T with R the rotation part of F; elliptic cylinder:
         // the same without the axis term, Q = ex ex^T / a^2 + ey ey^T / b^2
         const bool ecyl = typ == HT_ECYLINDER;
-        const double inv[3] = {M.prim_inv2[k][0], ecyl ? M.prim_inv2[k][2] : M.prim_inv2[k][1],
-                               ecyl ? 0.0 : M.prim_inv2[k][2]};
+        const double inv[3] = {pin.inv2[0], ecyl ? pin.inv2[2] : pin.inv2[1],
+                               ecyl ? 0.0 : pin.inv2[2]};
         double Q[6] = {0, 0, 0, 0, 0, 0};
         for (int j = 0; j < 3; ++j) {
           const double r0 = F[0 * 4 + j], r1 = F[1 * 4 + j], r2 = F[2 * 4 + j];
@@ -515,83 +555,100 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
         rec[10] = (float)Q[4];
         rec[11] = (float)Q[5];
         if (ecyl) {
-          const double a = sz[0], L = sz[1], b = sz[2];
-          double u[3] = {F[2], F[6], F[10]};
-          const double inu = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-          for (int i = 0; i < 3; ++i) u[i] *= inu;
           rec[16] = (float)u[0];
           rec[17] = (float)u[1];
           rec[18] = (float)u[2];
-          rec[19] = (float)L;
-          for (int i = 0; i < 3; ++i) {
-            const double e = sqrt((F[i * 4 + 0] * a) * (F[i * 4 + 0] * a) +
-                                  (F[i * 4 + 1] * b) * (F[i * 4 + 1] * b));
-            const double c1 = c[i] + L * u[i];
-            lo3[i] = fmin(c[i], c1) - e;
-            hi3[i] = fmax(c[i], c1) + e;
-          }
-        } else {
-          for (int i = 0; i < 3; ++i) {
-            const double e = sqrt((F[i * 4 + 0] * sz[0]) * (F[i * 4 + 0] * sz[0]) +
-                                  (F[i * 4 + 1] * sz[1]) * (F[i * 4 + 1] * sz[1]) +
-                                  (F[i * 4 + 2] * sz[2]) * (F[i * 4 + 2] * sz[2]));
-            lo3[i] = c[i] - e;
-            hi3[i] = c[i] + e;
-          }
+          rec[19] = (float)sz[1];
         }
       }
       float4* dst = reinterpret_cast<float4*>(ws.recs + ((size_t)p * n_prim + k) * kRec);
       for (int i = 0; i < kRec / 4; ++i)
         dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
 
-      // conservative pixel box of the axis-aligned 3D box
+      // conservative pixel box of an axis-aligned 3D box of the solid, in FP32 (its rounding,
+      // about 1e-4 mm, is covered by a quarter-pixel pad)
+      float lo3[3], hi3[3];
+      {
+        const float cf[3] = {(float)c[0], (float)c[1], (float)c[2]};
+        const float uf[3] = {(float)u[0], (float)u[1], (float)u[2]};
+        const float s0 = (float)sz[0], s1 = (float)sz[1], s2 = (float)sz[2];
+        if (typ == HT_SPHERE) {
+          for (int i = 0; i < 3; ++i) {
+            lo3[i] = cf[i] - s0;
+            hi3[i] = cf[i] + s0;
+          }
+        } else if (typ == HT_CYLINDER || typ == HT_CONE) {
+          // the solid is the convex hull of its two cap discs
+          const float r1 = typ == HT_CONE ? s2 : s0;
+          for (int i = 0; i < 3; ++i) {
+            const float sn = sqrtf(fmaxf(0.0f, 1.0f - uf[i] * uf[i]));
+            const float c1 = fmaf(s1, uf[i], cf[i]);
+            lo3[i] = fminf(cf[i] - s0 * sn, c1 - r1 * sn);
+            hi3[i] = fmaxf(cf[i] + s0 * sn, c1 + r1 * sn);
+          }
+        } else {
+          const bool ecyl = typ == HT_ECYLINDER;
+          for (int i = 0; i < 3; ++i) {
+            const float f0 = (float)F[i * 4 + 0] * s0;
+            const float f1 = (float)F[i * 4 + 1] * (ecyl ? s2 : s1);
+            const float f2 = ecyl ? 0.0f : (float)F[i * 4 + 2] * s2;
+            const float e = sqrtf(fmaf(f0, f0, fmaf(f1, f1, f2 * f2)));
+            const float c1 = ecyl ? fmaf(s1, uf[i], cf[i]) : cf[i];
+            lo3[i] = fminf(cf[i], c1) - e;
+            hi3[i] = fmaxf(cf[i], c1) + e;
+          }
+        }
+      }
       int4 box;
-      if (!(lo3[2] > 1.0)) {
+      if (!(lo3[2] > 1.0f)) {
         box = make_int4(0, fs.W - 1, 0, fs.H - 1);
-      } else if (fs.bg > 0.0f && lo3[2] >= (double)fs.bg) {
+      } else if (fs.bg > 0.0f && lo3[2] >= fs.bg) {
         box = make_int4(1, 0, 1, 0);   // entirely behind the background plane
       } else {
-        const double izl = 1.0 / lo3[2], izh = 1.0 / hi3[2];
-        const double xmin = fmin(lo3[0] * izl, lo3[0] * izh);
-        const double xmax = fmax(hi3[0] * izl, hi3[0] * izh);
-        const double ymin = fmin(lo3[1] * izl, lo3[1] * izh);
-        const double ymax = fmax(hi3[1] * izl, hi3[1] * izh);
-        const double lim = 1.0e6;
-        const double u0 = fmin(fmax(floor(fs.cx + fs.fx * xmin), -1.0), lim);
-        const double u1 = fmin(fmax(ceil(fs.cx + fs.fx * xmax), -1.0), lim);
-        const double v0 = fmin(fmax(floor(fs.cy + fs.fy * ymin), -1.0), lim);
-        const double v1 = fmin(fmax(ceil(fs.cy + fs.fy * ymax), -1.0), lim);
+        const float izl = 1.0f / lo3[2], izh = 1.0f / hi3[2];
+        const float xmin = fminf(lo3[0] * izl, lo3[0] * izh);
+        const float xmax = fmaxf(hi3[0] * izl, hi3[0] * izh);
+        const float ymin = fminf(lo3[1] * izl, lo3[1] * izh);
+        const float ymax = fmaxf(hi3[1] * izl, hi3[1] * izh);
+        const float lim = 1.0e6f;
+        const float u0 = fminf(fmaxf(floorf(fmaf(fs.fx, xmin, fs.cx) - 0.25f), -1.0f), lim);
+        const float u1 = fminf(fmaxf(ceilf(fmaf(fs.fx, xmax, fs.cx) + 0.25f), -1.0f), lim);
+        const float v0 = fminf(fmaxf(floorf(fmaf(fs.fy, ymin, fs.cy) - 0.25f), -1.0f), lim);
+        const float v1 = fminf(fmaxf(ceilf(fmaf(fs.fy, ymax, fs.cy) + 0.25f), -1.0f), lim);
         box.x = max((int)u0, 0);
         box.y = min((int)u1, fs.W - 1);
         box.z = max((int)v0, 0);
         box.w = min((int)v1, fs.H - 1);
       }
       if (a.cull && box.x <= box.y && box.z <= box.w) {
-        // tighter: the exact image extent of a bounding capsule (segment q0-q1, radius cr).
-        // An ellipsoid with semi-axes a >= b >= c lies in the capsule along its a-axis from
+        // tighter: the exact image extent of a bounding capsule (segment q0-q1, radius cr),
+        // intersected with the box above (the capsule reaches past a cylinder's ends).  An
+        // ellipsoid with semi-axes a >= b >= c lies in the capsule along its a-axis from
         // -(a - b) to (a - b) with radius b.
         double q0[3], q1[3], cr;
         if (typ == HT_SPHERE) {
           for (int i = 0; i < 3; ++i) q0[i] = q1[i] = c[i];
           cr = sz[0];
         } else if (typ == HT_CYLINDER || typ == HT_CONE || typ == HT_ECYLINDER) {
-          const float* u = rec + (typ == HT_ECYLINDER ? 16 : 8);
           for (int i = 0; i < 3; ++i) {
             q0[i] = c[i];
-            q1[i] = c[i] + sz[1] * (double)u[i];
+            q1[i] = c[i] + sz[1] * u[i];
           }
           cr = typ == HT_CYLINDER ? sz[0] : fmax(sz[0], sz[2]);
         } else {
-          int ia = 0;
-          for (int i = 1; i < 3; ++i)
-            if (sz[i] > sz[ia]) ia = i;
-          double b2 = 0.0;
-          for (int i = 0; i < 3; ++i)
-            if (i != ia) b2 = fmax(b2, sz[i]);
-          const double hl = sz[ia] - b2;
+          // longest semi-axis ia (the first of equal ones) by selects, so that no array is
+          // indexed at run time
+          const double s0 = sz[0], s1 = sz[1], s2 = sz[2];
+          const int i01 = s1 > s0 ? 1 : 0;
+          const double m01 = i01 ? s1 : s0;
+          const int ia = s2 > m01 ? 2 : i01;
+          const double sa = ia == 2 ? s2 : m01;
+          const double b2 = ia == 0 ? fmax(s1, s2) : (ia == 1 ? fmax(s0, s2) : fmax(s0, s1));
+          const double hl = sa - b2;
           for (int i = 0; i < 3; ++i) {
-            q0[i] = c[i] - hl * F[i * 4 + ia];
-            q1[i] = c[i] + hl * F[i * 4 + ia];
+            const double ax = ia == 0 ? F[i * 4] : (ia == 1 ? F[i * 4 + 1] : F[i * 4 + 2]);
+            q0[i] = c[i] - hl * ax;
+            q1[i] = c[i] + hl * ax;
           }
           cr = b2;
         }
@@ -612,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
       if (box.x > box.y || box.z > box.w) box = make_int4(1, 0, 1, 0);
       ws.boxes[(size_t)p * n_prim + k] = box;
       if (box.x <= box.y) {
-        int* rq = s_rect[w][M.prim_root[k]];
+        int* rq = s_rect[w][pin.root];
         atomicMin(rq + 0, box.x);
         atomicMax(rq + 1, box.y);
         atomicMin(rq + 2, box.z);
@@ -621,7 +678,9 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
     }
   }
   __syncthreads();
-  if (active && lane == 0) {
+  if (active) {
+    // every lane computes the record from wave-uniform values (scalar instructions); lane 0
+    // stores it
     PInfo pi{};
     pi.slot = slot_ok ? slot : -1;
     pi.valid = valid ? 1 : 0;
@@ -629,49 +688,64 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
     double kc = 0.0;
     int kc_mask = 0;
     if (valid) {
-      for (int i = 0; i < M.n_kc; ++i) {
-        kc += s_kc[w][i];
-        kc_mask |= s_kc[w][i] > 0.0 ? 1 << i : 0;
+      // the terms are differences of FP32 values: their FP64 sum is exact in any order
+      const int n_kc = __builtin_amdgcn_readfirstlane(M.n_kc);
+#pragma unroll
+      for (int i = 0; i < HT_MAX_KC; ++i) {
+        const double v = i < n_kc ? s_kc[w][i] : 0.0;
+        kc += v;
+        kc_mask |= v > 0.0 ? 1 << i : 0;
       }
     }
     pi.kc = (float)kc;
     pi.kc_mask = kc_mask;
-    // one tile rectangle per tree, as (x0, y0, x1, y1) inclusive; merge overlapping ones so
-    // that no tile is visited twice
+    // one tile rectangle per tree, as (x0, y0, x1, y1) inclusive; overlapping ones are merged
+    // (into the lower index) so that no tile is visited twice.  Every index below is a
+    // compile-time constant, so the rectangles stay in registers.
     int4 R[kMaxRects];
-    int n = 0;
-    if (valid) {
+    bool live[kMaxRects];
 #pragma unroll
-      for (int r = 0; r < kMaxRects; ++r) {
-        const int* rr = s_rect[w][r];
-        if (rr[0] > rr[1]) continue;
-        R[n++] = make_int4(rr[0] / kTile, rr[2] / kTile, rr[1] / kTile, rr[3] / kTile);
-      }
+    for (int r = 0; r < kMaxRects; ++r) {
+      const int x0 = __builtin_amdgcn_readfirstlane(s_rect[w][r][0]);
+      const int x1 = __builtin_amdgcn_readfirstlane(s_rect[w][r][1]);
+      const int y0 = __builtin_amdgcn_readfirstlane(s_rect[w][r][2]);
+      const int y1 = __builtin_amdgcn_readfirstlane(s_rect[w][r][3]);
+      live[r] = valid && x0 <= x1;
+      R[r] = make_int4(x0 / kTile, y0 / kTile, x1 / kTile, y1 / kTile);
     }
-    bool merged = true;
-    while (merged) {
-      merged = false;
-      for (int i = 0; i < n && !merged; ++i) {
-        for (int j = i + 1; j < n && !merged; ++j) {
-          if (R[i].x <= R[j].z && R[j].x <= R[i].z && R[i].y <= R[j].w && R[j].y <= R[i].w) {
+    // a sweep without a merge is the fixed point; each earlier sweep merges at least once
+#pragma unroll
+    for (int sweep = 0; sweep < kMaxRects - 1; ++sweep) {
+#pragma unroll
+      for (int i = 0; i < kMaxRects; ++i) {
+#pragma unroll
+        for (int j = i + 1; j < kMaxRects; ++j) {
+          if (live[i] && live[j] && R[i].x <= R[j].z && R[j].x <= R[i].z &&
+              R[i].y <= R[j].w && R[j].y <= R[i].w) {
             R[i] = make_int4(min(R[i].x, R[j].x), min(R[i].y, R[j].y), max(R[i].z, R[j].z),
                              max(R[i].w, R[j].w));
-            R[j] = R[n - 1];
-            --n;
-            merged = true;
+            live[j] = false;
           }
         }
       }
     }
-    pi.n_rects = n;
-    pi.n_tiles = 0;
-    for (int i = 0; i < n; ++i) {
-      const int tw = R[i].z - R[i].x + 1, th = R[i].w - R[i].y + 1;
-      pi.rect[i] = make_int4(R[i].x, R[i].y, tw, th);
-      pi.n_tiles += tw * th;
+    int n = 0, nt = 0;
+#pragma unroll
+    for (int r = 0; r < kMaxRects; ++r) {
+      if (live[r]) {
+        const int tw = R[r].z - R[r].x + 1, th = R[r].w - R[r].y + 1;
+        const int4 q = make_int4(R[r].x, R[r].y, tw, th);
+#pragma unroll
+        for (int d = 0; d <= r; ++d)
+          if (d == n) pi.rect[d] = q;
+        ++n;
+        nt += tw * th;
+      }
     }
+    pi.n_rects = n;
+    pi.n_tiles = nt;
     pi.n_items = 0;   // set by the work-list kernel
-    ws.pinfo[p] = pi;
+    if (lane == 0) ws.pinfo[p] = pi;
   }
 }
 
