@@ -141,6 +141,8 @@ void free_workspace(ht_ctx* c) {
   invalidate_graphs(c);
   dfree(c->ws.recs);
   dfree(c->ws.boxes);
+  dfree(c->ws.caps);
+  dfree(c->ws.capr);
   dfree(c->ws.pinfo);
   dfree(c->ws.dof_frame);
   dfree(c->ws.seg_org);
@@ -179,6 +181,8 @@ ht_status ensure_workspace(ht_ctx* c, int n_total, int max_tiles, bool grad, hip
   auto& w = c->ws;
   HT_HIP(hipMalloc(&w.recs, (size_t)np * c->n_prim * ht::kRec * sizeof(float)));
   HT_HIP(hipMalloc(&w.boxes, (size_t)np * c->n_prim * sizeof(int4)));
+  HT_HIP(hipMalloc(&w.caps, (size_t)np * c->n_prim * sizeof(float4)));
+  HT_HIP(hipMalloc(&w.capr, (size_t)np * c->n_prim * sizeof(float2)));
   HT_HIP(hipMalloc(&w.pinfo, (size_t)np * sizeof(ht::PInfo)));
   HT_HIP(hipMalloc(&w.dof_frame, (size_t)np * c->n_dof * 8 * sizeof(float)));
   HT_HIP(hipMalloc(&w.seg_org, (size_t)np * c->n_seg * 4 * sizeof(float)));

@@ -102,6 +102,10 @@ struct Partial {
 struct Workspace {
   float* recs;           // [n_total][n_prim][kRec]
   int4* boxes;           // [n_total][n_prim] pixel box (u0, u1, v0, v1), empty = (1, 0, 1, 0)
+  float4* caps;          // [n_total][n_prim] image segment (x0, y0, dx, dy) of the bounding
+                         // capsule: the centres of its end spheres' image discs (pixels)
+  float2* capr;          // [n_total][n_prim] (1 / |(dx, dy)|^2 or 0, reach^2): a tile whose
+                         // centre lies farther than reach from the segment sees none of it
   PInfo* pinfo;          // [n_total]
   float* dof_frame;      // [n_total][n_dof][8]: kind, axis xyz, point xyz (camera frame)
   float* seg_org;        // [n_total][n_seg][4]

@@ -317,6 +317,30 @@ __device__ bool capsule_extent(const double* q0, const double* q1, double r,
   return true;
 }
 
+// Bounding disc of the image of a sphere (centre q, radius r, q.z > r): the image is an
+// ellipse whose major axis points away from the principal point and spans the normalised
+// radii tan(theta - alpha) .. tan(theta + alpha), theta being the angle of q from the optical
+// axis and sin(alpha) = r / |q|.  Its centre and semi-major axis, in pixels (the larger focal
+// length for the radius), give a disc that contains it.
+__device__ void sphere_image_disc(const double* q, double r, const FrameSlot& fs, float* D,
+                                  float& rho) {
+  const float X = (float)q[0], Y = (float)q[1], Z = (float)q[2], R = (float)r;
+  const float rad = sqrtf(fmaf(X, X, Y * Y));
+  const float inv_n = 1.0f / sqrtf(fmaf(rad, rad, Z * Z));
+  const float st = rad * inv_n, ct = Z * inv_n, sa = R * inv_n;
+  const float ca = sqrtf(fmaxf(0.0f, 1.0f - sa * sa));
+  const float tp = fmaf(st, ca, ct * sa) / fmaf(ct, ca, -st * sa);   // tan(theta + alpha)
+  const float tm = fmaf(st, ca, -ct * sa) / fmaf(ct, ca, st * sa);   // tan(theta - alpha)
+  const float m = 0.5f * (tp + tm), h = 0.5f * (tp - tm);
+  const float ex = rad > 0.0f ? X / rad : 1.0f, ey = rad > 0.0f ? Y / rad : 0.0f;
+  D[0] = fmaf(fs.fx, m * ex, fs.cx);
+  D[1] = fmaf(fs.fy, m * ey, fs.cy);
+  rho = h * fmaxf(fs.fx, fs.fy);
+}
+
+// Farthest pixel centre of an 8x8 tile from the tile's centre: 3.5 sqrt(2) pixels.
+constexpr float kTileHalfDiag = 4.9498f;
+
 // ------------------------------------------------------------------------------------
 // forward kinematics prologue: one wavefront per particle (FP64 inside)
 
@@ -620,6 +644,8 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
         box.z = max((int)v0, 0);
         box.w = min((int)v1, fs.H - 1);
       }
+      float4 cap = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      float2 capr = make_float2(0.0f, INFINITY);
       if (a.cull && box.x <= box.y && box.z <= box.w) {
         // tighter: the exact image extent of a bounding capsule (segment q0-q1, radius cr),
         // intersected with the box above (the capsule reaches past a cylinder's ends).  An
@@ -664,8 +690,22 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
           box.y = min(box.y, u1);
           box.z = max(box.z, v0);
           box.w = min(box.w, v1);
+          // the capsule's image is the convex hull of its end spheres' images, so it lies
+          // within the larger of their bounding discs' radii of the segment joining the
+          // discs' centres; a tile is reached when its centre is within that radius plus the
+          // tile's half-diagonal (padded for the FP32 rounding)
+          float D0[2], D1[2], r0, r1;
+          sphere_image_disc(q0, cr, fs, D0, r0);
+          sphere_image_disc(q1, cr, fs, D1, r1);
+          const float reach = fmaxf(r0, r1) * 1.0001f + kTileHalfDiag + 0.5f;
+          const float dx = D1[0] - D0[0], dy = D1[1] - D0[1];
+          const float vv = fmaf(dx, dx, dy * dy);
+          cap = make_float4(D0[0], D0[1], dx, dy);
+          capr = make_float2(vv > 0.0f ? 1.0f / vv : 0.0f, reach * reach);
         }
       }
+      ws.caps[(size_t)p * n_prim + k] = cap;
+      ws.capr[(size_t)p * n_prim + k] = capr;
       if (box.x > box.y || box.z > box.w) box = make_int4(1, 0, 1, 0);
       ws.boxes[(size_t)p * n_prim + k] = box;
       if (box.x <= box.y) {
@@ -1111,6 +1151,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
                                                       TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
   __shared__ int4 s_box[HT_MAX_PRIM];
+  __shared__ float4 s_cap[HT_MAX_PRIM];
+  __shared__ float2 s_capr[HT_MAX_PRIM];
   __shared__ int s_item;
   __shared__ PInfo s_pi;
   __shared__ double s_td[kWavesPerBlock];
@@ -1145,7 +1187,11 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
     if (p != cur_p) {
       const float4* src = reinterpret_cast<const float4*>(ws.recs + (size_t)p * n_prim * kRec);
       for (int i = tid; i < n_prim * (kRec / 4); i += kBlock) s_rec[i] = src[i];
-      for (int i = tid; i < n_prim; i += kBlock) s_box[i] = ws.boxes[(size_t)p * n_prim + i];
+      for (int i = tid; i < n_prim; i += kBlock) {
+        s_box[i] = ws.boxes[(size_t)p * n_prim + i];
+        s_cap[i] = ws.caps[(size_t)p * n_prim + i];
+        s_capr[i] = ws.capr[(size_t)p * n_prim + i];
+      }
       if (tid == 0) s_pi = ws.pinfo[p];
       cur_p = p;
       __syncthreads();
@@ -1165,7 +1211,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
     for (int t = c * tpi + wave; t < t_end; t += kWavesPerBlock, walk.step(kWavesPerBlock)) {
       const int tx = walk.tx(), ty = walk.ty();
       const int x0 = tx * kTile, y0 = ty * kTile;
-      // culling, one lane per primitive: screen box overlap
+      // culling, one lane per primitive: screen box overlap, then the distance of the tile's
+      // centre from the primitive's image segment
       uint64_t mk[2];
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
@@ -1174,6 +1221,14 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
         if (k < n_prim) {
           const int4 b = s_box[k];
           ov = b.x <= x0 + kTile - 1 && b.y >= x0 && b.z <= y0 + kTile - 1 && b.w >= y0;
+          if (ov) {
+            const float4 cp = s_cap[k];
+            const float2 cq = s_capr[k];
+            const float wx = (float)x0 + 3.5f - cp.x, wy = (float)y0 + 3.5f - cp.y;
+            const float sp = fminf(fmaxf(fmaf(wx, cp.z, wy * cp.w) * cq.x, 0.0f), 1.0f);
+            const float ex = fmaf(-sp, cp.z, wx), ey = fmaf(-sp, cp.w, wy);
+            ov = fmaf(ex, ex, ey * ey) <= cq.y;
+          }
         }
         mk[half] = __ballot(ov);
       }
