@@ -89,6 +89,8 @@ struct PInfo {
   int valid;                  // 0: non-finite pose or unset slot
   int skip;                   // 1: the particle's frame has stopped: nothing is written
   int kc_mask;                // collision pairs with a positive term (bit i: pair i)
+  double bg_td, bg_or;        // the observation's ROI-wide background sums (copied from its
+                              // slot, so the finalize kernels need no slot lookup)
 };
 
 struct Partial {

@@ -365,7 +365,7 @@ __device__ __forceinline__ void load_prim(const DevModel* __restrict__ G, int o,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
+__global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws) {
   __shared__ double s_T[kWavesPerBlock][HT_MAX_SEG][12];
   __shared__ double s_h[kWavesPerBlock][HT_MAX_DOF];
   __shared__ double s_sin[kWavesPerBlock][HT_MAX_DOF], s_cos[kWavesPerBlock][HT_MAX_DOF];
@@ -416,6 +416,13 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
   // a particle of a stopped frame (tracking stop rule) is neither cast nor written
   const bool skip = active && a.frame_stop && a.frame_stop[p / a.n_particles] != 0;
   const bool valid = slot_ok && finite && !skip;
+  // the slot's background sums, needed only by the record written at the end
+  double bg_td = 0.0, bg_or = 0.0;
+  if (valid) {
+    const double* tot = a.slots[slot].totals;
+    bg_td = tot[0];
+    bg_or = tot[1];
+  }
   __syncthreads();
 
   // segment transforms: every lane composes its own segment's chain (the ancestors' local
@@ -739,6 +746,8 @@ __global__ __launch_bounds__(kBlock) void fk_kernel(EvalArgs a, Workspace ws) {
     }
     pi.kc = (float)kc;
     pi.kc_mask = kc_mask;
+    pi.bg_td = bg_td;
+    pi.bg_or = bg_or;
     // one tile rectangle per tree, as (x0, y0, x1, y1) inclusive; overlapping ones are merged
     // (into the lower index) so that no tile is visited twice.  Every index below is a
     // compile-time constant, so the rectangles stay in registers.
@@ -1376,7 +1385,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 // S_d, S_and, S_or of a particle: the ROI's background totals plus its items' partials,
 // summed by the lanes of one wavefront.  Every depth term is a multiple of 2^-15 mm, so the
 // FP64 sums are exact and equal to any other summation order.
-__device__ inline void wave_partial_sums(const FrameSlot& fs, const Workspace& ws, int b, int e,
+__device__ inline void wave_partial_sums(const PInfo& pi, const Workspace& ws, int b, int e,
                                          int lane, double& S_d, long long& S_and,
                                          long long& S_or) {
   double d = 0.0;
@@ -1390,9 +1399,9 @@ __device__ inline void wave_partial_sums(const FrameSlot& fs, const Workspace& w
   d = wave_sum(d);
   sa = wave_sum(sa);
   so = wave_sum(so);
-  S_d = fs.totals[0] + d;
+  S_d = pi.bg_td + d;
   S_and = sa;
-  S_or = (long long)fs.totals[1] + so;
+  S_or = (long long)pi.bg_or + so;
 }
 
 // Eq. 4-5 from the sums (FP64).
@@ -1420,8 +1429,7 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace 
   }
   double S_d;
   long long S_and, S_or;
-  const int b = ws.item_off[p];
-  wave_partial_sums(a.slots[pi.slot], ws, b, b + pi.n_items, lane, S_d, S_and, S_or);
+  wave_partial_sums(pi, ws, ws.item_off[p], ws.item_off[p + 1], lane, S_d, S_and, S_or);
   if (lane == 0) a.cost[p] = cost_from_sums(S_d, S_and, S_or, pi.kc);
 }
 
@@ -1445,7 +1453,7 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
     for (int j = t; j < n_dof; j += kBlock) a.grad[(size_t)p * n_dof + j] = 0.0f;
     return;
   }
-  const int b = ws.item_off[p], e = b + pi.n_items;
+  const int b = ws.item_off[p], e = ws.item_off[p + 1];
   // segment origins and collision pairs staged for the adjoint below
   for (int i = t; i < n_seg * 4; i += kBlock) s_org[i] = ws.seg_org[(size_t)p * n_seg * 4 + i];
   if (t < HT_MAX_KC) {
@@ -1479,7 +1487,7 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   if (q == 0) {
     double S_d;
     long long S_and, S_or;
-    wave_partial_sums(a.slots[pi.slot], ws, b, e, lane, S_d, S_and, S_or);
+    wave_partial_sums(pi, ws, b, e, lane, S_d, S_and, S_or);
     if (lane == 0) {
       a.cost[p] = cost_from_sums(S_d, S_and, S_or, pi.kc);
       s_inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
@@ -1506,8 +1514,9 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
     const bool trans = f[0] != 0.0f;
     const double ax = f[1], ay = f[2], az = f[3];
     double g = 0.0;
-    for (int s = 0; s < n_seg; ++s) {
-      if (!((desc >> s) & 1u)) continue;
+    // the segments this parameter moves, in increasing order
+    for (uint32_t m = desc; m; m &= m - 1) {
+      const int s = __builtin_ctz(m);
       const double* W = s_W + s * 6;
       if (trans) {
         g += ax * W[3] + ay * W[4] + az * W[5];
