@@ -146,6 +146,7 @@ void free_workspace(ht_ctx* c) {
   dfree(c->ws.pinfo);
   dfree(c->ws.dof_frame);
   dfree(c->ws.seg_org);
+  dfree(c->ws.tiles);
   dfree(c->ws.item_off);
   dfree(c->ws.item_map);
   dfree(c->ws.partial);
@@ -186,6 +187,7 @@ ht_status ensure_workspace(ht_ctx* c, int n_total, int max_tiles, bool grad, hip
   HT_HIP(hipMalloc(&w.pinfo, (size_t)np * sizeof(ht::PInfo)));
   HT_HIP(hipMalloc(&w.dof_frame, (size_t)np * c->n_dof * 8 * sizeof(float)));
   HT_HIP(hipMalloc(&w.seg_org, (size_t)np * c->n_seg * 4 * sizeof(float)));
+  HT_HIP(hipMalloc(&w.tiles, (size_t)np * sizeof(int)));
   HT_HIP(hipMalloc(&w.item_off, (size_t)(np + 1) * sizeof(int)));
   HT_HIP(hipMalloc(&w.item_map, (size_t)ni * sizeof(int)));
   HT_HIP(hipMalloc(&w.partial, (size_t)ni * sizeof(ht::Partial)));

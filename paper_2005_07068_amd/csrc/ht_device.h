@@ -83,7 +83,6 @@ struct PInfo {
   int4 rect[kMaxRects];       // tx0, ty0, tw, th (tiles)
   int n_rects;
   int n_tiles;                // sum of the rectangles' tiles
-  int n_items;                // work items of the ray-cast kernel
   int slot;                   // observation slot (-1: unset slot)
   float kc;                   // collision term of Eq. 5
   int valid;                  // 0: non-finite pose or unset slot
@@ -111,6 +110,7 @@ struct Workspace {
   PInfo* pinfo;          // [n_total]
   float* dof_frame;      // [n_total][n_dof][8]: kind, axis xyz, point xyz (camera frame)
   float* seg_org;        // [n_total][n_seg][4]
+  int* tiles;            // [n_total] tiles of each particle (a compact copy for the scheduler)
   int* item_off;         // [n_total + 1]
   int* item_map;         // [max_items]
   Partial* partial;      // [max_items]

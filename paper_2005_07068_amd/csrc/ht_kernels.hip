@@ -225,13 +225,14 @@ __device__ int block_scan(int* s_sum, int v, int* total) {
 }
 
 // Tile counts of particles [i0, i0 + kSchedBatch) clipped to e, loaded together so that their
-// latencies overlap (the records were written by every XCD, so each load misses this L2).
+// latencies overlap (the counts were written by every XCD, so each load misses this L2).
 constexpr int kSchedBatch = 8;
+constexpr int kSchedWindow = 8192;   // items staged in LDS per round (32 KB)
 
 __device__ __forceinline__ void load_tiles(const Workspace& ws, int i0, int e,
                                            int (&v)[kSchedBatch]) {
 #pragma unroll
-  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? ws.pinfo[i0 + j].n_tiles : 0;
+  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? ws.tiles[i0 + j] : 0;
 }
 
 __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& ws) {
@@ -264,20 +265,50 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   }
   int total_items;
   const int incl = block_scan(s_sum, local, &total_items);
-  int off = incl - local;
+  const int my_b = incl - local, my_e = incl;   // this thread's items, contiguous
+  // item offsets: staged in LDS (then stored coalesced) when they fit
+  __shared__ int s_map[kSchedWindow];
+  const bool staged = n_total <= kSchedWindow;
+  int off = my_b;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
     int v[kSchedBatch];
     load_tiles(ws, i0, e, v);
 #pragma unroll
     for (int j = 0; j < kSchedBatch; ++j) {
-      const int i = i0 + j;
-      if (i >= e) break;
-      const int n = (v[j] + tpi - 1) / tpi;
-      ws.pinfo[i].n_items = n;
-      ws.item_off[i] = off;
-      for (int q = 0; q < n; ++q) ws.item_map[off + q] = i;
-      off += n;
+      if (i0 + j >= e) break;
+      if (staged) s_map[i0 + j] = off;
+      else ws.item_off[i0 + j] = off;
+      off += (v[j] + tpi - 1) / tpi;
     }
+  }
+  if (staged) {
+    __syncthreads();
+    for (int i = t; i < n_total; i += kBlock) ws.item_off[i] = s_map[i];
+    __syncthreads();
+  }
+  // the item -> particle map, staged in LDS one window at a time so that the global stores
+  // are coalesced (each thread's items are contiguous, so its own stores would touch one
+  // cache line per lane)
+  for (int w0 = 0; w0 < total_items; w0 += kSchedWindow) {
+    const int w1 = min(w0 + kSchedWindow, total_items);
+    if (my_b < w1 && my_e > w0) {
+      int o = my_b;
+      for (int i0 = b; i0 < e && o < w1; i0 += kSchedBatch) {
+        int v[kSchedBatch];
+        load_tiles(ws, i0, e, v);
+#pragma unroll
+        for (int j = 0; j < kSchedBatch; ++j) {
+          if (i0 + j >= e) break;
+          const int n = (v[j] + tpi - 1) / tpi;
+          const int q0 = max(o, w0), q1 = min(o + n, w1);
+          for (int q = q0; q < q1; ++q) s_map[q - w0] = i0 + j;
+          o += n;
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = w0 + t; q < w1; q += kBlock) ws.item_map[q] = s_map[q - w0];
+    __syncthreads();
   }
   if (t == 0) {
     ws.item_off[n_total] = total_items;
@@ -793,8 +824,10 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
     }
     pi.n_rects = n;
     pi.n_tiles = nt;
-    pi.n_items = 0;   // set by the work-list kernel
-    if (lane == 0) ws.pinfo[p] = pi;
+    if (lane == 0) {
+      ws.pinfo[p] = pi;
+      ws.tiles[p] = nt;
+    }
   }
 }
 
