@@ -59,6 +59,14 @@ __device__ __forceinline__ float wave_total(float v) {
   const float r3 = __int_as_float(__builtin_amdgcn_readlane(b, 48));
   return (r0 + r1) + (r2 + r3);
 }
+// Row total: after the same four DPP steps every lane holds the sum over its 16-lane row.
+__device__ __forceinline__ float row_total(float v) {
+  v += __int_as_float(dpp<0xB1>(__float_as_int(v)));
+  v += __int_as_float(dpp<0x4E>(__float_as_int(v)));
+  v += __int_as_float(dpp<0x124>(__float_as_int(v)));
+  v += __int_as_float(dpp<0x128>(__float_as_int(v)));
+  return v;
+}
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
   int x = (int)v;
   x |= dpp<0xB1>(x);
@@ -1199,7 +1207,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
   __shared__ PInfo s_pi;
   __shared__ double s_td[kWavesPerBlock];
   __shared__ int s_a[kWavesPerBlock], s_o[kWavesPerBlock];
-  __shared__ float s_wr[GRAD ? kWavesPerBlock : 1][GRAD ? HT_MAX_SEG : 1][6];
+  // gradient: per wavefront, segment and 16-lane row, the six wrench components of the item
+  __shared__ float s_wr[GRAD ? kWavesPerBlock : 1][GRAD ? HT_MAX_SEG : 1][GRAD ? 4 : 1][6];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   const int n_prim = a.n_prim, n_seg = a.n_seg;
@@ -1240,7 +1249,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       fs = uni(a.slots[uni(s_pi.slot)]);
     }
     if (GRAD) {
-      for (int i = lane; i < n_seg * 6; i += kWave) s_wr[wave][i / 6][i % 6] = 0.0f;
+      float* wr = &s_wr[wave][0][0][0];
+      for (int i = lane; i < n_seg * 24; i += kWave) wr[i] = 0.0f;
     }
     const int c = item - uni(ws.item_off[p]);
     const int t_end = min((c + 1) * tpi, uni(pi.n_tiles));
@@ -1366,7 +1376,10 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
           mz = kap * (lx * wny - ly * wnx);
         }
         const float fx = kap * wnx, fy = kap * wny, fz = kap * wnz;
-        // segments present in this tile, reduced one at a time (uniform loop)
+        // segments present in this tile, one at a time (uniform loop): row sums on the
+        // vector unit, added by the first lane of each row into that row's accumulators (an
+        // LDS atomic add without return; the four lanes hit distinct addresses and the adds of
+        // a wavefront are applied in program order, so the result is deterministic)
         uint32_t segmask = wave_or(act ? (1u << seg) : 0u);
         while (segmask) {
           const int s = __builtin_ctz(segmask);
@@ -1376,10 +1389,11 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
                                  mine ? fx : 0.f, mine ? fy : 0.f, mine ? fz : 0.f};
           float sum[6];
 #pragma unroll
-          for (int q = 0; q < 6; ++q) sum[q] = wave_total(vals[q]);
-          if (lane == 0) {
+          for (int q = 0; q < 6; ++q) sum[q] = row_total(vals[q]);
+          if ((lane & 15) == 0) {
+            float* dst = &s_wr[wave][s][lane >> 4][0];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) s_wr[wave][s][q] += sum[q];
+            for (int q = 0; q < 6; ++q) atomicAdd(dst + q, sum[q]);
           }
         }
       }
@@ -1405,8 +1419,11 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
     if (GRAD) {
       for (int i = tid; i < n_seg * 6; i += kBlock) {
         const int s = i / 6, q = i % 6;
-        ws.wrench[(size_t)item * n_seg * 6 + i] =
-            ((s_wr[0][s][q] + s_wr[1][s][q]) + s_wr[2][s][q]) + s_wr[3][s][q];
+        float v = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w)
+          v += (s_wr[w][s][0][q] + s_wr[w][s][1][q]) + (s_wr[w][s][2][q] + s_wr[w][s][3][q]);
+        ws.wrench[(size_t)item * n_seg * 6 + i] = v;
       }
     }
   }
