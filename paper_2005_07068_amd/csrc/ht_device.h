@@ -35,6 +35,7 @@ constexpr uint32_t kValidBit = 1u << 17;
 struct DevModel {
   int n_dof, n_seg, n_prim, n_kc;
   int max_depth;
+  int n_roots;                           // independent kinematic trees (hands), <= kMaxRects
   int seg_parent[HT_MAX_SEG];
   int seg_root_dof[HT_MAX_SEG];
   int seg_depth[HT_MAX_SEG];
@@ -50,7 +51,6 @@ struct DevModel {
   int kc_a[HT_MAX_KC], kc_b[HT_MAX_KC];
   uint32_t dof_desc[HT_MAX_DOF];         // segments moved by each pose parameter
   int dof_trans[HT_MAX_DOF];             // 1 for the wrist translations (mm), else angle
-  int n_roots;                           // independent kinematic trees (hands)
   int prim_root[HT_MAX_PRIM];            // tree of each primitive
   int prim_order[HT_MAX_PRIM];           // primitive indices sorted by type
   double prim_inv2[HT_MAX_PRIM][3];      // 1 / size^2 (ellipsoid semi-axes)

@@ -801,13 +801,18 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
       live[r] = valid && x0 <= x1;
       R[r] = make_int4(x0 / kTile, y0 / kTile, x1 / kTile, y1 / kTile);
     }
-    // a sweep without a merge is the fixed point; each earlier sweep merges at least once
+    // a sweep without a merge is the fixed point; each earlier sweep merges at least once.
+    // Only the model's trees can hold rectangles (a one-hand model needs no merge, two hands
+    // one pair test per sweep); the bounds are wave-uniform, so the skipped tests cost nothing.
+    const int nr = M.n_roots;
 #pragma unroll
     for (int sweep = 0; sweep < kMaxRects - 1; ++sweep) {
+      if (sweep + 1 >= nr) break;
 #pragma unroll
       for (int i = 0; i < kMaxRects; ++i) {
 #pragma unroll
         for (int j = i + 1; j < kMaxRects; ++j) {
+          if (j >= nr) break;
           if (live[i] && live[j] && R[i].x <= R[j].z && R[j].x <= R[i].z &&
               R[i].y <= R[j].w && R[j].y <= R[i].w) {
             R[i] = make_int4(min(R[i].x, R[j].x), min(R[i].y, R[j].y), max(R[i].z, R[j].z),

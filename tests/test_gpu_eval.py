@@ -76,6 +76,30 @@ def test_debug_and_plain_costs_identical_and_deterministic():
         assert np.allclose(c3, c1, rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("prims", ["cylinders", "paper"])
+def test_culling_is_conservative_on_two_hand_frames(prims):
+    """640x480, two hands: launches with and without the capsule culling (image extent and
+    image-segment reach) give bit-identical costs and per-pixel images, near the true pose and
+    far from it."""
+    torch_cuda()
+    cfg, model, fr = frame_for(4, primitive_set=prims)
+    near = particles_for(model, fr, 12, seed=9)
+    far = particles_for(model, fr, 6, seed=10, angle_deg=40.0, trans_mm=80.0)
+    poses = np.concatenate([near, far])
+    ctx = make_ctx(model, [fr])
+    H, W = fr["depth"].shape
+    out = {}
+    for cull in (0, 1):
+        ctx.set_launch_config(16, 4, cull)
+        out[cull] = eval_debug(ctx, poses, 0, W, H)
+    ctx.close()
+    (c0, d0), (c1, d1) = out[0], out[1]
+    assert np.array_equal(c0, c1)
+    for k in ("depth", "hit", "rm", "winner"):
+        assert np.array_equal(d0[k], d1[k]), k
+    assert d1["hit"].any()
+
+
 def test_nonfinite_pose_unset_slot_and_empty_call():
     torch = torch_cuda()
     cfg, model, fr = frame_for(0)
