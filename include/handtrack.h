@@ -47,13 +47,13 @@ typedef enum {
   HT_ERR_STATE = -2,        /* call before set_model / set_observation, unset frame slot   */
   HT_ERR_OOM = -3,          /* device allocation failed                                    */
   HT_ERR_HIP = -4,          /* a HIP runtime call failed (message names it)                */
-  HT_ERR_UNSUPPORTED = -5   /* valid request outside what this build supports              */
+  HT_ERR_UNSUPPORTED = -5   /* valid request outside what this library supports            */
 } ht_status;
 
 enum { HT_SPHERE = 0, HT_CYLINDER = 1, HT_ELLIPSOID = 2, HT_CONE = 3, HT_ECYLINDER = 4 };
 enum { HT_PTR_HOST = 0, HT_PTR_DEVICE = 1 };
 
-/* Limits of this build. */
+/* Limits of this library. */
 #define HT_MAX_DOF 64
 #define HT_MAX_SEG 32
 #define HT_MAX_PRIM 128

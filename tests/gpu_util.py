@@ -1,5 +1,5 @@
 """Shared helpers of the GPU parity tests: contexts, seeded frames and the resolved-oracle
-comparison of the spec bar (exact masks outside margin < 1e-5 pixels, 1e-3 mm depths,
+comparison of the parity bar (exact masks outside margin < 1e-5 pixels, 1e-3 mm depths,
 1e-5 relative costs)."""
 from __future__ import annotations
 

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def test_fwd64_parity_masks_depths_costs():
-    """configs[0] shape: 64x64, 40 primitives, 16 particles around the true pose."""
+    """64x64 workload: 40 primitives, 16 particles around the true pose."""
     cfg, model, fr = frame_for(0)
     poses = particles_for(model, fr, cfg.n_particles, seed=1)
     poses[0] = fr["h_true"].astype(np.float32)
@@ -121,7 +121,7 @@ def test_nonfinite_pose_unset_slot_and_empty_call():
 
 
 def test_batched_frames_equal_per_frame_calls():
-    """configs[3] shape: uneven ROIs in one launch == one call per frame (bit-identical)."""
+    """64 frames of uneven ROIs (48..192 px): one launch == one call per frame (bit-identical)."""
     torch = torch_cuda()
     cfg = CONFIGS[3]
     model = make_hand_model(seed_sequence(3, 10_000))
@@ -144,7 +144,7 @@ def test_batched_frames_equal_per_frame_calls():
 
 
 def test_full_size_adjoint_shape_sampled_particles():
-    """configs[2] shape (320x240, 256 particles): every cost computed, 6 sampled vs oracle."""
+    """320x240 workload (256 particles): every cost computed, 6 sampled vs oracle."""
     cfg, model, fr = frame_for(2)
     poses = particles_for(model, fr, cfg.n_particles, seed=11)
     ctx = make_ctx(model, [fr])
@@ -155,7 +155,7 @@ def test_full_size_adjoint_shape_sampled_particles():
 
 
 def test_full_frame_two_hands_sampled_particles():
-    """configs[4] shape: 640x480, two hands (80 primitives, 52-D), 1024 particles."""
+    """640x480 workload: two hands (80 primitives, 52-D), 1024 particles."""
     cfg, model, fr = frame_for(4)
     poses = particles_for(model, fr, cfg.n_particles, seed=12)
     ctx = make_ctx(model, [fr])
