@@ -211,6 +211,7 @@ constexpr int kItemsPerGroup = 1;
 // Inclusive scan over the workgroup; every thread gets its own prefix and the total: a scan
 // within each wavefront by lane shifts, then the wavefront totals through LDS (two barriers
 // instead of two per doubling step).
+template <int NW>
 __device__ int block_scan(int* s_sum, int v, int* total) {
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
 #pragma unroll
@@ -222,7 +223,7 @@ __device__ int block_scan(int* s_sum, int v, int* total) {
   __syncthreads();
   int before = 0, all = 0;
 #pragma unroll
-  for (int q = 0; q < kWavesPerBlock; ++q) {
+  for (int q = 0; q < NW; ++q) {
     const int w = s_sum[q];
     before += q < wv ? w : 0;
     all += w;
@@ -235,6 +236,7 @@ __device__ int block_scan(int* s_sum, int v, int* total) {
 // Tile counts of particles [i0, i0 + kSchedBatch) clipped to e, loaded together so that their
 // latencies overlap (the counts were written by every XCD, so each load misses this L2).
 constexpr int kSchedBatch = 8;
+constexpr int kSchedBlock = 1024;    // threads of the work-list kernel (its only workgroup)
 constexpr int kSchedWindow = 8192;   // items staged in LDS per round (32 KB)
 
 __device__ __forceinline__ void load_tiles(const Workspace& ws, int i0, int e,
@@ -244,9 +246,10 @@ __device__ __forceinline__ void load_tiles(const Workspace& ws, int i0, int e,
 }
 
 __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& ws) {
-  __shared__ int s_sum[kWavesPerBlock];
+  constexpr int kNW = kSchedBlock / kWave;
+  __shared__ int s_sum[kNW];
   const int t = threadIdx.x;
-  const int chunk = (n_total + kBlock - 1) / kBlock;
+  const int chunk = (n_total + kSchedBlock - 1) / kSchedBlock;
   const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
   int tiles = 0;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
@@ -256,7 +259,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
     for (int j = 0; j < kSchedBatch; ++j) tiles += v[j];
   }
   int total_tiles;
-  block_scan(s_sum, tiles, &total_tiles);
+  block_scan<kNW>(s_sum, tiles, &total_tiles);
   const long long target = (long long)a.grid * kItemsPerGroup;
   long long tq = ((long long)total_tiles + target - 1) / target;
   tq = (tq + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
@@ -272,7 +275,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
     for (int j = 0; j < kSchedBatch; ++j) local += (v[j] + tpi - 1) / tpi;
   }
   int total_items;
-  const int incl = block_scan(s_sum, local, &total_items);
+  const int incl = block_scan<kNW>(s_sum, local, &total_items);
   const int my_b = incl - local, my_e = incl;   // this thread's items, contiguous
   // item offsets: staged in LDS (then stored coalesced) when they fit
   __shared__ int s_map[kSchedWindow];
@@ -291,7 +294,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   }
   if (staged) {
     __syncthreads();
-    for (int i = t; i < n_total; i += kBlock) ws.item_off[i] = s_map[i];
+    for (int i = t; i < n_total; i += kSchedBlock) ws.item_off[i] = s_map[i];
     __syncthreads();
   }
   // the item -> particle map, staged in LDS one window at a time so that the global stores
@@ -315,7 +318,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
       }
     }
     __syncthreads();
-    for (int q = w0 + t; q < w1; q += kBlock) ws.item_map[q] = s_map[q - w0];
+    for (int q = w0 + t; q < w1; q += kSchedBlock) ws.item_map[q] = s_map[q - w0];
     __syncthreads();
   }
   if (t == 0) {
@@ -847,7 +850,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
 // The work list is built by its own one-workgroup launch: folding it into the kinematics
 // kernel as "the last workgroup to finish builds it" needs a device-scope fence in every
 // workgroup, which on a multi-XCD part (one L2 per XCD) costs far more than a launch.
-__global__ __launch_bounds__(kBlock) void sched_kernel(EvalArgs a, Workspace ws) {
+__global__ __launch_bounds__(kSchedBlock) void sched_kernel(EvalArgs a, Workspace ws) {
   schedule_items(a, a.n_frames * a.n_particles, ws);
 }
 
@@ -1610,7 +1613,7 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
                          dim3(kBlock), 0, s, a, ws);
       break;
     case kStageSched:
-      hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kBlock), 0, s, a, ws);
+      hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kSchedBlock), 0, s, a, ws);
       if (dbg) {
         const size_t n = (size_t)a.n_particles * a.dbg_H * a.dbg_W;
         hipLaunchKernelGGL(debug_fill_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
