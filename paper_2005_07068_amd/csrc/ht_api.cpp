@@ -267,8 +267,12 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.cull = c->lc.cull;
   const long long bound = (long long)n_total *
                           ((c->max_tiles() + kMinTilesPerItem - 1) / kMinTilesPerItem);
-  a.grid = (int)std::max<long long>(1, std::min<long long>((long long)c->n_cu * c->lc.groups_per_cu,
-                                                           bound));
+  const bool dbg_on = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner;
+  const bool all_types = (c->tmask.m[HT_CONE][0] | c->tmask.m[HT_CONE][1] |
+                          c->tmask.m[HT_ECYLINDER][0] | c->tmask.m[HT_ECYLINDER][1]) != 0ull;
+  const int gpc = std::min(c->lc.groups_per_cu,
+                           ht::raycast_groups_per_cu(grad != nullptr, dbg_on, all_types));
+  a.grid = (int)std::max<long long>(1, std::min<long long>((long long)c->n_cu * gpc, bound));
   a.n_prim = c->n_prim;
   a.n_seg = c->n_seg;
   a.n_dof = c->n_dof;

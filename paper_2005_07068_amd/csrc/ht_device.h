@@ -145,6 +145,7 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
                                    int* tile_skin, double* totals, float bg, hipStream_t s);
 enum { kStageFk = 0, kStageSched = 1, kStageRaycast = 2, kStageFinalize = 3, kNumStages = 4 };
 hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s);
+int raycast_groups_per_cu(bool grad, bool dbg, bool all_types);
 hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s);
 int preprocess_partials(int W, int H);
 hipError_t launch_preprocess(int W, int H, const uint8_t* rgb, const uint16_t* depth,

@@ -1601,6 +1601,35 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
 
 // ------------------------------------------------------------------------------------
 
+// Workgroups of a ray-cast variant that are resident on one CU at once (its registers and
+// LDS decide).  The persistent grid is capped at this many per CU: a workgroup beyond it
+// starts only when another has finished, and its statically assigned first item then
+// finishes late (a 128-particle launch spent half its time in that tail).
+int raycast_groups_per_cu(bool grad, bool dbg, bool all_types) {
+  static int cache[2][2][2] = {};
+  int& n = cache[grad][dbg][all_types];
+  if (n > 0) return n;
+  const void* f;
+  if (all_types) {
+    f = grad ? (dbg ? reinterpret_cast<const void*>(&raycast_kernel<true, true, kNumTypes>)
+                    : reinterpret_cast<const void*>(&raycast_kernel<true, false, kNumTypes>))
+             : (dbg ? reinterpret_cast<const void*>(&raycast_kernel<false, true, kNumTypes>)
+                    : reinterpret_cast<const void*>(&raycast_kernel<false, false, kNumTypes>));
+  } else {
+    f = grad ? (dbg ? reinterpret_cast<const void*>(&raycast_kernel<true, true, 3>)
+                    : reinterpret_cast<const void*>(&raycast_kernel<true, false, 3>))
+             : (dbg ? reinterpret_cast<const void*>(&raycast_kernel<false, true, 3>)
+                    : reinterpret_cast<const void*>(&raycast_kernel<false, false, 3>));
+  }
+  int r = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, f, kBlock, 0) != hipSuccess || r < 1) {
+    (void)hipGetLastError();
+    r = 1;
+  }
+  n = r;
+  return n;
+}
+
 // The evaluation is four launches on one stream; `stage` selects one so the host can
 // bracket each with HIP events when profiling.
 hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s) {
