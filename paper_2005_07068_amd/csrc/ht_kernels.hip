@@ -199,8 +199,9 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
 }
 
 // ------------------------------------------------------------------------------------
-// work list, built by one workgroup of kBlock threads.  The tiles per work item are chosen
-// from the launch's actual tile count: about kItemsPerGroup items per persistent workgroup,
+// work list, built by one workgroup of kSchedBlock threads.  The tiles per work item are
+// chosen from the launch's actual tile count: about kItemsPerGroup items per persistent
+// workgroup (more, smaller items measured slower: each item stages its particle's tables),
 // a multiple of the wavefronts per workgroup, at least kFloorTilesFwd (kFloorTilesGrad for
 // a gradient) and at most the configured tiles_per_item (itself >= kMinTilesPerItem, which
 // sizes the workspace).  An exclusive scan of the per-particle item counts then gives the
