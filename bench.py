@@ -448,6 +448,61 @@ def cpu_baseline(model, frames, poses, budget_s):
                       f"(FP64 NumPy oracle, one process per core, {dt:.1f} s)"}
 
 
+def oracle_timing(cores_cap=16):
+    """The oracle as it stands on the host cores, per workload: the single-core rate on a small
+    sample and the all-core rate (one process per core, at most 16) on the full run where that
+    takes seconds -- workload 0's 16 evaluations, one whole 64 x 30 PSO run of workload 1 (each
+    generation's evaluations spread over the cores, the swarm update on the main process) and
+    workload 2's 256 evaluations -- and on a timed sample of 64 evaluations of workloads 3 (one
+    particle per frame) and 4."""
+    import multiprocessing as mp
+
+    from oracle import pso as opso
+    from workload.handmodel import init_halfwidth
+    cores = min(len(os.sched_getaffinity(0)), cores_cap)
+    out = {"cores": cores, "unit": "particle evals/s", "kind": "oracle", "workloads": {}}
+    with mp.get_context("fork").Pool(cores) as pool:
+        for idx in (0, 1, 2, 3, 4):
+            cfg, model, frames, _, _ = load_workload(idx)
+            lo_b, hi_b = model["bounds_lo"], model["bounds_hi"]
+            d = init_halfwidth(model["n_dof"], cfg.init_angle_deg, cfg.init_trans_mm)
+            lo = [np.clip(fr["h_true"] - d, lo_b, hi_b) for fr in frames]
+            hi = [np.clip(fr["h_true"] + d, lo_b, hi_b) for fr in frames]
+            P = cfg.n_particles
+            st = opso.init_state(lo, hi, P, 2005_07068)
+            jobs = [(model, frames[f], st["x"][f][i]) for f in range(len(frames)) for i in range(P)]
+            n1 = 2 if idx == 4 else 8
+            t = time.perf_counter()
+            for j in jobs[:n1]:
+                _oracle_eval(j)
+            single = n1 / (time.perf_counter() - t)
+            rec = {"workload": cfg.name, "single_core": single, "single_core_sample": n1}
+            log(f"oracle timing, workload {idx}: single core {single:.3g} evals/s")
+            if idx == 1:
+                params = opso.PsoParams(w=cfg.w, c1=cfg.c1, c2=cfg.c2)
+                t = time.perf_counter()
+                for _ in range(cfg.n_generations):
+                    c = pool.map(_oracle_eval, [(model, frames[0], st["x"][0][i]) for i in range(P)],
+                                 chunksize=1)
+                    st = opso.update(st, np.array([c]), params, lo_b, hi_b, model["mutate_mask"],
+                                     2005_07068)
+                dt = time.perf_counter() - t
+                n = P * cfg.n_generations
+                rec.update(all_cores=n / dt, all_cores_evals=n,
+                           all_cores_run=f"one {P} x {cfg.n_generations} PSO run, {dt:.1f} s")
+            else:
+                sample = jobs if idx in (0, 2) else (jobs[::P] if idx == 3 else jobs[:64])
+                t = time.perf_counter()
+                pool.map(_oracle_eval, sample, chunksize=1)
+                dt = time.perf_counter() - t
+                kind = "full run" if idx in (0, 2) else "timed sample"
+                rec.update(all_cores=len(sample) / dt, all_cores_evals=len(sample),
+                           all_cores_run=f"{kind}: {len(sample)} evaluations, {dt:.1f} s")
+            log(f"oracle timing, workload {idx}: all cores {rec['all_cores']:.3g} evals/s")
+            out["workloads"][str(idx)] = rec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -466,6 +521,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the CPU oracle on every workload (own JSON line)")
     ap.add_argument("--launch-config", default=None,
                     help="tiles_per_item,groups_per_cu,cull; skips the autotuner")
     args = ap.parse_args()
@@ -475,6 +532,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.oracle_timing:
+        print(json.dumps({"oracle_timing": oracle_timing()}), flush=True)
+        return
     if args.config == 2:
         import torch
 
