@@ -468,20 +468,29 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   }
   __syncthreads();
 
-  // segment transforms: every lane composes its own segment's chain (the ancestors' local
-  // transforms, right to left, then the wrist), so no level-by-level synchronisation is
-  // needed; the tree is shallow (palm and three phalanges)
-  if (valid && lane < n_seg) {
-    double P[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};   // ancestors below the root
+  // segment transforms, T_s = W L_root ... L_parent(s) L_s with L_s = Off_s Rot(a1, q1)
+  // Rot(a2, q2) and W the wrist of s's tree: every lane forms its own L_s once and stages it
+  // in LDS, then multiplies its ancestors' staged transforms right to left (the tree is
+  // shallow: palm and three phalanges), so no joint rotation is computed twice.
+  __shared__ double s_L[kWavesPerBlock][HT_MAX_SEG][12];
+  const bool seg_lane = valid && lane < n_seg;
+  if (seg_lane) {
+    double Lm[12];
+    for (int i = 0; i < 12; ++i) Lm[i] = M.seg_off[lane][i];
+    for (int j = 0; j < 2; ++j) {
+      const int dof = M.seg_dof[lane][j];
+      if (dof >= 0) post_rotate(Lm, M.seg_axis[lane][j], s_sin[w][dof], s_cos[w][dof]);
+    }
+    for (int i = 0; i < 12; ++i) s_L[w][lane][i] = Lm[i];
+  }
+  __syncthreads();
+  if (seg_lane) {
+    double P[12];
+    for (int i = 0; i < 12; ++i) P[i] = s_L[w][lane][i];
     int q = M.seg_parent[lane], root = lane;
     while (q >= 0) {
-      double L[12], Q[12];
-      for (int i = 0; i < 12; ++i) L[i] = M.seg_off[q][i];
-      for (int j = 0; j < 2; ++j) {
-        const int dof = M.seg_dof[q][j];
-        if (dof >= 0) post_rotate(L, M.seg_axis[q][j], s_sin[w][dof], s_cos[w][dof]);
-      }
-      mul34(L, P, Q);
+      double Q[12];
+      mul34(s_L[w][q], P, Q);
       for (int i = 0; i < 12; ++i) P[i] = Q[i];
       root = q;
       q = M.seg_parent[q];
@@ -531,23 +540,34 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
         f[7] = 0.0f;
       }
     }
-    double T0[12], T[12];
-    mul34(W0, P, T0);                 // the parent's frame (the wrist for a root)
-    mul34(T0, M.seg_off[lane], T);
+    double T[12];
+    mul34(W0, P, T);
+    for (int i = 0; i < 12; ++i) s_T[w][lane][i] = T[i];
+    // joint axes in the camera frame: the second joint's axis is R_s a2; the first's is
+    // R_s Rot(a2, q2)^T a1 (each rotation leaves its own axis fixed); both pass through the
+    // segment origin
+    const int dof1 = M.seg_dof[lane][0], dof2 = M.seg_dof[lane][1];
     for (int j = 0; j < 2; ++j) {
-      const int dof = M.seg_dof[lane][j];
+      const int dof = j ? dof2 : dof1;
       if (dof < 0) continue;
-      const double* ax = M.seg_axis[lane][j];
+      double v[3] = {M.seg_axis[lane][j][0], M.seg_axis[lane][j][1], M.seg_axis[lane][j][2]};
+      if (j == 0 && dof2 >= 0) {
+        // Rot(a2, q2)^T v = c v - s (a2 x v) + (1 - c)(a2 . v) a2
+        const double* a2 = M.seg_axis[lane][1];
+        const double sn = s_sin[w][dof2], cs = s_cos[w][dof2];
+        const double dt = (1.0 - cs) * (a2[0] * v[0] + a2[1] * v[1] + a2[2] * v[2]);
+        const double cr[3] = {a2[1] * v[2] - a2[2] * v[1], a2[2] * v[0] - a2[0] * v[2],
+                              a2[0] * v[1] - a2[1] * v[0]};
+        for (int i = 0; i < 3; ++i) v[i] = cs * v[i] - sn * cr[i] + dt * a2[i];
+      }
       float* f = ws.dof_frame + ((size_t)p * n_dof + dof) * 8;
       f[0] = 0.0f;
       for (int i = 0; i < 3; ++i) {
-        f[1 + i] = (float)(T[i * 4 + 0] * ax[0] + T[i * 4 + 1] * ax[1] + T[i * 4 + 2] * ax[2]);
+        f[1 + i] = (float)(T[i * 4 + 0] * v[0] + T[i * 4 + 1] * v[1] + T[i * 4 + 2] * v[2]);
         f[4 + i] = (float)T[i * 4 + 3];
       }
       f[7] = 0.0f;
-      post_rotate(T, ax, s_sin[w][dof], s_cos[w][dof]);
     }
-    for (int i = 0; i < 12; ++i) s_T[w][lane][i] = T[i];
     float* so = ws.seg_org + ((size_t)p * n_seg + lane) * 4;
     so[0] = (float)T[3];
     so[1] = (float)T[7];
