@@ -36,8 +36,8 @@ METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at 
 # reads half the bytes read, WRITE_SIZE all the bytes written).  Keyed by the SHA-256 of the
 # kernel sources it was measured on: any later change of the kernel reports null.
 MEASURED_TRAFFIC = {
-    "75af8d8ec2735e02a03bc2d2188a4064008f40a7ffecd3dd5596b2dcfc92106f": {
-        "config": 4, "fetch_kib": 15310.451, "write_kib": 314.671, "fetch_scale": 2.0,
+    "5a60a7157cb4f8693988f7b022ce3be948a04822025fc97442330a60640ce837": {
+        "config": 4, "fetch_kib": 15162.595, "write_kib": 304.333, "fetch_scale": 2.0,
         "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",
