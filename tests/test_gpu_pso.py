@@ -133,3 +133,46 @@ def test_refinement_selects_exactly_the_k_lowest(P, K):
     others = np.setdiff1d(np.arange(P), top)
     assert np.array_equal(c1[others], c0[others])
     assert np.all(c1[top] <= c0[top])
+
+
+def test_whole_runs_match_the_oracle_distribution():
+    """Whole 64 x 30 runs on the 128x128 frame, seeds 0..31, against the oracle's
+    (golden/pso_final_errors_pso128.json, written from the oracle alone by
+    golden/make_pso_final_errors.py).  Whole runs are chaotic, so the final joint errors and
+    global-best costs are compared as distributions: two-sample Kolmogorov-Smirnov p > 0.01 and
+    means within three standard errors of their difference."""
+    import json
+    import os
+
+    from scipy import stats
+
+    from workload.handmodel import init_halfwidth
+    path = os.path.join(os.path.dirname(__file__), "golden", "pso_final_errors_pso128.json")
+    with open(path) as f:
+        ref = json.load(f)
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(1)
+    ctx = make_ctx(model, [fr])
+    dev = torch.device("cuda:0")
+    delta = init_halfwidth(model["n_dof"], cfg.init_angle_deg, cfg.init_trans_mm)
+    lo = torch.tensor((fr["h_true"] - delta).astype(np.float32))
+    hi = torch.tensor((fr["h_true"] + delta).astype(np.float32))
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    params = ht.pso_params(w=ref["w"], c1=ref["c1"], c2=ref["c2"],
+                           mutate_every=ref["mutate_every"], mutate_frac=ref["mutate_frac"])
+    errs, costs = [], []
+    for s in ref["seeds"]:
+        sw = ctx.swarm(slots, ref["particles"], lo, hi, seed=s)
+        ctx.pso_init(sw)
+        for _ in range(ref["generations"]):
+            ctx.pso_step(sw, params)
+        g = sw["gbest_x"].cpu().numpy()[0].astype(np.float64)
+        errs.append(float(np.degrees(np.mean(np.abs(g[:20] - fr["h_true"][:20])))))
+        costs.append(float(sw["gbest_cost"].cpu().numpy()[0]))
+    ctx.close()
+    r_err = [r["joint_error_deg"] for r in ref["runs"]]
+    r_cost = [r["gbest_cost"] for r in ref["runs"]]
+    for a, b in ((errs, r_err), (costs, r_cost)):
+        assert stats.ks_2samp(a, b).pvalue > 0.01
+        se = np.sqrt(np.var(a, ddof=1) / len(a) + np.var(b, ddof=1) / len(b))
+        assert abs(np.mean(a) - np.mean(b)) <= 3.0 * se
