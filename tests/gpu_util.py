@@ -65,8 +65,12 @@ def eval_debug(ctx, poses, slot, W, H):
     return cost.cpu().numpy(), {k: (v.cpu().numpy() if k != "slot" else v) for k, v in dbg.items()}
 
 
-def check_particle(model, fr, pose, gpu_cost, gdbg, i):
-    """Compare one particle's GPU images and cost with the oracle; returns diagnostics."""
+def check_particle(model, fr, pose, gpu_cost, gdbg, i, depth_rounding_atol=False):
+    """Compare one particle's GPU images and cost with the oracle; returns diagnostics.
+
+    With ``depth_rounding_atol`` the cost may also differ by the FP32 rounding of the rendered
+    depths it sums (hit pixels x one FP32 ulp of the largest depth / S_or): for an ROI of a few
+    pixels E is a sub-millimetre residual and the relative bar alone is finer than FP32 depth."""
     h = np.asarray(pose, np.float32).astype(np.float64)
     H, W = fr["depth"].shape
     res = raycast.render(model, h, W, H, fr["cam"], fr["bg"])
@@ -97,7 +101,10 @@ def check_particle(model, fr, pose, gpu_cost, gdbg, i):
     o_s = fr["skin"].astype(bool)
     S_d, S_and, S_or = t_d.sum(), int((o_s & r_m).sum()), int((o_s | r_m).sum())
     E = ocost.discrepancy_from_sums(S_d, S_and, S_or) + ocost.LAMBDA_K * ocost.kc(model, h)
-    assert abs(gpu_cost - E) <= COST_RTOL * abs(E), f"particle {i}: cost {gpu_cost} vs {E}"
+    tol = COST_RTOL * abs(E)
+    if depth_rounding_atol and S_or > 0:
+        tol += int(hit.sum()) * float(np.spacing(np.float32(np.max(r_d)))) / S_or
+    assert abs(gpu_cost - E) <= tol, f"particle {i}: cost {gpu_cost} vs {E}"
     return {"ambiguous": int(amb.sum()), "hits": int(res["hit"].sum()),
             "max_depth_err": float(derr.max()) if derr.size else 0.0,
             "cost_rel": abs(gpu_cost - E) / abs(E)}

@@ -1,0 +1,97 @@
+"""GPU parity on the degenerate cases of the cost (Eq. 4-5) against the FP64 oracle: S_or = 0,
+a hypothesis that renders nothing (outside the view, or behind the background plane), an
+observation without any defined depth, and ROIs smaller than one tile (down to 1x1)."""
+import numpy as np
+import pytest
+
+from gpu_util import check_particle, eval_debug, frame_for, make_ctx, torch_cuda
+from oracle import cost as ocost
+from oracle import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _eval(ctx, poses):
+    torch = torch_cuda()
+    dev = torch.device("cuda:0")
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    return ctx.eval(torch.tensor(np.asarray(poses, np.float32), device=dev), slots).cpu().numpy()
+
+
+def _away(model, h, dx=0.0, dz=0.0):
+    """Pose h with its wrist moved by (dx, 0, dz) mm (every hand)."""
+    g = np.array(h, np.float64)
+    for k in range(model["n_dof"] // 26):
+        g[26 * k + 20] += dx
+        g[26 * k + 22] += dz
+    return g.astype(np.float32)
+
+
+def test_s_or_zero_gives_lambda():
+    """No skin and a hypothesis that renders nothing: S_or = 0, so D = lambda exactly and
+    E = lambda + lambda_k kc."""
+    torch_cuda()
+    cfg, model, fr = frame_for(0)
+    fr = dict(fr)
+    fr["skin"] = np.zeros_like(fr["skin"])
+    h = _away(model, fr["h_true"], dx=5000.0)
+    ctx = make_ctx(model, [fr])
+    c = _eval(ctx, [h])
+    ctx.close()
+    E = ocost.objective(model, h.astype(np.float64), fr)
+    assert E == ocost.LAMBDA + ocost.LAMBDA_K * ocost.kc(model, h.astype(np.float64))
+    assert abs(c[0] - E) <= 1e-6 * E
+
+
+@pytest.mark.parametrize("where", ["outside", "behind"])
+def test_hypothesis_that_renders_nothing(where):
+    """All-miss hypotheses (the hand far to the side, or beyond the background plane at 1.5 m):
+    every pixel renders the background; the cost matches the oracle's."""
+    torch_cuda()
+    cfg, model, fr = frame_for(1)
+    h = _away(model, fr["h_true"], dx=5000.0) if where == "outside" else \
+        _away(model, fr["h_true"], dz=2000.0)
+    H, W = fr["depth"].shape
+    ctx = make_ctx(model, [fr])
+    cost, dbg = eval_debug(ctx, [h], 0, W, H)
+    ctx.close()
+    assert not dbg["hit"].any()
+    assert np.all(dbg["depth"] == np.float32(fr["bg"]))
+    check_particle(model, fr, h, cost[0], dbg, 0)
+
+
+def test_observation_without_defined_depth():
+    """Every depth pixel undefined (0): each pixel's depth term is the clamp d_M and every
+    rendered pixel is matched (r_m = hit)."""
+    torch_cuda()
+    cfg, model, fr = frame_for(1)
+    fr = dict(fr)
+    fr["depth"] = np.zeros_like(fr["depth"])
+    H, W = fr["depth"].shape
+    poses = [fr["h_true"].astype(np.float32), _away(model, fr["h_true"], dx=15.0)]
+    ctx = make_ctx(model, [fr])
+    cost, dbg = eval_debug(ctx, poses, 0, W, H)
+    ctx.close()
+    for i in range(len(poses)):
+        check_particle(model, fr, poses[i], cost[i], dbg, i)
+        assert np.array_equal(dbg["rm"][i].astype(bool), dbg["hit"][i].astype(bool))
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 9), (9, 1), (7, 7), (8, 1), (1, 8)])
+def test_roi_smaller_than_a_tile(W, H):
+    """ROIs of one pixel up to one partial tile, looking at the hand's centre."""
+    torch_cuda()
+    cfg, model, fr0 = frame_for(1)
+    h = fr0["h_true"]
+    # the hand's centre at the middle of the ROI
+    c = synth.hand_centre(model, h, 0)
+    cam = (600.0, 600.0, (W - 1) / 2.0 - 600.0 * c[0] / c[2], (H - 1) / 2.0 - 600.0 * c[1] / c[2])
+    ob = synth.clean_observation(model, h, W, H, cam)
+    fr = {"depth": np.clip(np.round(ob["depth"]), 0, 65535).astype(np.uint16),
+          "skin": ob["skin"].astype(np.uint8), "cam": cam, "bg": ob["bg"], "h_true": h}
+    poses = [h.astype(np.float32), _away(model, h, dx=3.0), _away(model, h, dx=5000.0)]
+    ctx = make_ctx(model, [fr])
+    cost, dbg = eval_debug(ctx, poses, 0, W, H)
+    ctx.close()
+    for i in range(len(poses)):
+        check_particle(model, fr, poses[i], cost[i], dbg, i, depth_rounding_atol=True)
