@@ -95,3 +95,29 @@ def test_roi_smaller_than_a_tile(W, H):
     ctx.close()
     for i in range(len(poses)):
         check_particle(model, fr, poses[i], cost[i], dbg, i, depth_rounding_atol=True)
+
+
+def test_gradient_of_a_hypothesis_that_renders_nothing():
+    """Nothing rendered: the depth term has no gradient, so dE/dh is the collision term's alone,
+    -/+ lambda_k on the two angles of each violated pair (pairs violated on purpose here)."""
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(1)
+    h = _away(model, fr["h_true"], dx=5000.0).astype(np.float64)
+    used, n = set(), 0
+    for a, b in model["kc_pairs"]:              # violate two pairs with no angle in common
+        if n < 2 and a not in used and b not in used:
+            h[a], h[b] = -0.2, 0.1
+            used |= {int(a), int(b)}
+            n += 1
+    h = h.astype(np.float32)
+    ctx = make_ctx(model, [fr])
+    dev = torch.device("cuda:0")
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    c, g = ctx.eval_grad(torch.tensor(h[None], device=dev), slots)
+    ctx.close()
+    g = g.cpu().numpy()[0]
+    ref = ocost.LAMBDA_K * ocost.kc_grad(model, h.astype(np.float64))
+    assert np.count_nonzero(ref) >= 4
+    assert np.array_equal(g, ref.astype(np.float32))
+    E = ocost.objective(model, h.astype(np.float64), fr)
+    assert abs(c.cpu().numpy()[0] - E) <= 1e-5 * E
