@@ -987,13 +987,12 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   const float cc = par ? 0.0f : -B * invA;
   const float h2 = par ? r[3] - rho2 : fmaf(B, B * invA, r[3] - rho2);
   const float hs = par ? INFINITY : fast_sqrt(fmaxf(h2, 0.0f) * invA);
-  // slab 0 <= s <= L as offsets from t_r; a ray perpendicular to the axis (da == 0) is inside
-  // the slab everywhere or nowhere
+  // slab 0 <= s <= L as offsets from t_r.  A ray perpendicular to the axis (da == 0) needs no
+  // case of its own: 1/da is infinite, so the offsets are -inf and +inf inside the slab and
+  // both +inf or both -inf outside it (only a ray exactly in a cap plane, a zero-margin
+  // pixel, gives 0 * inf; min and max then drop it and the ray misses).
   const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
-  const bool flat = da == 0.0f;
-  const bool inside = (a3 >= 0.0f) & (a3 <= L);
-  const float din = flat ? (inside ? -INFINITY : INFINITY) : fminf(d0, d1);
-  const float dout = flat ? (inside ? INFINITY : -INFINITY) : fmaxf(d0, d1);
+  const float din = fminf(d0, d1), dout = fmaxf(d0, d1);
   const float tin = fmaxf(cc - hs, din), tout = fminf(cc + hs, dout);
   h.ok = (h2 >= 0.0f) & (tin <= tout);
   h.t = tr + tin;
