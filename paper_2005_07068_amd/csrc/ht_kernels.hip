@@ -1049,11 +1049,8 @@ __device__ __forceinline__ void cone_test(const float* r, float dx, float dy, fl
   const float ra = q / alpha, rb = gamma / q;
   const float lo = fminf(ra, rb), hi = fmaxf(ra, rb);
   // slab 0 <= s <= L as offsets from t_r
-  const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
-  const bool flat = da == 0.0f;
-  const bool inside = (a3 >= 0.0f) & (a3 <= L);
-  const float din = flat ? (inside ? -INFINITY : INFINITY) : fminf(d0, d1);
-  const float dout = flat ? (inside ? INFINITY : -INFINITY) : fmaxf(d0, d1);
+  const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;   // infinite for da == 0, as above
+  const float din = fminf(d0, d1), dout = fmaxf(d0, d1);
   const bool has = disc >= 0.0f;
   float tin;
   bool side;
@@ -1114,11 +1111,8 @@ __device__ __forceinline__ void ecylinder_test(const float* r, float dx, float d
   const float m = par ? 1.0f - vqv : fmaf(B, B * inv, 1.0f - vqv);
   const float hs = par ? INFINITY : fast_sqrt(fmaxf(m, 0.0f) * inv);
   const float a3 = fmaf(vx, ux, fmaf(vy, uy, vz * uz));
-  const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
-  const bool flat = da == 0.0f;
-  const bool inside = (a3 >= 0.0f) & (a3 <= L);
-  const float din = flat ? (inside ? -INFINITY : INFINITY) : fminf(d0, d1);
-  const float dout = flat ? (inside ? INFINITY : -INFINITY) : fmaxf(d0, d1);
+  const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;   // infinite for da == 0, as above
+  const float din = fminf(d0, d1), dout = fmaxf(d0, d1);
   const float tin = fmaxf(cc - hs, din), tout = fminf(cc + hs, dout);
   h.ok = (m >= 0.0f) & (tin <= tout);
   h.t = tr + tin;
