@@ -984,8 +984,11 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   // t_side carries the rounding of the perpendicular part of d (large when the ray is close
   // to the axis); the linear term B of the side quadratic re-centres the chord exactly
   const float B = fmaf(wx, px, fmaf(wy, py, wz * pz));
-  const float cc = par ? 0.0f : -B * invA;
-  const float h2 = par ? r[3] - rho2 : fmaf(B, B * invA, r[3] - rho2);
+  // near-parallel rays drop the linear term: a zero in place of 1/A (selects, no branch;
+  // B is finite, so B * 0 = 0 and the values equal the parallel case's exactly)
+  const float invA_s = par ? 0.0f : invA;
+  const float cc = -B * invA_s;
+  const float h2 = fmaf(B, B * invA_s, r[3] - rho2);
   const float hs = par ? INFINITY : fast_sqrt(fmaxf(h2, 0.0f) * invA);
   // slab 0 <= s <= L as offsets from t_r.  A ray perpendicular to the axis (da == 0) needs no
   // case of its own: 1/da is infinite, so the offsets are -inf and +inf inside the slab and
@@ -1107,8 +1110,9 @@ __device__ __forceinline__ void ecylinder_test(const float* r, float dx, float d
   const float qvz = fmaf(q02, vx, fmaf(q12, vy, q22 * vz));
   const float vqv = fmaf(vx, qvx, fmaf(vy, qvy, vz * qvz));
   const float B = fmaf(vx, qdx, fmaf(vy, qdy, vz * qdz));
-  const float cc = par ? 0.0f : -B * inv;
-  const float m = par ? 1.0f - vqv : fmaf(B, B * inv, 1.0f - vqv);
+  const float inv_s = par ? 0.0f : inv;     // as for the cylinder: selects, no branch
+  const float cc = -B * inv_s;
+  const float m = fmaf(B, B * inv_s, 1.0f - vqv);
   const float hs = par ? INFINITY : fast_sqrt(fmaxf(m, 0.0f) * inv);
   const float a3 = fmaf(vx, ux, fmaf(vy, uy, vz * uz));
   const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;   // infinite for da == 0, as above
