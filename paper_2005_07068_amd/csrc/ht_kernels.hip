@@ -1291,22 +1291,25 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       const int x0 = tx * kTile, y0 = ty * kTile;
       // culling, one lane per primitive: screen box overlap, then the distance of the tile's
       // centre from the primitive's image segment
-      uint64_t mk[2];
+      // (the three loads are issued together, the index clamped, so no branch waits on LDS;
+      // the segment test runs only where some lane's box overlaps; the second half is skipped
+      // outright for models of at most 64 primitives)
+      uint64_t mk[2] = {0ull, 0ull};
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
+        if (half * kWave >= n_prim) break;
         const int k = lane + half * kWave;
-        bool ov = false;
-        if (k < n_prim) {
-          const int4 b = s_box[k];
-          ov = b.x <= x0 + kTile - 1 && b.y >= x0 && b.z <= y0 + kTile - 1 && b.w >= y0;
-          if (ov) {
-            const float4 cp = s_cap[k];
-            const float2 cq = s_capr[k];
-            const float wx = (float)x0 + 3.5f - cp.x, wy = (float)y0 + 3.5f - cp.y;
-            const float sp = fminf(fmaxf(fmaf(wx, cp.z, wy * cp.w) * cq.x, 0.0f), 1.0f);
-            const float ex = fmaf(-sp, cp.z, wx), ey = fmaf(-sp, cp.w, wy);
-            ov = fmaf(ex, ex, ey * ey) <= cq.y;
-          }
+        const int kk = min(k, n_prim - 1);
+        const int4 b = s_box[kk];
+        const float4 cp = s_cap[kk];
+        const float2 cq = s_capr[kk];
+        bool ov = (k < n_prim) & (b.x <= x0 + kTile - 1) & (b.y >= x0) &
+                  (b.z <= y0 + kTile - 1) & (b.w >= y0);
+        if (ov) {
+          const float wx = (float)x0 + 3.5f - cp.x, wy = (float)y0 + 3.5f - cp.y;
+          const float sp = fminf(fmaxf(fmaf(wx, cp.z, wy * cp.w) * cq.x, 0.0f), 1.0f);
+          const float ex = fmaf(-sp, cp.z, wx), ey = fmaf(-sp, cp.w, wy);
+          ov = fmaf(ex, ex, ey * ey) <= cq.y;
         }
         mk[half] = __ballot(ov);
       }
