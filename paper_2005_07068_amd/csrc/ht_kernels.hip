@@ -1170,6 +1170,14 @@ __device__ __forceinline__ FrameSlot uni(const FrameSlot& f) {
   return u;
 }
 
+// A pointer read from memory (a FrameSlot field) is generic to the compiler, and generic
+// loads count against the LDS counter too, so every LDS wait would also wait for them; these
+// buffers are device memory, so their loads are issued as global loads.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // Walks a particle's tiles (the union of its rectangles, each row-major) in steps of the
 // number of wavefronts per workgroup, without a division per tile.
 struct TileWalk {
@@ -1317,7 +1325,15 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 
       const int tile_idx = ty * fs.TW + tx;
       const int u = x0 + (lane & 7), v = y0 + (lane >> 3);
-      const uint32_t word = fs.words[(size_t)tile_idx * kTilePx + lane];
+      const uint32_t word = global_ptr(fs.words)[(size_t)tile_idx * kTilePx + lane];
+      // the tile's background sums, loaded with the words (by lane 0, which subtracts them
+      // after the tests) so that their latency overlaps the tests
+      float bg_td = 0.0f;
+      int bg_sk = 0;
+      if (lane == 0) {
+        bg_td = global_ptr(fs.tile_td)[tile_idx];
+        bg_sk = global_ptr(fs.tile_skin)[tile_idx];
+      }
       const bool valid = (word & kValidBit) != 0;
       const float od = (float)(word & 0xFFFFu);
       const bool os = (word & kSkinBit) != 0;
@@ -1375,9 +1391,15 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
         acc_a += (os && rm) ? 1 : 0;
         acc_o += (os || rm) ? 1 : 0;
       }
-      if (lane == 0) {
-        acc_td -= (double)fs.tile_td[tile_idx];
-        acc_o -= fs.tile_skin[tile_idx];
+      {
+        // read back from lane 0 only here (a convergent read, so the wait for the loads stays
+        // after the tests)
+        const float bgt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(bg_td)));
+        const int bgs = __builtin_amdgcn_readfirstlane(bg_sk);
+        if (lane == 0) {
+          acc_td -= (double)bgt;
+          acc_o -= bgs;
+        }
       }
       if (DEBUG && valid) {
         const size_t pix = ((size_t)p * a.dbg_H + v) * a.dbg_W + u;
