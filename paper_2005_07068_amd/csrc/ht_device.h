@@ -115,7 +115,8 @@ struct Workspace {
   int* item_map;         // [max_items]
   Partial* partial;      // [max_items]
   float* wrench;         // [max_items][n_seg][6] (gradient only)
-  int* counters;         // [0] dequeue counter, [1] total items
+  int* counters;         // [0] dequeue counter, [1] total items, [2] tiles per item,
+                         // [3] 1: a particle's items take interleaved tiles
   int max_items;
 };
 

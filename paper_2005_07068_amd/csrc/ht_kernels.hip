@@ -327,6 +327,11 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
     ws.counters[0] = 0;
     ws.counters[1] = total_items;
     ws.counters[2] = tpi;
+    // a gradient launch with at most about two items per persistent workgroup has nothing to
+    // even out its items' different costs (and its tiles are the heavier ones), so each
+    // particle's items take interleaved tiles of about equal work; elsewhere runs of
+    // consecutive tiles measured faster (the dequeue balances larger launches)
+    ws.counters[3] = a.grad && total_items <= 2 * a.grid ? 1 : 0;
   }
 }
 
@@ -1246,8 +1251,9 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   const int n_prim = a.n_prim, n_seg = a.n_seg;
-  const int tpi = uni(ws.counters[2]);
   const int total = uni(ws.counters[1]);
+  const int tpi = uni(ws.counters[2]);
+  const bool interleave = uni(ws.counters[3]) != 0;
   int cur_p = -1;
   FrameSlot fs{};
   const PInfo& pi = s_pi;
@@ -1286,15 +1292,26 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       float* wr = &s_wr[wave][0][0][0];
       for (int i = lane; i < n_seg * 24; i += kWave) wr[i] = 0.0f;
     }
-    const int c = item - uni(ws.item_off[p]);
-    const int t_end = min((c + 1) * tpi, uni(pi.n_tiles));
+    // item c of a particle with n_it items takes tiles c tpi .. (c + 1) tpi - 1, or, when
+    // interleaved, tiles c, c + n_it, c + 2 n_it, ...: then every item samples the whole hand
+    // and carries about equal work (runs of consecutive tiles differed threefold, and a launch
+    // with about one item per workgroup lasts as long as its longest item); wavefront w takes
+    // every fourth of an item's tiles
+    const int off = uni(ws.item_off[p]);
+    const int c = item - off;
+    const int n_it = uni(ws.item_off[p + 1]) - off;
+    const int n_tiles = uni(pi.n_tiles);
+    const int first = interleave ? c : c * tpi;
+    const int gap = interleave ? n_it : 1;
+    const int t_end = interleave ? n_tiles : min((c + 1) * tpi, n_tiles);
+    const int stride = gap * kWavesPerBlock;
     double acc_td = 0.0;   // exact: the FP32 terms are multiples of 2^-15 mm
     int acc_a = 0, acc_o = 0;
     const float* recs = reinterpret_cast<const float*>(s_rec);
 
     TileWalk walk;
-    walk.start(&pi, c * tpi + wave);
-    for (int t = c * tpi + wave; t < t_end; t += kWavesPerBlock, walk.step(kWavesPerBlock)) {
+    walk.start(&pi, first + wave * gap);
+    for (int t = first + wave * gap; t < t_end; t += stride, walk.step(stride)) {
       const int tx = walk.tx(), ty = walk.ty();
       const int x0 = tx * kTile, y0 = ty * kTile;
       // culling, one lane per primitive: screen box overlap, then the distance of the tile's
