@@ -162,15 +162,21 @@ bool capturing(hipStream_t s) {
   return st != hipStreamCaptureStatusNone;
 }
 
+// Whether the workspace already holds n_total particles over observations of max_tiles tiles.
+bool workspace_fits(const ht_ctx* c, int n_total, int max_tiles, bool grad) {
+  const long long items =
+      std::max<long long>((long long)n_total * ((max_tiles + kMinTilesPerItem - 1) / kMinTilesPerItem), 1);
+  return n_total <= c->cap_particles && items <= c->cap_items && max_tiles <= c->cap_tiles &&
+         (!grad || c->cap_wrench);
+}
+
 // Make sure the workspace holds n_total particles over observations of max_tiles tiles.
 ht_status ensure_workspace(ht_ctx* c, int n_total, int max_tiles, bool grad, hipStream_t s) {
   const long long items_ll =
       (long long)n_total * ((max_tiles + kMinTilesPerItem - 1) / kMinTilesPerItem);
   if (items_ll > (1ll << 30)) return fail(HT_ERR_ARG, "workload too large: %lld work items", items_ll);
   const int items = (int)std::max<long long>(items_ll, 1);
-  const bool ok = n_total <= c->cap_particles && items <= c->cap_items &&
-                  max_tiles <= c->cap_tiles && (!grad || c->cap_wrench);
-  if (ok) return HT_OK;
+  if (workspace_fits(c, n_total, max_tiles, grad)) return HT_OK;
   if (capturing(s))
     return fail(HT_ERR_STATE, "workspace too small during graph capture; call ht_reserve first");
   HT_HIP(hipDeviceSynchronize());
@@ -235,11 +241,17 @@ ht_status check_slots_set(ht_ctx* c) {
 namespace ht {
 
 // Evaluation shared by ht_eval_particles, ht_eval_particles_grad and the swarm step.
+// With src, particle r of frame f reuses the kinematics that the previous evaluation (of
+// src_stride particles per frame) left for its particle src[r] of frame f: poses must equal
+// those, and the kinematics stage is skipped.
 ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_particles,
                     const float* poses, float* cost, float* grad, const uint8_t* pixel_mask,
-                    const ht_debug* dbg, hipStream_t s, const int32_t* frame_stop = nullptr) {
+                    const ht_debug* dbg, hipStream_t s, const int32_t* frame_stop = nullptr,
+                    const int32_t* src = nullptr, int src_stride = 0) {
   const int n_total = n_frames * n_particles;
   if (n_total == 0) return HT_OK;
+  // reused kinematics would not survive a reallocation of the workspace: compute them again
+  if (src && !workspace_fits(c, n_total, c->max_tiles(), grad != nullptr)) src = nullptr;
   ht_status st = ensure_workspace(c, n_total, c->max_tiles(), grad != nullptr, s);
   if (st != HT_OK) return st;
   EvalArgs a{};
@@ -253,6 +265,8 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.grad = grad;
   a.pixel_mask = pixel_mask;
   a.frame_stop = frame_stop;
+  a.src = src;
+  a.src_stride = src_stride;
   if (dbg) {
     a.dbg = *dbg;
     const SlotHost& sh = c->slots[dbg->slot];
@@ -278,9 +292,11 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.n_dof = c->n_dof;
   const int kinds[kNumStages] = {HT_K_FK, HT_K_SCHED, grad ? HT_K_RAYCAST_GRAD : HT_K_RAYCAST,
                                  HT_K_FINALIZE};
-  for (int stage = 0; stage < kNumStages; ++stage)
+  for (int stage = 0; stage < kNumStages; ++stage) {
+    if (stage == kStageFk && src) continue;   // reused from the previous evaluation
     HT_HIP(traced(c, kinds[stage], n_total, s,
                   [&] { return launch_eval_stage(stage, a, c->ws, s); }));
+  }
   return HT_OK;
 }
 
@@ -700,10 +716,11 @@ ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, h
     const int n_ref = F * K;
     if ((st = ensure_refine(c, n_ref, s)) != HT_OK) return st;
     HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_select(sw, K, D, c->r_sel, c->r_x, c->r_cost, c->r_active, s); }));
-    // the gradient at the start; afterwards each step's candidates are evaluated with their
-    // gradients (except in the last step), so the accepted candidate brings its own
+    // the gradient at the start (the selected particles' kinematics are the swarm
+    // evaluation's, still in the workspace); afterwards each step's candidates are evaluated
+    // with their gradients (except in the last step), so the accepted candidate brings its own
     st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s,
-                       sw.stop_gen);
+                       sw.stop_gen, c->r_sel, P);
     if (st != HT_OK) return st;
     // step s: candidates from the current positions and gradients (fused with accepting the
     // previous step's), their evaluation (with gradients but in the last step), and after the

@@ -130,6 +130,11 @@ struct EvalArgs {
   float* grad;                 // NULL for forward only
   const uint8_t* pixel_mask;   // gradient mask of frame 0, may be NULL
   const int* frame_stop;       // [n_frames] stop flags of a swarm, may be NULL
+  // NULL, or per evaluated particle r its source s = src[r]: the particle reuses the kinematics
+  // of workspace particle (r / n_particles) * src_stride + s from the previous evaluation
+  // (same poses; the kinematics stage is skipped)
+  const int* src;
+  int src_stride;
   ht_debug dbg;                // pointers may be NULL
   int dbg_W, dbg_H;
   float dbg_bg;

@@ -240,10 +240,16 @@ constexpr int kSchedBatch = 8;
 constexpr int kSchedBlock = 1024;    // threads of the work-list kernel (its only workgroup)
 constexpr int kSchedWindow = 8192;   // items staged in LDS per round (32 KB)
 
-__device__ __forceinline__ void load_tiles(const Workspace& ws, int i0, int e,
+// Workspace particle holding the kinematics of evaluated particle r (itself, or its source
+// from the previous evaluation).
+__device__ __forceinline__ int src_of(const EvalArgs& a, int r) {
+  return a.src ? (r / a.n_particles) * a.src_stride + a.src[r] : r;
+}
+
+__device__ __forceinline__ void load_tiles(const EvalArgs& a, const Workspace& ws, int i0, int e,
                                            int (&v)[kSchedBatch]) {
 #pragma unroll
-  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? ws.tiles[i0 + j] : 0;
+  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? ws.tiles[src_of(a, i0 + j)] : 0;
 }
 
 __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& ws) {
@@ -255,7 +261,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   int tiles = 0;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
     int v[kSchedBatch];
-    load_tiles(ws, i0, e, v);
+    load_tiles(a, ws, i0, e, v);
 #pragma unroll
     for (int j = 0; j < kSchedBatch; ++j) tiles += v[j];
   }
@@ -271,7 +277,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   int local = 0;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
     int v[kSchedBatch];
-    load_tiles(ws, i0, e, v);
+    load_tiles(a, ws, i0, e, v);
 #pragma unroll
     for (int j = 0; j < kSchedBatch; ++j) local += (v[j] + tpi - 1) / tpi;
   }
@@ -284,7 +290,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   int off = my_b;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
     int v[kSchedBatch];
-    load_tiles(ws, i0, e, v);
+    load_tiles(a, ws, i0, e, v);
 #pragma unroll
     for (int j = 0; j < kSchedBatch; ++j) {
       if (i0 + j >= e) break;
@@ -307,7 +313,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
       int o = my_b;
       for (int i0 = b; i0 < e && o < w1; i0 += kSchedBatch) {
         int v[kSchedBatch];
-        load_tiles(ws, i0, e, v);
+        load_tiles(a, ws, i0, e, v);
 #pragma unroll
         for (int j = 0; j < kSchedBatch; ++j) {
           if (i0 + j >= e) break;
@@ -1274,7 +1280,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       __syncthreads();
     }
     if (item >= total) break;
-    const int p = uni(ws.item_map[item]);
+    const int r = uni(ws.item_map[item]);     // evaluated particle
+    const int p = a.src ? uni(src_of(a, r)) : r;   // the workspace particle of its kinematics
     if (p != cur_p) {
       const float4* src = reinterpret_cast<const float4*>(ws.recs + (size_t)p * n_prim * kRec);
       for (int i = tid; i < n_prim * (kRec / 4); i += kBlock) s_rec[i] = src[i];
@@ -1297,9 +1304,9 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
     // and carries about equal work (runs of consecutive tiles differed threefold, and a launch
     // with about one item per workgroup lasts as long as its longest item); wavefront w takes
     // every fourth of an item's tiles
-    const int off = uni(ws.item_off[p]);
+    const int off = uni(ws.item_off[r]);
     const int c = item - off;
-    const int n_it = uni(ws.item_off[p + 1]) - off;
+    const int n_it = uni(ws.item_off[r + 1]) - off;
     const int n_tiles = uni(pi.n_tiles);
     const int first = interleave ? c : c * tpi;
     const int gap = interleave ? n_it : 1;
@@ -1419,7 +1426,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
         }
       }
       if (DEBUG && valid) {
-        const size_t pix = ((size_t)p * a.dbg_H + v) * a.dbg_W + u;
+        const size_t pix = ((size_t)r * a.dbg_H + v) * a.dbg_W + u;
         if (a.dbg.depth) a.dbg.depth[pix] = rd;
         if (a.dbg.hit) a.dbg.hit[pix] = hit ? 1 : 0;
         if (a.dbg.rm) a.dbg.rm[pix] = rm ? 1 : 0;
@@ -1536,10 +1543,10 @@ __device__ inline float cost_from_sums(double S_d, long long S_and, long long S_
 // Forward: one wavefront per particle.
 __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace ws) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int p = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int p = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);   // evaluated particle
   const int n_total = a.n_frames * a.n_particles;
   if (p >= n_total) return;
-  const PInfo pi = ws.pinfo[p];
+  const PInfo pi = ws.pinfo[src_of(a, p)];
   if (pi.skip) return;
   if (!pi.valid) {
     if (lane == 0) a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
@@ -1562,8 +1569,9 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   __shared__ double s_inv_or;
   __shared__ float s_org[HT_MAX_SEG * 4];
   __shared__ int s_kca[HT_MAX_KC], s_kcb[HT_MAX_KC];
-  const int p = blockIdx.x, t = threadIdx.x;
-  const PInfo pi = ws.pinfo[p];
+  const int p = blockIdx.x, t = threadIdx.x;   // evaluated particle
+  const int ps = src_of(a, p);                  // the workspace particle of its kinematics
+  const PInfo pi = ws.pinfo[ps];
   const int n_dof = a.n_dof, n_seg = a.n_seg;
   if (pi.skip) return;
   if (!pi.valid) {
@@ -1573,7 +1581,7 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   }
   const int b = ws.item_off[p], e = ws.item_off[p + 1];
   // segment origins and collision pairs staged for the adjoint below
-  for (int i = t; i < n_seg * 4; i += kBlock) s_org[i] = ws.seg_org[(size_t)p * n_seg * 4 + i];
+  for (int i = t; i < n_seg * 4; i += kBlock) s_org[i] = ws.seg_org[(size_t)ps * n_seg * 4 + i];
   if (t < HT_MAX_KC) {
     s_kca[t] = t < a.model->n_kc ? a.model->kc_a[t] : -1;
     s_kcb[t] = t < a.model->n_kc ? a.model->kc_b[t] : -1;
@@ -1618,7 +1626,7 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   float fr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (j < n_dof) {
     desc = a.model->dof_desc[j];
-    const float4* f4 = reinterpret_cast<const float4*>(ws.dof_frame + ((size_t)p * n_dof + j) * 8);
+    const float4* f4 = reinterpret_cast<const float4*>(ws.dof_frame + ((size_t)ps * n_dof + j) * 8);
     const float4 f0 = f4[0], f1 = f4[1];
     fr[0] = f0.x; fr[1] = f0.y; fr[2] = f0.z; fr[3] = f0.w;
     fr[4] = f1.x; fr[5] = f1.y; fr[6] = f1.z; fr[7] = f1.w;
@@ -1698,6 +1706,7 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
   const bool dbg = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner;
   switch (stage) {
     case kStageFk:
+      if (a.src) break;   // the kinematics of the previous evaluation are reused
       hipLaunchKernelGGL(fk_kernel, dim3((n_total + kWavesPerBlock - 1) / kWavesPerBlock),
                          dim3(kBlock), 0, s, a, ws);
       break;
