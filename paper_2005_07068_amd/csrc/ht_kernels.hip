@@ -1507,15 +1507,23 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 // ------------------------------------------------------------------------------------
 // finalize: combine partials in item order, Eq. 4-5, and the kinematic adjoint
 
+// This lane's partial among a particle's first 64 items (items b .. e-1), loaded without a
+// branch: the index is clamped into the buffer and the value is used only when in range.
+__device__ __forceinline__ Partial first_partial(const Workspace& ws, int b, int e, int lane) {
+  return ws.partial[max(min(b + lane, e - 1), 0)];
+}
+
 // S_d, S_and, S_or of a particle: the ROI's background totals plus its items' partials,
-// summed by the lanes of one wavefront.  Every depth term is a multiple of 2^-15 mm, so the
-// FP64 sums are exact and equal to any other summation order.
+// summed by the lanes of one wavefront (pr0: this lane's first_partial, loaded early by the
+// caller).  Every depth term is a multiple of 2^-15 mm, so the FP64 sums are exact and equal
+// to any other summation order.
 __device__ inline void wave_partial_sums(const PInfo& pi, const Workspace& ws, int b, int e,
-                                         int lane, double& S_d, long long& S_and,
-                                         long long& S_or) {
-  double d = 0.0;
-  int sa = 0, so = 0;
-  for (int i = b + lane; i < e; i += kWave) {
+                                         int lane, const Partial& pr0, double& S_d,
+                                         long long& S_and, long long& S_or) {
+  const bool in0 = b + lane < e;
+  double d = in0 ? pr0.td : 0.0;
+  int sa = in0 ? pr0.a : 0, so = in0 ? pr0.o : 0;
+  for (int i = b + kWave + lane; i < e; i += kWave) {
     const Partial pr = ws.partial[i];
     d += pr.td;
     sa += pr.a;
@@ -1543,18 +1551,23 @@ __device__ inline float cost_from_sums(double S_d, long long S_and, long long S_
 // Forward: one wavefront per particle.
 __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalArgs a, Workspace ws) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int p = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);   // evaluated particle
+  // evaluated particle, wave-uniform (its record and item range are scalar loads)
+  const int p = blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n_total = a.n_frames * a.n_particles;
   if (p >= n_total) return;
+  // the item range and the record are independent loads; the partials are summed before the
+  // record is tested (a skipped or invalid particle has no items), so no branch waits on it
+  const int b = ws.item_off[p], e = ws.item_off[p + 1];
   const PInfo pi = ws.pinfo[src_of(a, p)];
+  const Partial pr0 = first_partial(ws, b, e, lane);
+  double S_d;
+  long long S_and, S_or;
+  wave_partial_sums(pi, ws, b, e, lane, pr0, S_d, S_and, S_or);
   if (pi.skip) return;
   if (!pi.valid) {
     if (lane == 0) a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
     return;
   }
-  double S_d;
-  long long S_and, S_or;
-  wave_partial_sums(pi, ws, ws.item_off[p], ws.item_off[p + 1], lane, S_d, S_and, S_or);
   if (lane == 0) a.cost[p] = cost_from_sums(S_d, S_and, S_or, pi.kc);
 }
 
@@ -1571,65 +1584,76 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   __shared__ int s_kca[HT_MAX_KC], s_kcb[HT_MAX_KC];
   const int p = blockIdx.x, t = threadIdx.x;   // evaluated particle
   const int ps = src_of(a, p);                  // the workspace particle of its kinematics
-  const PInfo pi = ws.pinfo[ps];
   const int n_dof = a.n_dof, n_seg = a.n_seg;
-  if (pi.skip) return;
-  if (!pi.valid) {
-    if (t == 0) a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
-    for (int j = t; j < n_dof; j += kBlock) a.grad[(size_t)p * n_dof + j] = 0.0f;
-    return;
-  }
+  // every load that depends on the particle index alone is issued here: the item range, the
+  // record, and this thread's pose parameter (descendant mask, camera-frame axis and point;
+  // threads past n_dof have none).  The record is tested only after the sums below (a skipped
+  // or invalid particle has no items), so no branch holds these loads back.
   const int b = ws.item_off[p], e = ws.item_off[p + 1];
-  // segment origins and collision pairs staged for the adjoint below
-  for (int i = t; i < n_seg * 4; i += kBlock) s_org[i] = ws.seg_org[(size_t)ps * n_seg * 4 + i];
-  if (t < HT_MAX_KC) {
-    s_kca[t] = t < a.model->n_kc ? a.model->kc_a[t] : -1;
-    s_kcb[t] = t < a.model->n_kc ? a.model->kc_b[t] : -1;
-  }
+  const PInfo pi = ws.pinfo[ps];
+  const int j = t, jc = min(t, n_dof - 1);   // loads clamped in bounds, unconditional
+  const uint32_t desc = j < n_dof ? a.model->dof_desc[jc] : 0u;
+  const float4* f4 = reinterpret_cast<const float4*>(ws.dof_frame + ((size_t)ps * n_dof + jc) * 8);
+  const float4 f0 = f4[0], f1 = f4[1];
+  const float fr[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+  // segment origins and collision pairs for the adjoint below, loaded into registers now and
+  // staged in LDS after the wrench loads have been issued (one value per thread)
+  static_assert(HT_MAX_SEG * 4 <= kBlock, "one segment-origin value per thread");
+  const float org_v = t < n_seg * 4 ? ws.seg_org[(size_t)ps * n_seg * 4 + t] : 0.0f;
+  const int kc_i = t < HT_MAX_KC ? t : 0;
+  const int kca_v = a.model->kc_a[kc_i], kcb_v = a.model->kc_b[kc_i];
   // wave q sums items b+q, b+q+4, ... (two at a time, loads first); lane l sums values l,
   // l+64, l+128; then the four partial sums are added in a fixed order
-  const int nv = n_seg * 6, lane = t & (kWave - 1), q = t >> 6;
+  const int nv = n_seg * 6, lane = t & (kWave - 1);
+  const int q = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform
+  // the first partials, for the second wavefront's cost sums below; loaded by every wavefront
+  // (unconditionally, so that no branch waits on them), issued with the wrench loads
+  const Partial pr0 = first_partial(ws, b, e, lane);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int i = b + q; i < e; i += 2 * kWavesPerBlock) {
     const bool two = i + kWavesPerBlock < e;
     const float* s0 = ws.wrench + (size_t)i * nv;
-    const float* s1 = s0 + (size_t)kWavesPerBlock * nv;
+    const float* s1 = two ? s0 + (size_t)kWavesPerBlock * nv : s0;
+    // the six loads are unconditional (offsets clamped into the item), so they are in flight
+    // together; lanes past nv add zero
     float v0[3], v1[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const bool in = lane + k * kWave < nv;
-      v0[k] = in ? s0[lane + k * kWave] : 0.0f;
-      v1[k] = in && two ? s1[lane + k * kWave] : 0.0f;
+      const int o = min(lane + k * kWave, nv - 1);
+      v0[k] = s0[o];
+      v1[k] = s1[o];
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      acc[k] += (double)v0[k];
-      if (two) acc[k] += (double)v1[k];
+      const bool in = lane + k * kWave < nv;
+      acc[k] += in ? (double)v0[k] : 0.0;
+      if (two) acc[k] += in ? (double)v1[k] : 0.0;
     }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     if (lane + k * kWave < nv) s_part[q][lane + k * kWave] = acc[k];
-  if (q == 0) {
-    double S_d;
-    long long S_and, S_or;
-    wave_partial_sums(pi, ws, b, e, lane, S_d, S_and, S_or);
-    if (lane == 0) {
-      a.cost[p] = cost_from_sums(S_d, S_and, S_or, pi.kc);
-      s_inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
-    }
+  if (t < n_seg * 4) s_org[t] = org_v;
+  if (t < HT_MAX_KC) {
+    const bool on = t < a.model->n_kc;
+    s_kca[t] = on ? kca_v : -1;
+    s_kcb[t] = on ? kcb_v : -1;
   }
-  // this thread's pose parameter: its descendant mask and camera-frame axis / point, loaded
-  // before the barriers
-  const int j = t;
-  uint32_t desc = 0;
-  float fr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (j < n_dof) {
-    desc = a.model->dof_desc[j];
-    const float4* f4 = reinterpret_cast<const float4*>(ws.dof_frame + ((size_t)ps * n_dof + j) * 8);
-    const float4 f0 = f4[0], f1 = f4[1];
-    fr[0] = f0.x; fr[1] = f0.y; fr[2] = f0.z; fr[3] = f0.w;
-    fr[4] = f1.x; fr[5] = f1.y; fr[6] = f1.z; fr[7] = f1.w;
+  // the cost sums go to the second wavefront, which has no pose parameter (at most 64 of them,
+  // all in the first), so they overlap the first one's wrench sums
+  static_assert(HT_MAX_DOF <= kWave, "pose parameters fit the first wavefront");
+  double S_d = 0.0;
+  long long S_and = 0, S_or = 0;
+  if (q == 1) wave_partial_sums(pi, ws, b, e, lane, pr0, S_d, S_and, S_or);
+  if (pi.skip) return;
+  if (!pi.valid) {
+    if (t == 0) a.cost[p] = pi.slot < 0 ? NAN : INFINITY;
+    for (int i = t; i < n_dof; i += kBlock) a.grad[(size_t)p * n_dof + i] = 0.0f;
+    return;
+  }
+  if (q == 1 && lane == 0) {
+    a.cost[p] = cost_from_sums(S_d, S_and, S_or, pi.kc);
+    s_inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
   }
   __syncthreads();
   if (t < nv) s_W[t] = ((s_part[0][t] + s_part[1][t]) + s_part[2][t]) + s_part[3][t];

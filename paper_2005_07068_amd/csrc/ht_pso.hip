@@ -457,28 +457,47 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(
   const int d = on ? lane : 0;
   const size_t xi = (size_t)r * n_dof + d;
   bool act = active[r] != 0;
-  float x = on ? rx[xi] : 0.0f;
+  float x = rx[xi];
   float c = rcost[r];
-  float g = on ? grad[xi] : 0.0f;
-  if (op.accept && act) {
-    int pick = -1;
-    for (int j = 3; j >= 0; --j)
-      if (ccost[(size_t)r * 4 + j] < c) pick = j;
-    if (pick < 0) {
-      act = false;
-      if (lane == 0) active[r] = 0;
-    } else {
-      const size_t src = ((size_t)r * 4 + pick) * n_dof + d;
-      c = ccost[(size_t)r * 4 + pick];
-      if (on) {
-        x = cand[src];
-        rx[xi] = x;
-        if (cgrad) {
-          g = cgrad[src];
-          grad[xi] = g;
+  float g = grad[xi];
+  if (op.accept) {
+    // the four candidates' costs, positions and gradients are loaded together (lanes past
+    // n_dof read dimension 0 and store nothing), then the accepted one is selected
+    float cc[4], cx[4], cg[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const size_t src = ((size_t)r * 4 + j) * n_dof + d;
+      cc[j] = ccost[(size_t)r * 4 + j];
+      cx[j] = cand[src];
+      cg[j] = cgrad ? cgrad[src] : 0.0f;
+    }
+    if (act) {
+      int pick = -1;
+#pragma unroll
+      for (int j = 3; j >= 0; --j)
+        if (cc[j] < c) pick = j;
+      if (pick < 0) {
+        act = false;
+        if (lane == 0) active[r] = 0;
+      } else {
+        float nx = cx[0], ng = cg[0];
+        c = cc[0];
+#pragma unroll
+        for (int j = 1; j < 4; ++j) {
+          nx = pick == j ? cx[j] : nx;
+          ng = pick == j ? cg[j] : ng;
+          c = pick == j ? cc[j] : c;
         }
+        x = nx;
+        if (on) {
+          rx[xi] = x;
+          if (cgrad) {
+            g = ng;
+            grad[xi] = g;
+          }
+        }
+        if (lane == 0) rcost[r] = c;
       }
-      if (lane == 0) rcost[r] = c;
     }
   }
   if (op.propose) {
