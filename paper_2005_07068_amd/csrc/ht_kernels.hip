@@ -246,10 +246,40 @@ __device__ __forceinline__ int src_of(const EvalArgs& a, int r) {
   return a.src ? (r / a.n_particles) * a.src_stride + a.src[r] : r;
 }
 
+// Tile counts of particles i0 .. i0 + kSchedBatch - 1 (zero from e on).  The loads are
+// unconditional, their indices clamped to the last particle, so all of them are in flight at
+// once (a guarded load per particle compiled into a wait per particle).
 __device__ __forceinline__ void load_tiles(const EvalArgs& a, const Workspace& ws, int i0, int e,
                                            int (&v)[kSchedBatch]) {
+  const int last = a.n_frames * a.n_particles - 1;
+  int r[kSchedBatch];
 #pragma unroll
-  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? ws.tiles[src_of(a, i0 + j)] : 0;
+  for (int j = 0; j < kSchedBatch; ++j) r[j] = min(i0 + j, last);
+  if (a.src) {   // one branch for the batch (src_of per particle branched per load)
+    int q[kSchedBatch];
+#pragma unroll
+    for (int j = 0; j < kSchedBatch; ++j) q[j] = a.src[r[j]];
+#pragma unroll
+    for (int j = 0; j < kSchedBatch; ++j) r[j] = (r[j] / a.n_particles) * a.src_stride + q[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kSchedBatch; ++j) v[j] = ws.tiles[r[j]];
+#pragma unroll
+  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? v[j] : 0;
+}
+
+// The tile counts of batch i0 of a thread whose particles start at b: the first batch (every
+// batch of launches up to kSchedBlock * kSchedBatch particles) is kept in registers from the
+// first pass, later ones are loaded again.
+__device__ __forceinline__ void batch_tiles(const EvalArgs& a, const Workspace& ws, int i0, int b,
+                                            int e, const int (&v0)[kSchedBatch],
+                                            int (&v)[kSchedBatch]) {
+  if (i0 == b) {
+#pragma unroll
+    for (int j = 0; j < kSchedBatch; ++j) v[j] = v0[j];
+  } else {
+    load_tiles(a, ws, i0, e, v);
+  }
 }
 
 __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& ws) {
@@ -258,10 +288,12 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   const int t = threadIdx.x;
   const int chunk = (n_total + kSchedBlock - 1) / kSchedBlock;
   const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
+  int v0[kSchedBatch];
+  load_tiles(a, ws, b, e, v0);
   int tiles = 0;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
     int v[kSchedBatch];
-    load_tiles(a, ws, i0, e, v);
+    batch_tiles(a, ws, i0, b, e, v0, v);
 #pragma unroll
     for (int j = 0; j < kSchedBatch; ++j) tiles += v[j];
   }
@@ -277,7 +309,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   int local = 0;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
     int v[kSchedBatch];
-    load_tiles(a, ws, i0, e, v);
+    batch_tiles(a, ws, i0, b, e, v0, v);
 #pragma unroll
     for (int j = 0; j < kSchedBatch; ++j) local += (v[j] + tpi - 1) / tpi;
   }
@@ -290,7 +322,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   int off = my_b;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
     int v[kSchedBatch];
-    load_tiles(a, ws, i0, e, v);
+    batch_tiles(a, ws, i0, b, e, v0, v);
 #pragma unroll
     for (int j = 0; j < kSchedBatch; ++j) {
       if (i0 + j >= e) break;
@@ -313,7 +345,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
       int o = my_b;
       for (int i0 = b; i0 < e && o < w1; i0 += kSchedBatch) {
         int v[kSchedBatch];
-        load_tiles(a, ws, i0, e, v);
+        batch_tiles(a, ws, i0, b, e, v0, v);
 #pragma unroll
         for (int j = 0; j < kSchedBatch; ++j) {
           if (i0 + j >= e) break;
