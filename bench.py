@@ -36,8 +36,8 @@ METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at 
 # reads half the bytes read, WRITE_SIZE all the bytes written).  Keyed by the SHA-256 of the
 # kernel sources it was measured on: any later change of the kernel reports null.
 MEASURED_TRAFFIC = {
-    "5a60a7157cb4f8693988f7b022ce3be948a04822025fc97442330a60640ce837": {
-        "config": 4, "fetch_kib": 15162.595, "write_kib": 304.333, "fetch_scale": 2.0,
+    "6a0bf9027ffbddd7d97cdceb53bf8a377ea98d31603b7aa1cea27bc2d0806b19": {
+        "config": 4, "fetch_kib": 15149.707, "write_kib": 303.665, "fetch_scale": 2.0,
         "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",

@@ -32,6 +32,33 @@ def test_adjoint_matches_fp64_gradient_on_smooth_pixels(i):
     assert err <= 1e-5 * scale
 
 
+@pytest.mark.parametrize("i", [3, 20])
+def test_two_hand_adjoint_in_a_refinement_sized_launch(i):
+    """Two hands (52 pose parameters, 32 segments) at 640x480, 32 particles in one gradient
+    launch (the refinement's top-K size, where each workgroup takes about one work item with
+    interleaved tiles): particle i's gradient against the FP64 analytic gradient on its smooth
+    pixels (the pixel mask is particle i's; the other particles only share the launch)."""
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(4)
+    poses = particles_for(model, fr, 32, seed=31, angle_deg=5.0, trans_mm=8.0)
+    h = poses[i].astype(np.float64)
+    E, parts = ocost.objective(model, h, fr, return_parts=True)
+    mask = ograd.fd_mask(parts["render"], fr["depth"])
+    _, g_ref = ograd.analytic_gradient(model, h, fr, pixel_mask=mask)
+    ctx = make_ctx(model, [fr])
+    dev = torch.device("cuda:0")
+    m = torch.tensor(mask.astype(np.uint8), device=dev)
+    c, g = ctx.eval_grad(torch.tensor(poses, device=dev),
+                         torch.zeros(1, dtype=torch.int32, device=dev), pixel_mask=m)
+    ctx.close()
+    g = g.cpu().numpy()[i].astype(np.float64)
+    scale = np.max(np.abs(g_ref))
+    err = np.max(np.abs(g - g_ref))
+    print(f"pose {i}: |g_ref|inf {scale:.4g}, max err {err:.3g}, rel {err / scale:.3g}")
+    assert np.count_nonzero(g_ref) > 26
+    assert err <= 1e-5 * scale
+
+
 def test_autograd_function_backward():
     torch = torch_cuda()
     cfg, model, fr = frame_for(0)

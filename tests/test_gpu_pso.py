@@ -113,6 +113,30 @@ def test_refinement_never_raises_the_cost():
     assert np.array_equal(c1[others], c0[others])
 
 
+def test_refinement_reusing_the_swarm_kinematics_matches_recomputing_them():
+    """The refinement's first gradient evaluation reads the swarm evaluation's kinematic tables
+    through the selection when the workspace already holds them with a wrench buffer (after
+    reserve), and computes them again when the workspace must grow first (no reserve, first
+    step): the swarms agree bit for bit after one step and after three."""
+    runs = []
+    for reserve in (False, True):
+        torch, ctx, model, fr, sw, lo, hi = _setup(P=64)
+        if reserve:
+            ctx.reserve(64 * 4, fr["depth"].size)
+        ctx.pso_init(sw)
+        p = ht.pso_params(mutate_every=0, refine_topk=8, refine_steps=2)
+        states = []
+        for _ in range(3):
+            ctx.pso_step(sw, p)
+            states.append({k: sw[k].cpu().numpy().copy()
+                           for k in ("x", "cost", "pbest_cost", "gbest_x", "gbest_cost")})
+        ctx.close()
+        runs.append(states)
+    for a, b in zip(*runs):
+        for k in a:
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
 @pytest.mark.parametrize("P,K", [(100, 40), (1000, 64), (100, 80)])
 def test_refinement_selects_exactly_the_k_lowest(P, K):
     """The refined set is the K lowest current costs (ties: lower index), for a particle count
