@@ -62,8 +62,8 @@ def measured_traffic(config: int):
 
 
 def load_workload(idx: int):
-    from workload import CONFIGS, make_hand_model, seed_sequence
-    cfg = CONFIGS[idx]
+    from workload import WORKLOADS, make_hand_model, seed_sequence
+    cfg = WORKLOADS[idx]
     d = np.load(os.path.join(ROOT, "workload", "data", f"config{idx}.npz"))
     frames = [{"depth": d[f"depth_{f}"], "skin": d[f"skin_{f}"], "cam": tuple(d["cam"][f]),
                "bg": float(d["bg"]), "h_true": d["h_true"][f]} for f in range(cfg.n_frames)]

@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import pso, synth  # noqa: E402
-from workload import CONFIGS, make_hand_model, seed_sequence  # noqa: E402
+from workload import WORKLOADS, make_hand_model, seed_sequence  # noqa: E402
 from workload.handmodel import init_halfwidth  # noqa: E402
 
 OUT = os.path.join(HERE, "pso_final_errors_pso128.json")
@@ -33,7 +33,7 @@ P, G = 64, 30
 
 
 def setup():
-    cfg = CONFIGS[1]
+    cfg = WORKLOADS[1]
     model = make_hand_model(seed_sequence(1, 10_000), cfg.n_hands, cfg.primitive_set)
     fr = synth.make_frame(model, cfg, 0)
     delta = init_halfwidth(model["n_dof"], cfg.init_angle_deg, cfg.init_trans_mm)

@@ -8,7 +8,7 @@ import pytest
 
 from oracle import cost as ocost
 from oracle import raycast, synth
-from workload import CONFIGS, make_hand_model, seed_sequence
+from workload import WORKLOADS, make_hand_model, seed_sequence
 from workload.handmodel import perturbed_particles
 
 MARGIN_TAU = 1e-5          # pixels whose ray-surface margin is below this are ambiguous
@@ -26,7 +26,7 @@ def torch_cuda():
 
 def frame_for(cfg_idx: int, frame: int = 0, model_seed: int = 0,
               primitive_set: str = "cylinders"):
-    cfg = CONFIGS[cfg_idx]
+    cfg = WORKLOADS[cfg_idx]
     model = make_hand_model(seed_sequence(cfg_idx, 10_000 + model_seed), cfg.n_hands,
                             primitive_set)
     fr = synth.make_frame(model, cfg, frame)

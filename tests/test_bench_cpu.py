@@ -18,9 +18,9 @@ def test_bench_refuses_more_than_one_gpu():
 def test_stored_workloads_are_the_oracle_output():
     """workload/data/config{0,1}.npz are exactly what the committed generator writes."""
     from oracle import synth
-    from workload import CONFIGS, make_hand_model, seed_sequence
+    from workload import WORKLOADS, make_hand_model, seed_sequence
     for idx in (0, 1):
-        cfg = CONFIGS[idx]
+        cfg = WORKLOADS[idx]
         d = np.load(os.path.join(ROOT, "workload", "data", f"config{idx}.npz"))
         model = make_hand_model(seed_sequence(idx, 10_000), cfg.n_hands)
         fr = synth.make_frame(model, cfg, 0)

@@ -7,7 +7,7 @@ from gpu_util import (check_particle, eval_debug, frame_for, make_ctx, particles
                       torch_cuda)
 from oracle import cost as ocost
 from oracle import synth
-from workload import CONFIGS, make_hand_model, seed_sequence
+from workload import WORKLOADS, make_hand_model, seed_sequence
 from workload.configs import camera_for_roi
 
 pytestmark = pytest.mark.gpu
@@ -123,7 +123,7 @@ def test_nonfinite_pose_unset_slot_and_empty_call():
 def test_batched_frames_equal_per_frame_calls():
     """64 frames of uneven ROIs (48..192 px): one launch == one call per frame (bit-identical)."""
     torch = torch_cuda()
-    cfg = CONFIGS[3]
+    cfg = WORKLOADS[3]
     model = make_hand_model(seed_sequence(3, 10_000))
     frames = [synth.make_frame(model, cfg, f) for f in range(6)]
     ctx = make_ctx(model, frames)

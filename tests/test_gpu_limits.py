@@ -7,7 +7,7 @@ import pytest
 
 from gpu_util import check_particle, eval_debug, make_ctx, particles_for, torch_cuda
 from oracle import synth
-from workload import CONFIGS, make_hand_model, seed_sequence
+from workload import WORKLOADS, make_hand_model, seed_sequence
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +76,7 @@ def test_roi_at_the_side_limit(W, H):
     """Observation strips 4096 pixels long (a ragged 13-pixel height too), one hand across
     them."""
     torch_cuda()
-    cfg = CONFIGS[1]
+    cfg = WORKLOADS[1]
     model = make_hand_model(seed_sequence(1, 10_000), cfg.n_hands, cfg.primitive_set)
     h = np.load(os.path.join(DATA, "config1.npz"))["h_true"][0]
     cam = (600.0, 600.0, (W - 1) / 2.0, (H - 1) / 2.0)
@@ -93,7 +93,7 @@ def test_roi_at_the_side_limit(W, H):
 def test_roi_beyond_the_side_limit_is_rejected():
     import paper_2005_07068_amd as ht
     torch_cuda()
-    cfg = CONFIGS[0]
+    cfg = WORKLOADS[0]
     model = make_hand_model(seed_sequence(0, 10_000), cfg.n_hands, cfg.primitive_set)
     ctx = ht.Context(0)
     ctx.set_model(model)

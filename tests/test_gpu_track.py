@@ -8,7 +8,7 @@ import pytest
 import paper_2005_07068_amd as ht
 from gpu_util import frame_for, make_ctx, torch_cuda
 from oracle import synth
-from workload import CONFIGS, make_hand_model, seed_sequence
+from workload import WORKLOADS, make_hand_model, seed_sequence
 from workload.handmodel import init_halfwidth
 
 pytestmark = pytest.mark.gpu
@@ -90,7 +90,7 @@ def test_stop_rule_freezes_only_the_frame_below_the_threshold():
 def test_tracking_a_moving_hand():
     torch = torch_cuda()
     dev = torch.device("cuda:0")
-    cfg = dataclasses.replace(CONFIGS[6], idx=61, n_frames=6, roi=(128, 128))
+    cfg = dataclasses.replace(WORKLOADS[6], idx=61, n_frames=6, roi=(128, 128))
     model = make_hand_model(seed_sequence(61, 10_000))
     frames = synth.make_sequence(model, cfg)
     ctx = make_ctx(model, frames)

@@ -9,4 +9,4 @@ from .handmodel import (  # noqa: F401
     DOF_PER_HAND, SEG_PER_HAND, PRIM_PER_HAND, PRIM_PER_HAND_PAPER, SPHERE, CYLINDER,
     ELLIPSOID, CONE, ECYLINDER, make_hand_model, finger_dof, WRIST_DOF,
 )
-from .configs import CONFIGS, WorkloadConfig, camera_for_roi, seed_sequence  # noqa: F401
+from .configs import WORKLOADS, WorkloadConfig, camera_for_roi, seed_sequence  # noqa: F401

@@ -63,7 +63,7 @@ class WorkloadConfig:
         return int(W), int(H)
 
 
-CONFIGS = {
+WORKLOADS = {
     0: WorkloadConfig(0, "fwd64", 1, (64, 64), n_particles=16, n_generations=1),
     1: WorkloadConfig(1, "pso128", 1, (128, 128), n_particles=64, n_generations=30),
     2: WorkloadConfig(2, "adjoint320x240", 1, (320, 240), n_particles=256, n_generations=1),

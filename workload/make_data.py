@@ -17,7 +17,7 @@ import time
 import numpy as np
 
 from oracle import flops, raycast, synth
-from workload import CONFIGS, make_hand_model, seed_sequence
+from workload import WORKLOADS, make_hand_model, seed_sequence
 from workload.handmodel import perturbed_particles
 
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
@@ -28,7 +28,7 @@ def model_seed(idx: int):
 
 
 def make(idx: int, flop_samples: int = 8) -> str:
-    cfg = CONFIGS[idx]
+    cfg = WORKLOADS[idx]
     model = make_hand_model(model_seed(idx), cfg.n_hands, cfg.primitive_set)
     out = {}
     cams, hs = [], []
@@ -65,7 +65,7 @@ def make(idx: int, flop_samples: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    which = [int(a) for a in sys.argv[1:]] or sorted(CONFIGS)
+    which = [int(a) for a in sys.argv[1:]] or sorted(WORKLOADS)
     for i in which:
         t = time.time()
         p = make(i)
