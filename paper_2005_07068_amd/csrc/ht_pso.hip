@@ -349,87 +349,99 @@ __global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, i
 // pairwise in rounds keeping the first K (an element's rank in the union of two sorted lists
 // is its own position plus the number of the other list's elements before it; the keys are
 // unique, so the ranks are distinct).  The K lowest, ties by lower index, as the full sort.
-__device__ __forceinline__ bool key_before(float ka, int ia, float kb, int ib) {
-  return ka < kb || (ka == kb && ia < ib);
+//
+// A (cost, index) pair is one 64-bit key: the cost's bits mapped to an unsigned integer of the
+// same order (negative floats inverted, others with the sign bit set; NaN counted as +inf and
+// -0 as +0) above the index, so one unsigned compare orders by cost and then by index.
+__device__ __forceinline__ uint64_t select_key(float c, int i) {
+  const uint32_t b = __float_as_uint(cost_key(c) + 0.0f);
+  const uint32_t u = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ((uint64_t)u << 32) | (uint32_t)i;
 }
 
-__device__ __forceinline__ int count_before(const float* xk, const int* xi, int n, float k,
-                                            int i) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (key_before(xk[mid], xi[mid], k, i)) lo = mid + 1;
-    else hi = mid;
+__device__ __forceinline__ float select_cost(uint64_t key) {
+  const uint32_t u = (uint32_t)(key >> 32);
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+// Elements of the sorted list x[0 .. n) (n <= 64) below key: a binary search with a fixed trip
+// count (loads clamped into the list, selects instead of branches).
+__device__ __forceinline__ int count_below(const uint64_t* x, int n, uint64_t key) {
+  int pos = 0;
+#pragma unroll
+  for (int step = kWave; step > 0; step >>= 1) {
+    const int q = min(pos + step, n) - 1;
+    const bool ok = pos + step <= n && x[q] < key;
+    pos = ok ? pos + step : pos;
   }
-  return lo;
+  return pos;
 }
 
 __global__ __launch_bounds__(kPsoBlock) void refine_select_small_kernel(
     ht_swarm sw, int K, int n_dof, int* __restrict__ sel, float* __restrict__ rx,
     float* __restrict__ rcost, int* __restrict__ active) {
-  __shared__ float s_k[2][kPsoBlock / kWave][kWave];
-  __shared__ int s_i[2][kPsoBlock / kWave][kWave];
+  __shared__ uint64_t s_k[2][kPsoBlock / kWave][kWave];
   const int P = sw.n_particles, f = blockIdx.x;
   const size_t base = (size_t)f * P;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
   int nl = blockDim.x / kWave;                  // sorted lists
-  // 1. bitonic sort of each wavefront's 64 entries (padding: +inf, indices past P)
+  // 1. bitonic sort of each wavefront's 64 entries (padding: +inf, indices past P); the cost
+  // load is clamped into the frame and replaced for padding lanes
   const int e = w * kWave + lane;
-  float k = e < P ? cost_key(sw.cost[base + e]) : INFINITY;
-  int i = e;
+  const float c = sw.cost[base + min(e, P - 1)];
+  uint64_t k = select_key(e < P ? c : INFINITY, e);
   for (int size = 2; size <= kWave; size <<= 1) {
     for (int j = size >> 1; j > 0; j >>= 1) {
-      const float pk = __shfl_xor(k, j);
-      const int pi = __shfl_xor(i, j);
+      const uint64_t pk = __shfl_xor(k, j);
       const bool up = (lane & size) == 0, lower = (lane & j) == 0;
-      const bool take = lower == up ? key_before(pk, pi, k, i) : key_before(k, i, pk, pi);
-      if (take) {
-        k = pk;
-        i = pi;
-      }
+      const bool take = lower == up ? pk < k : k < pk;
+      k = take ? pk : k;
     }
   }
   s_k[0][w][lane] = k;
-  s_i[0][w][lane] = i;
   __syncthreads();
   // 2. pairwise merges keeping the first K of each union
   int cur = 0;
   while (nl > 1) {
     const int pairs = nl >> 1;
     if (w < pairs && lane < K) {
-      const float* ak = s_k[cur][2 * w];
-      const int* ai = s_i[cur][2 * w];
-      const float* bk = s_k[cur][2 * w + 1];
-      const int* bi = s_i[cur][2 * w + 1];
-      const int ra = lane + count_before(bk, bi, K, ak[lane], ai[lane]);
-      const int rb = lane + count_before(ak, ai, K, bk[lane], bi[lane]);
-      if (ra < K) {
-        s_k[cur ^ 1][w][ra] = ak[lane];
-        s_i[cur ^ 1][w][ra] = ai[lane];
-      }
-      if (rb < K) {
-        s_k[cur ^ 1][w][rb] = bk[lane];
-        s_i[cur ^ 1][w][rb] = bi[lane];
-      }
+      const uint64_t* a = s_k[cur][2 * w];
+      const uint64_t* b = s_k[cur][2 * w + 1];
+      const uint64_t ka = a[lane], kb = b[lane];
+      const int ra = lane + count_below(b, K, ka);
+      const int rb = lane + count_below(a, K, kb);
+      if (ra < K) s_k[cur ^ 1][w][ra] = ka;
+      if (rb < K) s_k[cur ^ 1][w][rb] = kb;
     }
-    if ((nl & 1) && w == pairs && lane < K) {    // odd list passes through
+    if ((nl & 1) && w == pairs && lane < K)      // odd list passes through
       s_k[cur ^ 1][w][lane] = s_k[cur][nl - 1][lane];
-      s_i[cur ^ 1][w][lane] = s_i[cur][nl - 1][lane];
-    }
     __syncthreads();
     nl = pairs + (nl & 1);
     cur ^= 1;
   }
-  // 3. the K best
+  // 3. the K best, and their positions gathered (up to four per thread, loads issued first,
+  // offsets clamped into the K x n_dof block)
+  const uint64_t* best = s_k[cur][0];
   for (int r = threadIdx.x; r < K; r += blockDim.x) {
     const size_t q = (size_t)f * K + r;
-    sel[q] = s_i[cur][0][r];
-    rcost[q] = s_k[cur][0][r];
+    sel[q] = (int)(uint32_t)best[r];
+    rcost[q] = select_cost(best[r]);
     active[q] = 1;
   }
-  for (int x = threadIdx.x; x < K * n_dof; x += blockDim.x) {
-    const int r = x / n_dof, d = x % n_dof;
-    rx[((size_t)f * K + r) * n_dof + d] = sw.x[(base + s_i[cur][0][r]) * n_dof + d];
+  const int n = K * n_dof;
+  for (int x0 = 0; x0 < n; x0 += 4 * (int)blockDim.x) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int x = min(x0 + u * (int)blockDim.x + (int)threadIdx.x, n - 1);
+      const int r = x / n_dof, d = x - r * n_dof;
+      v[u] = sw.x[(base + (uint32_t)best[r]) * n_dof + d];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int x = x0 + u * (int)blockDim.x + (int)threadIdx.x;
+      if (x < n) rx[(size_t)f * n + x] = v[u];
+    }
   }
 }
 
