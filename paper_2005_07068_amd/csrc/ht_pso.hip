@@ -43,6 +43,20 @@ __device__ __forceinline__ uint4 draw(uint64_t seed, int dim, int gpart, int gen
 
 __device__ __forceinline__ float cost_key(float c) { return isnan(c) ? INFINITY : c; }
 
+// A (cost, index) pair as one 64-bit key: the cost's bits mapped to an unsigned integer of the
+// same order (negative floats inverted, others with the sign bit set; NaN counted as +inf and
+// -0 as +0) above the index, so one unsigned compare orders by cost and then by index.
+__device__ __forceinline__ uint64_t select_key(float c, int i) {
+  const uint32_t b = __float_as_uint(cost_key(c) + 0.0f);
+  const uint32_t u = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ((uint64_t)u << 32) | (uint32_t)i;
+}
+
+__device__ __forceinline__ float select_cost(uint64_t key) {
+  const uint32_t u = (uint32_t)(key >> 32);
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
 // per-particle flags from part 1 to part 2 of a generation: personal best improved, mutated,
 // the frame stopped in this generation (bests kept, no move), the frame had stopped before
 constexpr int kFlagImproved = 1, kFlagMutated = 2, kFlagStop = 4, kFlagFrozen = 8;
@@ -153,6 +167,31 @@ hipError_t launch_box_around(const DevModel* model, int n_frames, int n_dof, con
 }
 
 // ------------------------------------------------------------------------------------
+// Ascending bitonic sort of one 64-bit key per thread across the workgroup (blockDim.x a
+// power of two, at most kPsoBlock): exchanges between lanes of a wavefront are lane shuffles,
+// wider ones go through LDS with a barrier (10 of the 55 steps at 1024 threads).  Returns the
+// key of rank threadIdx.x.
+__device__ uint64_t block_sort_keys(uint64_t k, uint64_t* s_x) {
+  const int t = threadIdx.x, n = blockDim.x;
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      uint64_t pk;
+      if (j >= kWave) {
+        s_x[t] = k;
+        __syncthreads();
+        pk = s_x[t ^ j];
+        __syncthreads();
+      } else {
+        pk = __shfl_xor(k, j);
+      }
+      const bool up = (t & size) == 0, lower = (t & j) == 0;
+      const bool take = lower == up ? pk < k : k < pk;
+      k = take ? pk : k;
+    }
+  }
+  return k;
+}
+
 // generation update, part 1: one workgroup per frame
 
 __global__ __launch_bounds__(kPsoBlock) void pso_best_kernel(ht_swarm sw, ht_pso_params prm,
@@ -242,9 +281,18 @@ __global__ __launch_bounds__(kPsoBlock) void pso_best_kernel(ht_swarm sw, ht_pso
   if (stop) {
     for (int i = tid; i < P; i += blockDim.x) flags[base + i] |= kFlagStop;
   } else if (mutate_gen && n_mut > 0) {
-    // the worst n_mut by current cost are the last positions of the ascending sort
-    sort_costs(sw.cost + base, P, n_pad, s_key, s_idx);
-    for (int r = P - n_mut + tid; r < P; r += blockDim.x) flags[base + s_idx[r]] |= kFlagMutated;
+    // the worst n_mut by current cost are the last positions of the ascending sort (ties: the
+    // higher index is worse)
+    if (n_pad == (int)blockDim.x) {   // one key per thread
+      __shared__ uint64_t s_x[kPsoBlock];
+      const uint64_t k = block_sort_keys(
+          select_key(tid < P ? sw.cost[base + min(tid, P - 1)] : INFINITY, tid), s_x);
+      if (tid >= P - n_mut && tid < P) flags[base + (uint32_t)k] |= kFlagMutated;
+    } else {
+      sort_costs(sw.cost + base, P, n_pad, s_key, s_idx);
+      for (int r = P - n_mut + tid; r < P; r += blockDim.x)
+        flags[base + s_idx[r]] |= kFlagMutated;
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -349,20 +397,7 @@ __global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, i
 // pairwise in rounds keeping the first K (an element's rank in the union of two sorted lists
 // is its own position plus the number of the other list's elements before it; the keys are
 // unique, so the ranks are distinct).  The K lowest, ties by lower index, as the full sort.
-//
-// A (cost, index) pair is one 64-bit key: the cost's bits mapped to an unsigned integer of the
-// same order (negative floats inverted, others with the sign bit set; NaN counted as +inf and
-// -0 as +0) above the index, so one unsigned compare orders by cost and then by index.
-__device__ __forceinline__ uint64_t select_key(float c, int i) {
-  const uint32_t b = __float_as_uint(cost_key(c) + 0.0f);
-  const uint32_t u = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-  return ((uint64_t)u << 32) | (uint32_t)i;
-}
 
-__device__ __forceinline__ float select_cost(uint64_t key) {
-  const uint32_t u = (uint32_t)(key >> 32);
-  return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
-}
 
 // Elements of the sorted list x[0 .. n) (n <= 64) below key: a binary search with a fixed trip
 // count (loads clamped into the list, selects instead of branches).

@@ -74,6 +74,45 @@ def test_single_generation_matches_oracle(gen):
         assert moved.sum() >= 32
 
 
+@pytest.mark.parametrize("P", [100, 600, 1000])
+def test_mutation_generation_matches_oracle_with_ties(P):
+    """A mutation generation (the worst half by current cost re-drawn, ties: the higher index is
+    worse) at swarm sizes whose ranking sorts one key per thread across several wavefronts
+    (100, 1000 particles) or several keys per thread (600); duplicated positions give exactly
+    tied costs."""
+    torch, ctx, model, fr, sw, lo, hi = _setup(P=P)
+    ctx.pso_init(sw)
+    x = sw["x"].clone()
+    x[0, 1::7] = x[0, 0]
+    sw["x"].copy_(x)
+    sw["gen"].fill_(2)
+    torch.cuda.synchronize()
+    before = _host(sw)
+    params = ht.pso_params(w=0.72, c1=2.05, c2=2.05)
+    ctx.pso_step(sw, params)
+    torch.cuda.synchronize()
+    costs = sw["cost"].cpu().numpy().astype(np.float64)
+    assert len(np.unique(costs)) < P            # ties present
+    after = _host(sw)
+    ref = pso.update(before, costs, pso.PsoParams(w=0.72, c1=2.05, c2=2.05),
+                     model["bounds_lo"].astype(np.float32), model["bounds_hi"].astype(np.float32),
+                     model["mutate_mask"], 123456789012345)
+    moved_gpu = np.any(after["x"][0] != before["x"][0], axis=1)
+    moved_ref = np.any(ref["x"][0] != before["x"][0], axis=1)
+    # mutated particles are exactly the oracle's (their re-drawn dimensions differ from any
+    # Eq. 6-7 move); the others follow Eq. 6-7 within FP32 rounding
+    mutated_ref = np.zeros(P, bool)
+    order = sorted(range(P), key=lambda i: (costs[0, i], i))
+    mutated_ref[order[P - P // 2:]] = True
+    mask = model["mutate_mask"].astype(bool)
+    assert np.allclose(after["x"][0][mutated_ref][:, mask], ref["x"][0][mutated_ref][:, mask],
+                       rtol=1e-6, atol=1e-6)
+    assert np.all(after["v"][0][mutated_ref][:, mask] == 0.0)
+    assert np.allclose(after["x"], ref["x"], rtol=1e-5, atol=2e-5)
+    assert np.allclose(after["v"], ref["v"], rtol=1e-5, atol=2e-5)
+    assert np.array_equal(moved_gpu, moved_ref)
+
+
 def test_graph_replay_equals_eager_and_gbest_monotone():
     torch, ctx, model, fr, sw, lo, hi = _setup()
     params = ht.pso_params()
