@@ -199,7 +199,9 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
 }
 
 // ------------------------------------------------------------------------------------
-// work list, built by one workgroup of kSchedBlock threads.  The tiles per work item are
+// work list, built by one workgroup (kSchedBlock threads, kSchedSmall for launches of at most
+// kSchedSmall particles, whose barriers then wait on 4 wavefronts instead of 16).  The tiles
+// per work item are
 // chosen from the launch's actual tile count: about kItemsPerGroup items per persistent
 // workgroup (more, smaller items measured slower: each item stages its particle's tables),
 // a multiple of the wavefronts per workgroup, at least kFloorTilesFwd (kFloorTilesGrad for
@@ -238,6 +240,7 @@ __device__ int block_scan(int* s_sum, int v, int* total) {
 // latencies overlap (the counts were written by every XCD, so each load misses this L2).
 constexpr int kSchedBatch = 8;
 constexpr int kSchedBlock = 1024;    // threads of the work-list kernel (its only workgroup)
+constexpr int kSchedSmall = 256;     // ... for launches of at most this many particles
 constexpr int kSchedWindow = 8192;   // items staged in LDS per round (32 KB)
 
 // Workspace particle holding the kinematics of evaluated particle r (itself, or its source
@@ -269,7 +272,7 @@ __device__ __forceinline__ void load_tiles(const EvalArgs& a, const Workspace& w
 }
 
 // The tile counts of batch i0 of a thread whose particles start at b: the first batch (every
-// batch of launches up to kSchedBlock * kSchedBatch particles) is kept in registers from the
+// batch of launches up to BLOCK * kSchedBatch particles) is kept in registers from the
 // first pass, later ones are loaded again.
 __device__ __forceinline__ void batch_tiles(const EvalArgs& a, const Workspace& ws, int i0, int b,
                                             int e, const int (&v0)[kSchedBatch],
@@ -282,11 +285,12 @@ __device__ __forceinline__ void batch_tiles(const EvalArgs& a, const Workspace& 
   }
 }
 
+template <int BLOCK>
 __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& ws) {
-  constexpr int kNW = kSchedBlock / kWave;
+  constexpr int kNW = BLOCK / kWave;
   __shared__ int s_sum[kNW];
   const int t = threadIdx.x;
-  const int chunk = (n_total + kSchedBlock - 1) / kSchedBlock;
+  const int chunk = (n_total + BLOCK - 1) / BLOCK;
   const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
   int v0[kSchedBatch];
   load_tiles(a, ws, b, e, v0);
@@ -333,7 +337,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   }
   if (staged) {
     __syncthreads();
-    for (int i = t; i < n_total; i += kSchedBlock) ws.item_off[i] = s_map[i];
+    for (int i = t; i < n_total; i += BLOCK) ws.item_off[i] = s_map[i];
     __syncthreads();
   }
   // the item -> particle map, staged in LDS one window at a time so that the global stores
@@ -357,7 +361,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
       }
     }
     __syncthreads();
-    for (int q = w0 + t; q < w1; q += kSchedBlock) ws.item_map[q] = s_map[q - w0];
+    for (int q = w0 + t; q < w1; q += BLOCK) ws.item_map[q] = s_map[q - w0];
     __syncthreads();
   }
   if (t == 0) {
@@ -914,8 +918,9 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
 // The work list is built by its own one-workgroup launch: folding it into the kinematics
 // kernel as "the last workgroup to finish builds it" needs a device-scope fence in every
 // workgroup, which on a multi-XCD part (one L2 per XCD) costs far more than a launch.
-__global__ __launch_bounds__(kSchedBlock) void sched_kernel(EvalArgs a, Workspace ws) {
-  schedule_items(a, a.n_frames * a.n_particles, ws);
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void sched_kernel(EvalArgs a, Workspace ws) {
+  schedule_items<BLOCK>(a, a.n_frames * a.n_particles, ws);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1767,7 +1772,10 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
                          dim3(kBlock), 0, s, a, ws);
       break;
     case kStageSched:
-      hipLaunchKernelGGL(sched_kernel, dim3(1), dim3(kSchedBlock), 0, s, a, ws);
+      if (n_total <= kSchedSmall)
+        hipLaunchKernelGGL(sched_kernel<kSchedSmall>, dim3(1), dim3(kSchedSmall), 0, s, a, ws);
+      else
+        hipLaunchKernelGGL(sched_kernel<kSchedBlock>, dim3(1), dim3(kSchedBlock), 0, s, a, ws);
       if (dbg) {
         const size_t n = (size_t)a.n_particles * a.dbg_H * a.dbg_W;
         hipLaunchKernelGGL(debug_fill_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
