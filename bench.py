@@ -36,8 +36,8 @@ METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at 
 # reads half the bytes read, WRITE_SIZE all the bytes written).  Keyed by the SHA-256 of the
 # kernel sources it was measured on: any later change of the kernel reports null.
 MEASURED_TRAFFIC = {
-    "6a0bf9027ffbddd7d97cdceb53bf8a377ea98d31603b7aa1cea27bc2d0806b19": {
-        "config": 4, "fetch_kib": 15149.707, "write_kib": 303.665, "fetch_scale": 2.0,
+    "bfafab2847efebeed25649e1db4f6909f5d57f930ab71d786608eca891a2c5b7": {
+        "config": 4, "fetch_kib": 15146.664, "write_kib": 303.679, "fetch_scale": 2.0,
         "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",
