@@ -168,3 +168,34 @@ def test_full_frame_two_hands_sampled_particles():
 def test_camera_helper_and_config_shapes():
     assert camera_for_roi(64, 64) == (144.0, 144.0, 31.5, 31.5)
     assert camera_for_roi(640, 480, True)[0] == 575.0
+
+
+def test_launch_shapes_and_autotuner_keep_costs_bit_identical():
+    """Every launch shape gives bit-identical costs (partials are combined in item order and
+    the FP64 depth sums are exact), the autotuner returns one of its candidates and keeps it,
+    and out-of-range shapes are rejected."""
+    import paper_2005_07068_amd as ht
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(4)
+    poses = particles_for(model, fr, 64, seed=9)
+    ctx = make_ctx(model, [fr])
+    dev = torch.device("cuda:0")
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    x = torch.tensor(poses, device=dev)
+    ref = None
+    for tpi, gpc, cull in [(4, 1, 0), (16, 2, 1), (64, 8, 1), (1024, 64, 1), (8, 3, 0)]:
+        ctx.set_launch_config(tpi, gpc, cull)
+        assert ctx.launch_config() == (tpi, gpc, cull)
+        c = ctx.eval(x, slots).cpu().numpy()
+        if ref is None:
+            ref = c
+        assert np.array_equal(c, ref), (tpi, gpc, cull)
+    lc = ctx.autotune(x[None], slots, repeats=2)
+    assert lc[0] in (4, 8, 16, 32, 64) and lc[1] in (1, 2, 4, 8) and lc[2] in (0, 1)
+    assert ctx.launch_config() == lc
+    assert np.array_equal(ctx.eval(x, slots).cpu().numpy(), ref)
+    for bad in [(3, 1, 1), (2048, 1, 1), (16, 0, 1), (16, 65, 1), (16, 1, 2)]:
+        with pytest.raises(Exception):
+            ctx.set_launch_config(*bad)
+    assert ctx.launch_config() == lc
+    ctx.close()
