@@ -239,3 +239,25 @@ def test_whole_runs_match_the_oracle_distribution():
         assert stats.ks_2samp(a, b).pvalue > 0.01
         se = np.sqrt(np.var(a, ddof=1) / len(a) + np.var(b, ddof=1) / len(b))
         assert abs(np.mean(a) - np.mean(b)) <= 3.0 * se
+
+
+def test_kernel_tracing_counts_one_refined_generation():
+    """The per-kernel trace of one generation with refinement (K = 8, 2 steps, workspace
+    reserved, so the first gradient evaluation reuses the swarm's kinematics): the swarm
+    evaluation, the gradient evaluation of the 8 best, a gradient and a forward evaluation of
+    the 32 candidates, the select and three updates, and the swarm update."""
+    torch, ctx, model, fr, sw, lo, hi = _setup(P=64)
+    ctx.reserve(64 * 4, fr["depth"].size)
+    ctx.pso_init(sw)
+    torch.cuda.synchronize()
+    ctx.profile_begin()
+    ctx.pso_step(sw, ht.pso_params(mutate_every=0, refine_topk=8, refine_steps=2))
+    st = ctx.profile_end()
+    ctx.close()
+    launches = {k: v["launches"] for k, v in st.items()}
+    assert launches == {"fk": 3, "sched": 4, "raycast": 2, "raycast_grad": 2, "finalize": 4,
+                        "pso": 1, "refine": 4}, launches
+    assert st["fk"]["particles"] == 64 + 2 * 32
+    assert st["raycast_grad"]["particles"] == 8 + 32
+    assert st["raycast"]["particles"] == 64 + 32
+    assert all(v["ms"] > 0.0 for v in st.values())
