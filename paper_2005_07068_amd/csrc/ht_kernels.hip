@@ -236,7 +236,7 @@ __device__ int block_scan(int* s_sum, int v, int* total) {
   return v + before;
 }
 
-// Tile counts of particles [i0, i0 + kSchedBatch) clipped to e, loaded together so that their
+// Each thread of the work-list kernel loads kSchedBatch tile counts at a time, so that their
 // latencies overlap (the counts were written by every XCD, so each load misses this L2).
 constexpr int kSchedBatch = 8;
 constexpr int kSchedBlock = 1024;    // threads of the work-list kernel (its only workgroup)
