@@ -30,15 +30,16 @@ PEAK_FP32_VALU = 157.3e12      # MI355X vector FP32, FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E, B/s
 METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at equal pose error"
 
-# HBM traffic of the forward ray-cast kernel: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
-# dispatch, mean over the dispatches of one profiled run of the named workload), each scaled
-# by what the same counter reads for a plain device copy of known size (256 MiB: FETCH_SIZE
-# reads half the bytes read, WRITE_SIZE all the bytes written).  Keyed by the SHA-256 of the
-# kernel sources it was measured on: any later change of the kernel reports null.
-MEASURED_TRAFFIC = {
+# Counters of the forward ray-cast kernel from rocprofv3 runs of the named workload (mean
+# per dispatch over one profiled run): HBM traffic from FETCH_SIZE and WRITE_SIZE (KiB), each
+# scaled by what the same counter reads for a plain device copy of known size (256 MiB:
+# FETCH_SIZE reads half the bytes read, WRITE_SIZE all the bytes written), and the executed
+# FP32 operations (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes).  Keyed by the SHA-256 of the kernel
+# sources they were measured on: any later change of the kernel reports null.
+MEASURED_COUNTERS = {
     "c34b2e4233c13428fd68f7935d6c5419419118d04269dd5ed7b575bd3f680af6": {
         "config": 4, "fetch_kib": 15146.664, "write_kib": 303.679, "fetch_scale": 2.0,
-        "write_scale": 1.0},
+        "write_scale": 1.0, "fp32_flop": 2.318e9},
 }
 KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",
                   "paper_2005_07068_amd/csrc/ht_device.h")
@@ -53,22 +54,31 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(config: int):
-    """Bytes per launch from the counters above, or None if they do not apply."""
-    t = MEASURED_TRAFFIC.get(kernel_source_hash())
+def measured_counters(config: int):
+    """(HBM bytes per launch, executed FP32 FLOP per launch) from the counters above, or
+    (None, None) if they do not apply to this kernel source or workload."""
+    t = MEASURED_COUNTERS.get(kernel_source_hash())
     if t is None or t["config"] != config:
-        return None
-    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+        return None, None
+    return (1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]),
+            t.get("fp32_flop"))
 
 
 def load_workload(idx: int):
+    """Model, stored frames and the oracle's work counts per evaluation of workload idx."""
     from workload import WORKLOADS, make_hand_model, seed_sequence
     cfg = WORKLOADS[idx]
     d = np.load(os.path.join(ROOT, "workload", "data", f"config{idx}.npz"))
     frames = [{"depth": d[f"depth_{f}"], "skin": d[f"skin_{f}"], "cam": tuple(d["cam"][f]),
                "bg": float(d["bg"]), "h_true": d["h_true"][f]} for f in range(cfg.n_frames)]
     model = make_hand_model(seed_sequence(idx, 10_000), cfg.n_hands, cfg.primitive_set)
-    return cfg, model, frames, float(d["flops_per_eval"]), int(d["flops_sample"])
+    work = {"flops_per_eval": float(d["flops_per_eval"]),
+            "flops_hit_tiles_per_eval": float(d["flops_hit_tiles_per_eval"]),
+            "pixels_per_eval": float(d["pixels_per_eval"]),
+            "hit_tile_pixels_per_eval": float(d["hit_tile_pixels_per_eval"]),
+            "fragments_per_eval": [float(c) for c in d["cov_per_eval"]],
+            "sample": int(d["flops_sample"])}
+    return cfg, model, frames, work
 
 
 def joint_error_deg(h, h_true, n_hands):
@@ -198,7 +208,7 @@ def eval_throughput(ht, torch, idx=2, reps=50):
     """Evaluation alone on the 320x240 one-hand workload: its particles (drawn like an
     initial swarm) evaluated forward and with gradients, each looped in a captured graph."""
     from workload.handmodel import init_halfwidth
-    cfg, model, frames, flops_per_eval, _ = load_workload(idx)
+    cfg, model, frames, _ = load_workload(idx)
     fr = frames[0]
     dev = torch.device("cuda:0")
     ctx = ht.Context(0)
@@ -276,7 +286,7 @@ def track_sequence(ht, torch, idx=6, stop_factor=None):
     replay per frame, no host synchronisation in between).  With ``stop_factor`` the stop rule
     is on with stop_cost = stop_factor x the median cost of the true poses."""
     from workload.handmodel import init_halfwidth
-    cfg, model, frames, _, _ = load_workload(idx)
+    cfg, model, frames, _ = load_workload(idx)
     dev = torch.device("cuda:0")
     ctx = ht.Context(0)
     ctx.set_model(model)
@@ -337,7 +347,8 @@ def roofline_sweep(ht, torch, totals=(256, 4096, 65536), min_ms=10.0):
     from workload.handmodel import init_halfwidth
     out = []
     for idx in (2, 3):
-        cfg, model, frames, flops_per_eval, _ = load_workload(idx)
+        cfg, model, frames, work = load_workload(idx)
+        flops_per_eval = work["flops_per_eval"]
         ctx = ht.Context(0)
         ctx.set_model(model)
         for f, fr in enumerate(frames):
@@ -393,10 +404,49 @@ def roofline_sweep(ht, torch, totals=(256, 4096, 65536), min_ms=10.0):
                         "raycast_tflops": flops_per_eval * F * P / (rc_ms / 1e3) / 1e12,
                         "raycast_frac": flops_per_eval * F * P / (rc_ms / 1e3)
                         / PEAK_FP32_VALU,
+                        "raycast_frac_hit_tiles": work["flops_hit_tiles_per_eval"] * F * P
+                        / (rc_ms / 1e3) / PEAK_FP32_VALU,
                         "algorithmic_flops_per_eval": flops_per_eval})
             del g, x, cost
         ctx.close()
     return out
+
+
+def roofline_figures(work, avg_ms, particles_per_launch, model, frames, counters):
+    """Roofline of the forward ray cast from its live average launch duration.
+
+    achieved_definition: W per evaluation with the per-pixel term charged for every ROI pixel
+    (Eq. 4 sums over all of them) x particles per launch / duration; achieved_hit_tiles: the
+    per-pixel term only in the 8x8 tiles holding a model hit (the rest is a per-observation
+    constant); executed: FP32 operations the counters saw / duration.  The reported
+    `achieved` is the definition's figure, capped by the executed one when the counters of
+    this kernel are known."""
+    s = avg_ms / 1e3
+    definition = work["flops_per_eval"] * particles_per_launch / s
+    hit_tiles = work["flops_hit_tiles_per_eval"] * particles_per_launch / s
+    traffic, fp32_flop = counters
+    executed = fp32_flop / s if fp32_flop else None
+    achieved = min(definition, executed) if executed else definition
+    # algorithmic HBM bytes per launch: each particle's pose in and cost out, the observation
+    # (3 bytes per pixel: 16-bit depth + skin) once
+    pose_b = 4 * model["n_dof"]
+    obs_b = 3 * max(fr["depth"].size for fr in frames)
+    alg_bytes = particles_per_launch * (pose_b + 4) + obs_b
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": traffic,
+            "kernel": "raycast_kernel<false,false,%d>" % (5 if model["prim_type"].max() > 2
+                                                          else 3),
+            "avg_launch_ms": avg_ms, "particles_per_launch": particles_per_launch,
+            "achieved_definition": definition / 1e12,
+            "frac_definition": definition / PEAK_FP32_VALU,
+            "achieved_hit_tiles": hit_tiles / 1e12,
+            "frac_hit_tiles": hit_tiles / PEAK_FP32_VALU,
+            "executed": None if executed is None else executed / 1e12,
+            "frac_executed": None if executed is None else executed / PEAK_FP32_VALU,
+            "flops_per_eval": work["flops_per_eval"],
+            "flops_hit_tiles_per_eval": work["flops_hit_tiles_per_eval"],
+            "algorithmic_bytes": alg_bytes,
+            "traffic_over_algorithmic": None if traffic is None else traffic / alg_bytes}
 
 
 def copy_calibration(torch, mib: int):
@@ -463,7 +513,7 @@ def oracle_timing(cores_cap=16):
     out = {"cores": cores, "unit": "particle evals/s", "kind": "oracle", "workloads": {}}
     with mp.get_context("fork").Pool(cores) as pool:
         for idx in (0, 1, 2, 3, 4):
-            cfg, model, frames, _, _ = load_workload(idx)
+            cfg, model, frames, _ = load_workload(idx)
             lo_b, hi_b = model["bounds_lo"], model["bounds_hi"]
             d = init_halfwidth(model["n_dof"], cfg.init_angle_deg, cfg.init_trans_mm)
             lo = [np.clip(fr["h_true"] - d, lo_b, hi_b) for fr in frames]
@@ -562,7 +612,7 @@ def main():
     from workload.handmodel import init_halfwidth
 
     log(f"loading workload {args.config}")
-    cfg, model, frames, flops_per_eval, flops_sample = load_workload(args.config)
+    cfg, model, frames, work = load_workload(args.config)
     baseline = None
     if not args.no_cpu_baseline:
         # before the GPU is initialised: the worker processes are forked from this one
@@ -639,17 +689,8 @@ def main():
     rc = stats["raycast"]
     avg_ms = rc["ms"] / max(rc["launches"], 1)
     particles_per_launch = rc["particles"] / max(rc["launches"], 1)
-    flops_launch = flops_per_eval * particles_per_launch
-    achieved = flops_launch / (avg_ms / 1e3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                "traffic": measured_traffic(args.config),
-                "kernel": "raycast_kernel<false,false,%d>" % (5 if model["prim_type"].max() > 2
-                                                              else 3),
-                "avg_launch_ms": avg_ms,
-                "particles_per_launch": particles_per_launch,
-                "algorithmic_flops_per_eval": flops_per_eval}
-
+    roofline = roofline_figures(work, avg_ms, particles_per_launch, model, frames,
+                                measured_counters(args.config))
     line = {
         "metric": METRIC, "value": value, "unit": "particle evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -668,9 +709,11 @@ def main():
         "wall_s": wall,
         "final_joint_error_deg": err,
         "roofline": roofline,
-        "kernels": {k: {"launches": v["launches"],
-                        "avg_ms": v["ms"] / v["launches"] if v["launches"] else 0.0}
-                    for k, v in stats.items()},
+        # one eager run with every launch bracketed by HIP events: the small kernels' figures
+        # include the event overhead (their sum exceeds the graph replay's ms_per_step)
+        "kernels_eager_traced": {k: {"launches": v["launches"],
+                                     "avg_ms": v["ms"] / v["launches"] if v["launches"] else 0.0}
+                                 for k, v in stats.items()},
     }
     if K == 0 and not args.no_study:
         log("plain swarm over seeds")

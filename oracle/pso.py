@@ -145,25 +145,44 @@ def top_k(costs, K: int) -> np.ndarray:
     return np.array(order[:K], dtype=np.int64)
 
 
-def refine_particle(model, obs, x, E, params: PsoParams, lo, hi):
-    """Normalised steepest-descent refinement of one particle; returns (x, E)."""
+def refine_particle(model, obs, x, E, params: PsoParams, lo, hi, objective=None,
+                    gradient=None, trace=None):
+    """Normalised steepest-descent refinement of one particle; returns (x, E).
+
+    Each step takes the gradient g at x, scales it by eta (g_s = eta * g) and tries the
+    step eta * g_s / max|g_s| and its halves (1/2, 1/4, 1/8) in that order, each clipped to
+    [lo, hi]; the first candidate whose cost is strictly below E(x) is taken.  No decrease
+    (or a zero or non-finite g_s) ends the refinement.  ``objective(x) -> E`` and
+    ``gradient(x) -> (E, g)`` default to the hand cost of Eq. 5 and its analytic gradient.
+    With ``trace`` (a list), one entry per step is appended: the index j of the accepted
+    length 2^-j, -1 for a rejected step, or None when g_s vanished."""
+    if objective is None:
+        def objective(xx):
+            return cost.objective(model, xx, obs)
+    if gradient is None:
+        def gradient(xx):
+            return grad.analytic_gradient(model, xx, obs)
     eta = eta_vector(model, params)
     x = np.asarray(x, np.float64).copy()
     for _ in range(params.refine_steps):
-        E0, g = grad.analytic_gradient(model, x, obs)
+        E0, g = gradient(x)
         gs = eta * g
         n = np.max(np.abs(gs))
         if not np.isfinite(n) or n == 0.0:
+            if trace is not None:
+                trace.append(None)
             break
         delta = eta * gs / n
-        accepted = False
+        accepted = -1
         for j in range(4):
             cand = np.clip(x - delta * 2.0 ** -j, lo, hi)
-            Ec = cost.objective(model, cand, obs)
+            Ec = objective(cand)
             if Ec < E0:
-                x, E, accepted = cand, Ec, True
+                x, E, accepted = cand, Ec, j
                 break
-        if not accepted:
+        if trace is not None:
+            trace.append(accepted)
+        if accepted < 0:
             break
     return x, E
 

@@ -41,18 +41,48 @@ def test_joint_error_metric():
     assert abs(bench.joint_error_deg(h, t, 2) - 1.0) < 1e-12
 
 
-def test_measured_traffic_only_for_the_measured_kernel(monkeypatch):
-    """The roofline traffic figure applies only to the kernel sources it was measured on."""
+def test_measured_counters_only_for_the_measured_kernel(monkeypatch):
+    """The roofline traffic and executed-FLOP figures apply only to the kernel sources they
+    were measured on."""
     sys.path.insert(0, ROOT)
     import bench
     h = bench.kernel_source_hash()
     rec = {"config": 4, "fetch_kib": 100.0, "write_kib": 10.0, "fetch_scale": 2.0,
-           "write_scale": 1.0}
-    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", {h: rec})
-    assert bench.measured_traffic(4) == 1024.0 * (200.0 + 10.0)
-    assert bench.measured_traffic(3) is None
-    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", {"0" * 64: rec})
-    assert bench.measured_traffic(4) is None
+           "write_scale": 1.0, "fp32_flop": 3.0e9}
+    monkeypatch.setattr(bench, "MEASURED_COUNTERS", {h: rec})
+    assert bench.measured_counters(4) == (1024.0 * (200.0 + 10.0), 3.0e9)
+    assert bench.measured_counters(3) == (None, None)
+    monkeypatch.setattr(bench, "MEASURED_COUNTERS", {"0" * 64: rec})
+    assert bench.measured_counters(4) == (None, None)
+
+
+def test_roofline_achieved_never_exceeds_the_executed_rate():
+    """The reported rate is the definition's W x particles / duration, capped by the executed
+    FP32 rate; the hit-tile figure and the byte ratio are reported beside it."""
+    sys.path.insert(0, ROOT)
+    import bench
+    work = {"flops_per_eval": 4.0e6, "flops_hit_tiles_per_eval": 1.0e6}
+    model = {"n_dof": 52, "prim_type": np.zeros(80, np.int32)}
+    frames = [{"depth": np.zeros((480, 640), np.uint16)}]
+    r = bench.roofline_figures(work, 0.1, 500.0, model, frames, (None, None))
+    assert abs(r["achieved"] - 4.0e6 * 500 / 1e-4 / 1e12) < 1e-9
+    assert r["executed"] is None and r["traffic_over_algorithmic"] is None
+    r = bench.roofline_figures(work, 0.1, 500.0, model, frames, (3.0e7, 1.0e9))
+    assert abs(r["achieved"] - 10.0) < 1e-9 and abs(r["executed"] - 10.0) < 1e-9
+    assert r["achieved_definition"] > r["achieved"] > r["achieved_hit_tiles"]
+    assert abs(r["traffic_over_algorithmic"] - 3.0e7 / (500 * 212 + 3 * 640 * 480)) < 1e-9
+
+
+def test_stored_work_counts_reproduce_the_flop_figures():
+    """The stored FLOP figures are the per-unit counts applied to the stored coverage."""
+    from oracle import flops
+    for idx in range(7):
+        d = np.load(os.path.join(ROOT, "workload", "data", f"config{idx}.npz"))
+        assert d["flops_per_eval"] == flops.flops_from_counts(d["cov_per_eval"],
+                                                              d["pixels_per_eval"])
+        assert d["flops_hit_tiles_per_eval"] == flops.flops_from_counts(
+            d["cov_per_eval"], d["hit_tile_pixels_per_eval"])
+        assert 0 < d["hit_tile_pixels_per_eval"] <= d["pixels_per_eval"]
 
 
 def test_first_staying_index():

@@ -2,8 +2,9 @@
 
 Every stored value comes from the CPU oracle: a seeded true pose per frame is rendered by the
 oracle and the noise model of the workloads is applied (the simulation protocol of section
-V.A.1 with sensor noise); the algorithmic work per evaluation (for roofline figures) is the
-oracle's coverage count on a sample of particles drawn like the swarm's initial particles.
+V.A.1 with sensor noise); the algorithmic work per evaluation (for roofline figures) comes
+from the oracle's coverage counts on a sample of particles drawn like the swarm's initial
+particles.
 
     python -m workload.make_data            # all configs
     python -m workload.make_data 1 4        # some
@@ -42,9 +43,11 @@ def make(idx: int, flop_samples: int = 8) -> str:
     out["cam"] = np.array(cams, np.float64)
     out["h_true"] = np.array(hs, np.float64)
     out["bg"] = np.float64(synth.BACKGROUND_MM)
-    # algorithmic work per evaluation on particles drawn like the swarm's initial ones
+    # algorithmic work per evaluation on particles drawn like the swarm's initial ones: the
+    # fragments per primitive type, the ROI pixels and the pixels of the 8x8 tiles holding a
+    # model hit, and the FLOP figures built from them
     rng = np.random.default_rng(seed_sequence(idx, 20_000))
-    work, pixels = [], []
+    covs, pixels, tile_px = [], [], []
     frames = rng.choice(cfg.n_frames, size=min(flop_samples, cfg.n_frames), replace=False) \
         if cfg.n_frames > 1 else np.zeros(1, int)
     per_frame = max(1, flop_samples // len(frames))
@@ -54,10 +57,18 @@ def make(idx: int, flop_samples: int = 8) -> str:
                                     cfg.init_trans_mm, model["bounds_lo"], model["bounds_hi"])
         for h in poses:
             res = raycast.render(model, h, W, H, tuple(out["cam"][f]), synth.BACKGROUND_MM)
-            work.append(flops.eval_flops(res, model["prim_type"]))
-            pixels.append(W * H)
-    out["flops_per_eval"] = np.float64(np.mean(work))
-    out["flops_sample"] = np.int64(len(work))
+            w = flops.work_counts(res, model["prim_type"])
+            covs.append(w["cov_per_type"])
+            pixels.append(w["pixels"])
+            tile_px.append(w["hit_tile_pixels"])
+    out["cov_per_eval"] = np.mean(np.array(covs, np.float64), axis=0)
+    out["pixels_per_eval"] = np.float64(np.mean(pixels))
+    out["hit_tile_pixels_per_eval"] = np.float64(np.mean(tile_px))
+    out["flops_per_eval"] = np.float64(flops.flops_from_counts(out["cov_per_eval"],
+                                                               out["pixels_per_eval"]))
+    out["flops_hit_tiles_per_eval"] = np.float64(
+        flops.flops_from_counts(out["cov_per_eval"], out["hit_tile_pixels_per_eval"]))
+    out["flops_sample"] = np.int64(len(covs))
     os.makedirs(DATA, exist_ok=True)
     path = os.path.join(DATA, f"config{idx}.npz")
     np.savez_compressed(path, **out)
