@@ -243,8 +243,11 @@ ht_status ht_pso_step(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_params* p
                       void* hip_stream);
 
 /* A whole run: ht_pso_init followed by n_generations x ht_pso_step, captured once into a HIP
- * graph (cached in the context per swarm / params / n_generations) and launched on
- * hip_stream.  Requires ht_reserve to cover the swarm.  HT_ERR_HIP if capture fails. */
+ * graph (cached in the context per swarm / params / n_generations, at most 32 graphs: a full
+ * cache is emptied before the next capture) and launched on hip_stream.  A new launch shape
+ * (ht_set_launch_config, ht_autotune), model or larger workspace drops the cached graphs (the
+ * device is synchronised first).  Requires ht_reserve to cover the swarm.  HT_ERR_HIP if
+ * capture fails. */
 ht_status ht_pso_run_graph(ht_ctx* ctx, const ht_swarm* swarm, const ht_pso_params* params,
                            int n_generations, void* hip_stream);
 

@@ -202,6 +202,61 @@ def fd_mask(res, obs_depth, border: int = 2, occlusion_dz: float = 1.0,
     return ~bad
 
 
+def dof_is_translation(model: dict) -> np.ndarray:
+    """True for the wrist translations (mm), False for the angles (rad)."""
+    trans = np.zeros(model["n_dof"], bool)
+    for b in model["seg_root_dof"][model["seg_root_dof"] >= 0]:
+        trans[b:b + 3] = True
+    return trans
+
+
+def fd_protocol_mask(model, h, res, obs, step_rad=1e-3, step_mm=1e-2, **kw):
+    """``fd_mask`` narrowed for central differences with fixed steps: a step moves a pixel's
+    depth by up to reach = max_j |d r_d / d h_j| * step_j (first order), so the kinks of |.| and
+    min(., d_M) and the crease to the second-nearest surface must be farther than twice that
+    for the pixel's term to stay on one smooth piece over [h - step, h + step].  Every change
+    of the nearest primitive between neighbouring pixels is also an edge here, whatever the
+    depth step across it (a primitive emerging from another's surface makes a crease that the
+    pixels beside it, where the emerging primitive misses, cannot see)."""
+    H, W = obs["depth"].shape
+    base = fd_mask(res, obs["depth"], **kw)
+    win = res["winner"]
+    crease = np.zeros((H, W), bool)
+    for dy, dx in ((0, 1), (1, 0), (1, 1), (1, -1)):
+        a = (slice(0, H - dy), slice(max(-dx, 0), W - max(dx, 0)))
+        b = (slice(dy, H), slice(max(dx, 0), W - max(-dx, 0)))
+        e = win[a] != win[b]
+        crease[a] |= e
+        crease[b] |= e
+    base &= ~_dilate(crease, kw.get("border", 2))
+    dz = depth_gradient(model, h, res, W, H, obs["cam"])
+    steps = np.where(dof_is_translation(model), step_mm, step_rad)
+    reach = np.max(np.abs(dz) * steps[:, None, None], axis=0)
+    diff = np.abs(np.asarray(obs["depth"], np.float64) - res["depth"])
+    bad = (diff < 2.0 * reach) | (np.abs(diff - cost.D_CLAMP_MM) < 2.0 * reach)
+    pt = np.sort(res["prim_t"], axis=0)
+    if pt.shape[0] >= 2:
+        with np.errstate(invalid="ignore"):
+            bad |= res["hit"] & (pt[1] - pt[0] < 2.0 * reach)
+    return base & ~bad
+
+
+def gradient_terms(model, h, obs, pixel_mask=None):
+    """Per-pixel terms of the depth part of dE/dh, [n_dof, H, W]: s_p * d r_d(p) / dh /
+    sum(o_s or r_m) (their sum over the pixels plus lambda_k dkc/dh is the analytic
+    gradient)."""
+    h = np.asarray(h, np.float64)
+    E, parts = cost.objective(model, h, obs, return_parts=True)
+    res = parts["render"]
+    H, W = obs["depth"].shape
+    s = depth_sign(obs["depth"], res)
+    if pixel_mask is not None:
+        s = s * np.asarray(pixel_mask, bool)
+    if parts["S_or"] == 0:
+        return np.zeros((model["n_dof"], H, W))
+    return depth_gradient(model, h, res, W, H, obs["cam"]) * s[None] / parts["S_or"]
+
+
 def masked_smooth_cost(model, h, obs, mask, S_or_fixed):
     """(1 / S_or_fixed) * sum over ``mask`` of min(|o_d - r_d(h)|, d_M) + lambda_k kc(h)."""
     H, W = obs["depth"].shape
@@ -215,9 +270,7 @@ def fd_gradient(model, h, obs, mask, S_or_fixed, step_rad=1e-3, step_mm=1e-2, do
     """Central differences of ``masked_smooth_cost``; translation dims use ``step_mm``."""
     h = np.asarray(h, np.float64)
     g = np.zeros(model["n_dof"])
-    trans = np.zeros(model["n_dof"], bool)
-    for b in model["seg_root_dof"][model["seg_root_dof"] >= 0]:
-        trans[b:b + 3] = True
+    trans = dof_is_translation(model)
     for j in (range(model["n_dof"]) if dofs is None else dofs):
         step = step_mm if trans[j] else step_rad
         hp, hm = h.copy(), h.copy()

@@ -131,6 +131,22 @@ def _ptr(t):
     return C.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _dev(t, dtype, shape, name):
+    """Check that t is a contiguous cuda tensor of the given torch dtype and shape (None in
+    shape: any size), so that the library never receives a host pointer or a misread type."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a cuda tensor (got a {t.device} tensor)")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if len(shape) != t.dim() or any(e is not None and e != g for e, g in zip(shape, t.shape)):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+    return t
+
+
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -243,13 +259,21 @@ class Context:
         F, P, D = p3.shape
         if D != self.n_dof:
             raise ValueError(f"poses have {D} parameters, model has {self.n_dof}")
-        p3 = p3.contiguous()
+        p3 = _dev(p3.contiguous(), torch.float32, (F, P, D), "poses")
+        _dev(frame_slots, torch.int32, (F,), "frame_slots")
         if cost is None:
             cost = torch.empty((F, P), device=poses.device, dtype=torch.float32)
+        _dev(cost, torch.float32, (F, P), "cost")
         dbg = None
         if debug is not None:
-            dbg = Debug(int(debug["slot"]), *[_ptr(debug.get(k)) for k in
-                                               ("depth", "hit", "rm", "winner")])
+            slot = int(debug["slot"])
+            if F != 1 or slot not in self.slots:
+                raise ValueError("debug images need one frame whose slot is set")
+            W, H, _ = self.slots[slot]
+            for k, dt in (("depth", torch.float32), ("hit", torch.uint8), ("rm", torch.uint8),
+                          ("winner", torch.int32)):
+                _dev(debug.get(k), dt, (P, H, W), "debug " + k)
+            dbg = Debug(slot, *[_ptr(debug.get(k)) for k in ("depth", "hit", "rm", "winner")])
         _check(self.lib.ht_eval_particles(self.handle, F, _ptr(frame_slots), P, _ptr(p3),
                                           _ptr(cost), C.byref(dbg) if dbg else None, _stream()))
         return cost[0] if squeeze else cost
@@ -259,6 +283,14 @@ class Context:
         squeeze = poses.dim() == 2
         p3 = (poses.unsqueeze(0) if squeeze else poses).contiguous()
         F, P, D = p3.shape
+        _dev(p3, torch.float32, (F, P, self.n_dof), "poses")
+        _dev(frame_slots, torch.int32, (F,), "frame_slots")
+        if pixel_mask is not None:
+            # the frame's slot is on the device: the mask must fit one of the set slots
+            _dev(pixel_mask, torch.uint8, (None, None), "pixel_mask")
+            H, W = pixel_mask.shape
+            if F != 1 or (int(W), int(H)) not in {sl[:2] for sl in self.slots.values()}:
+                raise ValueError("pixel_mask needs one frame and the [H, W] of a set slot")
         cost = torch.empty((F, P), device=poses.device, dtype=torch.float32)
         grad = torch.empty((F, P, D), device=poses.device, dtype=torch.float32)
         _check(self.lib.ht_eval_particles_grad(self.handle, F, _ptr(frame_slots), P, _ptr(p3),

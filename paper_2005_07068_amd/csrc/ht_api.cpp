@@ -132,7 +132,13 @@ namespace {
 
 using ht::kMinTilesPerItem;
 
+constexpr size_t kMaxCachedGraphs = 32;
+
+// Drop every cached graph (they hold buffers, launch shapes and sizes captured earlier); the
+// device is synchronised first, so no launch of them is still running.
 void invalidate_graphs(ht_ctx* c) {
+  if (c->graphs.empty()) return;
+  (void)hipDeviceSynchronize();
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
 }
@@ -843,6 +849,9 @@ ht_status ht_pso_run_graph(ht_ctx* c, const ht_swarm* sw, const ht_pso_params* p
   key.gens = n_gen;
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
+    // the cache is keyed by the whole swarm (buffers and seed): bounded, it is emptied when
+    // full rather than growing with every new swarm
+    if (c->graphs.size() >= kMaxCachedGraphs) invalidate_graphs(c);
     // size every buffer before capture: nothing may be allocated while capturing
     const int F = sw->n_frames, P = sw->n_particles, K = p->refine_topk;
     const bool refine = K > 0 && p->refine_steps > 0;
@@ -934,6 +943,8 @@ ht_status ht_autotune(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n
     c->lc = saved;
     return st;
   }
+  // captured graphs hold the launch shape they were captured with
+  if (std::memcmp(&best_cfg, &saved, sizeof saved) != 0) invalidate_graphs(c);
   c->lc = best_cfg;
   *out = best_cfg;
   return HT_OK;
@@ -989,6 +1000,11 @@ ht_status ht_set_launch_config(ht_ctx* c, const ht_launch_config* cfg) {
   if (cfg->cull != 0 && cfg->cull != 1) return fail(HT_ERR_ARG, "cull must be 0 or 1");
   if (cfg->groups_per_cu < 1 || cfg->groups_per_cu > 64)
     return fail(HT_ERR_ARG, "groups_per_cu %d out of 1..64", cfg->groups_per_cu);
+  if (std::memcmp(cfg, &c->lc, sizeof c->lc) != 0) {
+    // captured graphs hold the launch shape they were captured with
+    DeviceGuard g(c->device);
+    invalidate_graphs(c);
+  }
   c->lc = *cfg;
   return HT_OK;
 }

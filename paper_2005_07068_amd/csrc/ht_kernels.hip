@@ -1462,7 +1462,9 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
           acc_o -= bgs;
         }
       }
-      if (DEBUG && valid) {
+      // the debug images have the host's W x H of the debug slot; a frame slot of another
+      // size would write past them, so stores outside that extent are dropped
+      if (DEBUG && valid && u < a.dbg_W && v < a.dbg_H) {
         const size_t pix = ((size_t)r * a.dbg_H + v) * a.dbg_W + u;
         if (a.dbg.depth) a.dbg.depth[pix] = rd;
         if (a.dbg.hit) a.dbg.hit[pix] = hit ? 1 : 0;

@@ -68,16 +68,42 @@ def eval_debug(ctx, poses, slot, W, H):
     return cost.cpu().numpy(), {k: (v.cpu().numpy() if k != "slot" else v) for k, v in dbg.items()}
 
 
-def check_particle(model, fr, pose, gpu_cost, gdbg, i, depth_rounding_atol=False):
+def oracle_render(model, fr, pose):
+    """The oracle's render of the FP32 pose and its pixel classification (CPU only)."""
+    h = np.asarray(pose, np.float32).astype(np.float64)
+    H, W = fr["depth"].shape
+    res = raycast.render(model, h, W, H, fr["cam"], fr["bg"])
+    return res, raycast.classify_pixels(res, MARGIN_TAU)
+
+
+def _oracle_render_job(args):
+    return oracle_render(*args)
+
+
+def oracle_renders(model, frames_and_poses):
+    """oracle_render for many (frame, pose) pairs, spread over the host cores (at most 16
+    processes, started fresh: the workers run NumPy only and never touch the GPU)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    jobs = [(model, fr, pose) for fr, pose in frames_and_poses]
+    workers = min(16, len(os.sched_getaffinity(0)), len(jobs))
+    if workers <= 1:
+        return [oracle_render(*j) for j in jobs]
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_oracle_render_job, jobs))
+
+
+def check_particle(model, fr, pose, gpu_cost, gdbg, i, depth_rounding_atol=False,
+                   rendered=None):
     """Compare one particle's GPU images and cost with the oracle; returns diagnostics.
 
     With ``depth_rounding_atol`` the cost may also differ by the FP32 rounding of the rendered
     depths it sums (hit pixels x one FP32 ulp of the largest depth / S_or): for an ROI of a few
-    pixels E is a sub-millimetre residual and the relative bar alone is finer than FP32 depth."""
+    pixels E is a sub-millimetre residual and the relative bar alone is finer than FP32 depth.
+    ``rendered``: the oracle_render of this pose, if already computed."""
     h = np.asarray(pose, np.float32).astype(np.float64)
-    H, W = fr["depth"].shape
-    res = raycast.render(model, h, W, H, fr["cam"], fr["bg"])
-    cls = raycast.classify_pixels(res, MARGIN_TAU)
+    res, cls = rendered if rendered is not None else oracle_render(model, fr, pose)
     amb = cls["ambiguous"]
     n_hits = int(res["hit"].sum())
     assert amb.sum() <= max(1, MAX_AMBIGUOUS_FRAC * n_hits), \
@@ -99,13 +125,7 @@ def check_particle(model, fr, pose, gpu_cost, gdbg, i, depth_rounding_atol=False
     rm_amb = amb | (np.abs(np.abs(o_d - res["depth"]) - ocost.D_MATCH_MM) < RM_AMBIG_MM)
     bad_rm = (g_rm != r_m) & ~rm_amb
     assert not bad_rm.any(), f"particle {i}: {bad_rm.sum()} r_m mismatches"
-    # resolved oracle: the GPU's decisions at ambiguous pixels, the oracle's elsewhere
-    r_d = np.where(amb, g_depth, res["depth"])
-    hit = np.where(amb, g_hit, res["hit"])
-    t_d, r_m, _, _ = ocost.pixel_terms(o_d, fr["skin"], r_d, hit)
-    r_m = np.where(rm_amb, g_rm, r_m)
-    o_s = fr["skin"].astype(bool)
-    S_d, S_and, S_or = t_d.sum(), int((o_s & r_m).sum()), int((o_s | r_m).sum())
+    r_d, hit, S_d, S_and, S_or = resolved_sums(fr, res, cls, g_depth, g_hit, g_rm)
     E = ocost.discrepancy_from_sums(S_d, S_and, S_or) + ocost.LAMBDA_K * ocost.kc(model, h)
     tol = COST_RTOL * abs(E)
     if depth_rounding_atol and S_or > 0:
@@ -114,3 +134,66 @@ def check_particle(model, fr, pose, gpu_cost, gdbg, i, depth_rounding_atol=False
     return {"ambiguous": int(amb.sum()), "hits": n_hits,
             "max_depth_err": float(derr.max()) if derr.size else 0.0,
             "cost_rel": abs(gpu_cost - E) / abs(E)}
+
+
+def resolved_sums(fr, res, cls, g_depth, g_hit, g_rm):
+    """The resolved oracle: the GPU's decisions (r_d, hit, r_m of its debug images) at the
+    pixels the oracle classifies as ambiguous (margin < 1e-5, or the d_m test within 1e-3 mm),
+    the oracle's elsewhere.  Returns r_d, hit and the sums S_d, S_and, S_or of Eq. 4."""
+    o_d = fr["depth"].astype(np.float64)
+    amb = cls["ambiguous"]
+    rm_amb = amb | (np.abs(np.abs(o_d - res["depth"]) - ocost.D_MATCH_MM) < RM_AMBIG_MM)
+    r_d = np.where(amb, g_depth, res["depth"])
+    hit = np.where(amb, g_hit, res["hit"])
+    t_d, r_m, _, _ = ocost.pixel_terms(o_d, fr["skin"], r_d, hit)
+    r_m = np.where(rm_amb, g_rm, r_m)
+    o_s = fr["skin"].astype(bool)
+    return r_d, hit, t_d.sum(), int((o_s & r_m).sum()), int((o_s | r_m).sum())
+
+
+def resolved_gradient(model, fr, h, gdbg, i):
+    """The FP64 analytic gradient of E (the oracle's formula) with the GPU's decisions, from
+    its debug images of particle i at the same FP32 pose, at the pixels where the oracle finds
+    them within the parity tolerances: hit (margin < 1e-5), the nearest of two surfaces
+    (entries within twice the depth bar), the sign of r_d - o_d and the d_M clamp (|r_d - o_d|
+    within twice the depth bar of 0 or d_M), and sum(o_s or r_m) as resolved for the cost.
+    Returns (E, g) or (E, None) when the GPU hits where the oracle has no entry point (a
+    margin-ambiguous miss: its depth derivative is not defined there)."""
+    from oracle import grad as ograd
+    h = np.asarray(h, np.float32).astype(np.float64)
+    H, W = fr["depth"].shape
+    res, cls = oracle_render(model, fr, h)
+    g_depth = gdbg["depth"][i].astype(np.float64)
+    g_hit = gdbg["hit"][i].astype(bool)
+    g_win = gdbg["winner"][i]
+    amb = cls["ambiguous"]
+    r_d, hit, S_d, S_and, S_or = resolved_sums(fr, res, cls, g_depth, g_hit,
+                                                gdbg["rm"][i].astype(bool))
+    E = ocost.discrepancy_from_sums(S_d, S_and, S_or) + ocost.LAMBDA_K * ocost.kc(model, h)
+    if np.any(amb & g_hit & ~res["hit"]):
+        return E, None
+    # the nearest surface: the GPU's where two entries are within twice the depth bar
+    pt = np.sort(res["prim_t"], axis=0)
+    with np.errstate(invalid="ignore"):
+        crease = res["hit"] & (pt[1] - pt[0] < 2 * DEPTH_TOL_MM)
+    swap = crease & g_hit & (g_win >= 0) & (g_win != res["winner"])
+    rr = res
+    if swap.any():
+        win = res["winner"].copy()
+        win[swap] = g_win[swap]
+        zmin = res["zmin"].copy()
+        yy, xx = np.nonzero(swap)
+        zmin[swap] = res["prim_t"][win[swap], yy, xx]
+        if not np.all(np.isfinite(zmin[swap])):
+            return E, None
+        rr = dict(res, winner=win, zmin=zmin)
+    dz = ograd.depth_gradient(model, h, rr, W, H, fr["cam"])
+    # s_p with the GPU's depth where its sign or clamp is decided within twice the depth bar
+    o_d = fr["depth"].astype(np.float64)
+    diff = res["depth"] - o_d
+    close = (np.abs(diff) < 2 * DEPTH_TOL_MM) | \
+        (np.abs(np.abs(diff) - ocost.D_CLAMP_MM) < 2 * DEPTH_TOL_MM)
+    diff = np.where(close | amb, g_depth - o_d, diff)
+    s = np.where(hit & (np.abs(diff) < ocost.D_CLAMP_MM), np.sign(diff), 0.0)
+    g = np.einsum("jhw,hw->j", dz, s) / S_or if S_or > 0 else np.zeros(model["n_dof"])
+    return E, g + ocost.LAMBDA_K * ocost.kc_grad(model, h)

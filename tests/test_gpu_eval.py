@@ -3,9 +3,8 @@ the FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
 
-from gpu_util import (check_particle, eval_debug, frame_for, make_ctx, particles_for,
-                      torch_cuda)
-from oracle import cost as ocost
+from gpu_util import (check_particle, eval_debug, frame_for, make_ctx, oracle_renders,
+                      particles_for, torch_cuda)
 from oracle import synth
 from workload import WORKLOADS, make_hand_model, seed_sequence
 from workload.configs import camera_for_roi
@@ -120,27 +119,41 @@ def test_nonfinite_pose_unset_slot_and_empty_call():
     assert out.numel() == 0
 
 
-def test_batched_frames_equal_per_frame_calls():
-    """64 frames of uneven ROIs (48..192 px): one launch == one call per frame (bit-identical)."""
+def test_batched_frames_equal_per_frame_calls_and_the_oracle():
+    """The uneven-ROI workload's frames (48..192 px per side): one batched launch over 8 frames
+    x 16 particles == one call per frame, bit for bit; every cost of the batched launch against
+    the resolved oracle at the 1e-5 bar (the per-frame debug calls, bit-identical to the
+    batched launch, give the GPU's decisions at ambiguous pixels)."""
     torch = torch_cuda()
     cfg = WORKLOADS[3]
     model = make_hand_model(seed_sequence(3, 10_000))
-    frames = [synth.make_frame(model, cfg, f) for f in range(6)]
+    frames = [synth.make_frame(model, cfg, f) for f in range(8)]
     ctx = make_ctx(model, frames)
     dev = torch.device("cuda:0")
     P = 16
     poses = np.stack([particles_for(model, fr, P, seed=10 + i) for i, fr in enumerate(frames)])
     slots = torch.arange(len(frames), dtype=torch.int32, device=dev)
     batched = ctx.eval(torch.tensor(poses, device=dev), slots).cpu().numpy()
-    for f in range(len(frames)):
+    dbgs = []
+    for f, fr in enumerate(frames):
         one = ctx.eval(torch.tensor(poses[f], device=dev),
                        torch.tensor([f], dtype=torch.int32, device=dev)).cpu().numpy()
         assert np.array_equal(one, batched[f])
-    # and the first two frames' costs against the oracle
-    for f in range(2):
-        for i in range(0, P, 5):
-            E = ocost.objective(model, poses[f, i].astype(np.float64), frames[f])
-            assert abs(batched[f, i] - E) <= 1e-3 * E
+        H, W = fr["depth"].shape
+        c_dbg, dbg = eval_debug(ctx, poses[f], f, W, H)
+        assert np.array_equal(c_dbg, batched[f])
+        dbgs.append(dbg)
+    ctx.close()
+    rendered = oracle_renders(model, [(frames[f], poses[f, i]) for f in range(len(frames))
+                                      for i in range(P)])
+    rel = []
+    for f, fr in enumerate(frames):
+        for i in range(P):
+            d = check_particle(model, fr, poses[f, i], batched[f, i], dbgs[f], i,
+                               rendered=rendered[f * P + i])
+            rel.append(d["cost_rel"])
+    print(f"batched: {len(rel)} costs, max relative difference {max(rel):.2e}")
+    assert len({fr["depth"].shape for fr in frames}) == len(frames)   # uneven ROIs
 
 
 def test_full_size_adjoint_shape_sampled_particles():
@@ -155,14 +168,19 @@ def test_full_size_adjoint_shape_sampled_particles():
 
 
 def test_full_frame_two_hands_sampled_particles():
-    """640x480 workload: two hands (80 primitives, 52-D), 1024 particles."""
+    """640x480 workload: two hands (80 primitives, 52-D), 1024 particles in one launch; 32 of
+    them (every 32nd, first and last included) against the resolved oracle."""
     cfg, model, fr = frame_for(4)
     poses = particles_for(model, fr, cfg.n_particles, seed=12)
     ctx = make_ctx(model, [fr])
     cost, dbg = eval_debug(ctx, poses, 0, 640, 480)
+    ctx.close()
     assert np.all(np.isfinite(cost))
-    for i in (0, 511, 1023):
-        check_particle(model, fr, poses[i], cost[i], dbg, i)
+    idx = list(range(0, 1024, 33)) + [1023]
+    assert len(idx) >= 32
+    rendered = oracle_renders(model, [(fr, poses[i]) for i in idx])
+    for i, rd in zip(idx, rendered):
+        check_particle(model, fr, poses[i], cost[i], dbg, i, rendered=rd)
 
 
 def test_camera_helper_and_config_shapes():

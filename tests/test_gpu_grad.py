@@ -75,3 +75,27 @@ def test_autograd_function_backward():
     assert torch.allclose(p.grad, w[:, None] * g2)
     c3 = ctx.eval(p.detach(), slots)
     assert torch.allclose(c3, c2, rtol=1e-6, atol=0)
+
+
+def test_nonfinite_pose_gives_infinite_cost_and_zero_gradient():
+    """A pose with a NaN or an infinite component scores +inf with a zero gradient (not an
+    error), in a launch beside finite poses whose results are unaffected."""
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(0)
+    poses = particles_for(model, fr, 4, seed=8)
+    ctx = make_ctx(model, [fr])
+    dev = torch.device("cuda:0")
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    c_ref, g_ref = ctx.eval_grad(torch.tensor(poses, device=dev), slots)
+    bad = poses.copy()
+    bad[1, 5] = np.nan
+    bad[3, 21] = -np.inf
+    c, g = ctx.eval_grad(torch.tensor(bad, device=dev), slots)
+    ctx.close()
+    c, g = c.cpu().numpy(), g.cpu().numpy()
+    c_ref, g_ref = c_ref.cpu().numpy(), g_ref.cpu().numpy()
+    assert c[1] == np.inf and c[3] == np.inf
+    assert np.all(g[1] == 0.0) and np.all(g[3] == 0.0)
+    for i in (0, 2):
+        assert c[i] == c_ref[i] and np.array_equal(g[i], g_ref[i])
+        assert np.any(g[i] != 0.0)

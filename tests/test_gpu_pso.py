@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import paper_2005_07068_amd as ht
-from gpu_util import frame_for, make_ctx, torch_cuda
+from gpu_util import frame_for, make_ctx, oracle_renders, torch_cuda
 from oracle import philox, pso
 
 pytestmark = pytest.mark.gpu
@@ -43,8 +43,24 @@ def test_init_matches_oracle():
     assert np.all(np.isinf(sw["pbest_cost"].cpu().numpy()))
 
 
+W_PAPER = float(pso.constriction(2.8, 1.3))
+CONSTANTS = {
+    # the workloads' literal constants, with the mutation of section III.B
+    "workload": dict(w=0.72, c1=2.05, c2=2.05, mutate_every=3),
+    # section III.B: c1 = 2.8, c2 = 1.3 and the constriction factor w of psi = c1 + c2
+    "paper": dict(w=W_PAPER, c1=2.8, c2=1.3, mutate_every=3),
+    # without the mutation step
+    "no_mutation": dict(w=0.72, c1=2.05, c2=2.05, mutate_every=0),
+    "paper_no_mutation": dict(w=W_PAPER, c1=2.8, c2=1.3, mutate_every=0),
+}
+
+
+@pytest.mark.parametrize("consts", sorted(CONSTANTS))
 @pytest.mark.parametrize("gen", [0, 2])
-def test_single_generation_matches_oracle(gen):
+def test_single_generation_matches_oracle(gen, consts):
+    """One generation from a mid-run state against the oracle's update, for each set of swarm
+    constants (generation 2 is a mutation generation when the mutation is on)."""
+    kw = CONSTANTS[consts]
     torch, ctx, model, fr, sw, lo, hi = _setup()
     ctx.pso_init(sw)
     rng = np.random.default_rng(gen)
@@ -56,12 +72,13 @@ def test_single_generation_matches_oracle(gen):
     sw["gen"].fill_(gen)
     torch.cuda.synchronize()
     before = _host(sw)
-    params = ht.pso_params(w=0.72, c1=2.05, c2=2.05)
+    params = ht.pso_params(**kw)
     ctx.pso_step(sw, params)
     torch.cuda.synchronize()
     costs = sw["cost"].cpu().numpy().astype(np.float64)
     after = _host(sw)
-    ref = pso.update(before, costs, pso.PsoParams(w=0.72, c1=2.05, c2=2.05),
+    ref = pso.update(before, costs, pso.PsoParams(w=float(np.float32(kw["w"])), c1=kw["c1"],
+                                                  c2=kw["c2"], mutate_every=kw["mutate_every"]),
                      model["bounds_lo"].astype(np.float32), model["bounds_hi"].astype(np.float32),
                      model["mutate_mask"], 123456789012345)
     assert np.array_equal(after["pbest_cost"], ref["pbest_cost"])
@@ -69,9 +86,13 @@ def test_single_generation_matches_oracle(gen):
     assert after["gen"][0] == gen + 1
     for k in ("x", "v", "pbest_x", "gbest_x"):
         assert np.allclose(after[k], ref[k], rtol=1e-5, atol=2e-5), k
-    if gen == 2:
-        moved = np.any(after["x"][0, :, :20] != before["x"][0, :, :20], axis=1)
-        assert moved.sum() >= 32
+    # mutated particles (only in a mutation generation with the mutation on): their finger
+    # dimensions are re-drawn and their velocity there zeroed
+    zeroed = np.all(after["v"][0, :, :20] == 0.0, axis=1)
+    if gen == 2 and kw["mutate_every"] == 3:
+        assert zeroed.sum() >= 32
+    else:
+        assert not zeroed.any()
 
 
 @pytest.mark.parametrize("P", [100, 600, 1000])
@@ -261,3 +282,104 @@ def test_kernel_tracing_counts_one_refined_generation():
     assert st["raycast_grad"]["particles"] == 8 + 32
     assert st["raycast"]["particles"] == 64 + 32
     assert all(v["ms"] > 0.0 for v in st.values())
+
+
+def test_refinement_matches_the_oracle_step_by_step():
+    """The HIP refinement (gradient, four step lengths, accept, write-back into the swarm)
+    against oracle.pso.refine_particle, one step at a time from the GPU's state (single-step
+    parity, as for the swarm update), on the 128x128 frame: 12 particles within 1 deg / 1 mm
+    of the true pose (steps halved or rejected, some at the first step) and 12 within
+    3 deg / 3 mm (mostly full steps), all 24 refined (K = P), 3 steps.  With w = c1 = c2 = 0
+    and no mutation a generation moves nobody, so the swarm's positions after each generation
+    are the refined ones.
+
+    Per step and particle, the oracle takes one step from the GPU's FP32 position with the
+    resolved FP64 gradient (the oracle's formula, with the GPU's per-pixel decisions where the
+    oracle finds them within the parity tolerances, from its debug images at that position).
+    A step is compared when its accept decision is clear (every candidate cost differs from
+    the current one by more than 1e-4 relative, the FP32 costs agree with the oracle's to
+    about 1e-5, plus the most the candidate's margin-ambiguous pixels can move it): the new
+    position must equal the oracle's to 1e-3 of the step scale eta per
+    parameter (a different decision moves the parameter with the largest |eta g| by at least
+    eta / 16), and the new cost must be the resolved oracle's cost there (1e-5 relative).
+    Finally the three steps chained in one generation (candidates evaluated with their
+    gradients, a stopped particle proposing nothing new) end where the single steps end."""
+    torch, ctx, model, fr, sw, lo, hi = _setup(P=24)
+    from gpu_util import check_particle, eval_debug, particles_for, resolved_gradient
+    from oracle import cost as ocost
+    from oracle import raycast
+    near = particles_for(model, fr, 12, seed=7, angle_deg=1.0, trans_mm=1.0)
+    mid = particles_for(model, fr, 12, seed=8, angle_deg=3.0, trans_mm=3.0)
+    x0 = np.concatenate([near, mid])
+    K, S = 24, 3
+    H, W = fr["depth"].shape
+    blo = model["bounds_lo"].astype(np.float32).astype(np.float64)
+    bhi = model["bounds_hi"].astype(np.float32).astype(np.float64)
+    one = pso.PsoParams(mutate_every=0, refine_topk=K, refine_steps=1)
+    eta = pso.eta_vector(model, one)
+    ctx.pso_init(sw)
+    sw["x"].copy_(torch.tensor(x0[None]))
+    step_p = ht.pso_params(w=0.0, c1=0.0, c2=0.0, mutate_every=0, refine_topk=K, refine_steps=1)
+    n_cmp, rejected, halved, skipped = 0, 0, 0, 0
+    first_rejected = set()
+    for step in range(S):
+        xs = sw["x"].cpu().numpy()[0].copy()
+        c_s, dbg = eval_debug(ctx, xs, 0, W, H)
+        ctx.pso_step(sw, step_p)
+        torch.cuda.synchronize()
+        xn = sw["x"].cpu().numpy()[0].astype(np.float64)
+        cn = sw["cost"].cpu().numpy()[0]
+        assert np.all(cn <= c_s)
+        for i in range(K):
+            clear, cur = [], [None]
+
+            def objective(xx):
+                # the decision E(candidate) < E(x) is clear when the gap exceeds 1e-4 of E
+                # plus what the pixels decided within the margin can move E: each at most
+                # (d_M + 2 lambda) / sum(o_s or r_m)
+                e, parts = ocost.objective(model, xx, fr, return_parts=True)
+                n_amb = int(raycast.classify_pixels(parts["render"])["ambiguous"].sum())
+                per_px = (ocost.D_CLAMP_MM + 2 * ocost.LAMBDA) / max(parts["S_or"], 1)
+                bound = 1e-4 * e + n_amb * per_px
+                clear.append(abs(e - cur[0]) > bound)
+                return e
+
+            def gradient(xx, i=i):
+                e, g = resolved_gradient(model, fr, xx, dbg, i)
+                cur[0] = e
+                return e, (g if g is not None else np.full(model["n_dof"], np.nan))
+
+            trace = []
+            xr, _ = pso.refine_particle(model, fr, xs[i].astype(np.float64), None, one, blo,
+                                        bhi, objective=objective, gradient=gradient,
+                                        trace=trace)
+            if trace == [None] or not all(clear):
+                skipped += 1          # undefined resolved gradient or a near-tie decision
+                continue
+            n_cmp += 1
+            rejected += trace == [-1]
+            halved += trace[0] > 0
+            if step == 0 and trace == [-1]:
+                first_rejected.add(i)
+            err = np.abs(xn[i] - xr)
+            assert np.all(err <= 1e-3 * eta), (step, i, trace, float(np.max(err / eta)))
+            if trace == [-1]:
+                assert np.array_equal(xn[i], xs[i].astype(np.float64)) and cn[i] == c_s[i]
+        # the new costs are the GPU's evaluations at the new positions: the resolved oracle
+        c_new, dbg_new = eval_debug(ctx, xn.astype(np.float32), 0, W, H)
+        assert np.array_equal(c_new, cn)
+        rendered = oracle_renders(model, [(fr, xn[i]) for i in range(K)])
+        for i in range(K):
+            check_particle(model, fr, xn[i], cn[i], dbg_new, i, rendered=rendered[i])
+    print(f"refinement: {n_cmp} of {S * K} steps compared ({skipped} not), {rejected} "
+          f"rejected ({len(first_rejected)} at the first step), {halved} halved")
+    assert n_cmp >= 0.75 * S * K and first_rejected and halved >= 8
+    # the chained refinement of one generation ends where the single steps end
+    x_steps = sw["x"].cpu().numpy()[0].astype(np.float64)
+    ctx.pso_init(sw)
+    sw["x"].copy_(torch.tensor(x0[None]))
+    ctx.pso_step(sw, ht.pso_params(w=0.0, c1=0.0, c2=0.0, mutate_every=0, refine_topk=K,
+                                   refine_steps=S))
+    x_chain = sw["x"].cpu().numpy()[0].astype(np.float64)
+    ctx.close()
+    assert np.all(np.abs(x_chain - x_steps) <= 1e-3 * eta)

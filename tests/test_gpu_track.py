@@ -7,11 +7,93 @@ import pytest
 
 import paper_2005_07068_amd as ht
 from gpu_util import frame_for, make_ctx, torch_cuda
-from oracle import synth
+from oracle import pso, synth
 from workload import WORKLOADS, make_hand_model, seed_sequence
 from workload.handmodel import init_halfwidth
 
 pytestmark = pytest.mark.gpu
+
+
+def test_box_around_matches_the_oracle():
+    """The tracking box against oracle.pso.box_around (FP64 on the FP32 inputs); its outputs
+    are a clip, a difference and a sum of FP32 values, so they agree within one FP32
+    rounding of each endpoint."""
+    torch = torch_cuda()
+    model = make_hand_model(seed_sequence(1, 10_000))
+    ctx = make_ctx(model, [])
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(4)
+    F, D = 7, 26
+    lo_b = model["bounds_lo"].astype(np.float32)
+    hi_b = model["bounds_hi"].astype(np.float32)
+    center = (lo_b + rng.uniform(-0.3, 1.3, (F, D)) * (hi_b - lo_b)).astype(np.float32)
+    hw = init_halfwidth(D, 10.0, 20.0).astype(np.float32)
+    lo = torch.empty((F, D), device=dev)
+    hi = torch.empty((F, D), device=dev)
+    ctx.box_around(torch.tensor(center, device=dev), torch.tensor(hw, device=dev), lo, hi)
+    ctx.close()
+    for f in range(F):
+        r_lo, r_hi = pso.box_around(center[f].astype(np.float64), hw.astype(np.float64),
+                                    lo_b.astype(np.float64), hi_b.astype(np.float64))
+        for got, ref in ((lo.cpu().numpy()[f], r_lo), (hi.cpu().numpy()[f], r_hi)):
+            ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+            assert np.all(np.abs(got.astype(np.float64) - ref) <= ulp)
+    # clipped centres: the box stays inside the bounds and contains the clipped centre
+    c = np.clip(center, lo_b, hi_b)
+    assert np.all(lo.cpu().numpy() >= lo_b) and np.all(hi.cpu().numpy() <= hi_b)
+    assert np.all(lo.cpu().numpy() <= c) and np.all(c <= hi.cpu().numpy())
+
+
+def test_stop_rule_generation_matches_the_oracle():
+    """Two frames, one generation with the stop rule on and the threshold between the two
+    frames' best costs: the GPU state after the generation against oracle.pso.update with
+    stop_cost > 0 from the same state and the GPU's costs (the frame below the threshold keeps
+    its bests, does not move and records stop_gen; the other moves by Eq. 6-7), and a second
+    generation, in which the stopped frame changes nothing."""
+    torch = torch_cuda()
+    dev = torch.device("cuda:0")
+    cfg, model, fr0 = frame_for(3, 0)
+    _, _, fr1 = frame_for(3, 1)
+    ctx = make_ctx(model, [fr0, fr1])
+    sw = _two_frame_swarm(ctx, model, [fr0, fr1], dev, seed=77)
+    ctx.pso_init(sw)
+    x = sw["x"].clone()
+    c0 = ctx.eval(x, sw["frame_slots"]).cpu().numpy()
+    g = c0.min(axis=1)
+    a = int(np.argmin(g))
+    b = 1 - a
+    stop_cost = float(g[a]) + 0.5 * float(g[b] - g[a])
+    params = ht.pso_params(stop_cost=stop_cost)
+    o_params = pso.PsoParams(w=float(np.float32(0.72)), c1=2.05, c2=2.05,
+                             stop_cost=float(np.float32(stop_cost)))
+    lo_b = model["bounds_lo"].astype(np.float32)
+    hi_b = model["bounds_hi"].astype(np.float32)
+    keys = ("x", "v", "pbest_x", "pbest_cost", "gbest_x", "gbest_cost", "gen", "stop_gen")
+
+    def host():
+        return {k: sw[k].cpu().numpy().astype(np.int64 if k in ("gen", "stop_gen")
+                                                else np.float64) for k in keys}
+
+    for step in range(2):
+        before = host()
+        ctx.pso_step(sw, params)
+        torch.cuda.synchronize()
+        after = host()
+        costs = sw["cost"].cpu().numpy().astype(np.float64)
+        if step == 0:
+            assert np.array_equal(costs, c0.astype(np.float64))
+        ref = pso.update(before, costs, o_params, lo_b, hi_b, model["mutate_mask"], 77)
+        for k in ("gen", "stop_gen", "pbest_cost", "gbest_cost"):
+            assert np.array_equal(after[k], ref[k]), (step, k)
+        for k in ("x", "v", "pbest_x", "gbest_x"):
+            assert np.allclose(after[k], ref[k], rtol=1e-5, atol=2e-5), (step, k)
+        assert after["stop_gen"][a] == 1
+        # the stopped frame: nothing changes after its stopping generation
+        assert np.array_equal(after["x"][a], before["x"][a])
+        assert np.array_equal(after["v"][a], before["v"][a])
+        if after["stop_gen"][b] == 0:
+            assert not np.array_equal(after["x"][b], before["x"][b])
+    ctx.close()
 
 
 def test_box_around_matches_float32_formula():
