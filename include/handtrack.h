@@ -194,6 +194,22 @@ ht_status ht_eval_particles_grad(ht_ctx* ctx, int n_frames, const int32_t* frame
                                  int n_particles, const float* poses, float* cost, float* grad,
                                  const uint8_t* pixel_mask, void* hip_stream);
 
+/* ht_eval_particles (forward, no debug images) for callers that cannot allocate device
+ * memory: code under HIP graph capture without a prior ht_reserve, tight serving loops,
+ * harnesses that forbid allocation.  The call allocates nothing: its workspace (kinematics
+ * records, work list, partial sums) is a 64 MiB device array inside the library, one per GPU,
+ * held until the process ends.  Every call on a GPU shares that GPU's array, so calls that
+ * overlap on one GPU (on different streams, or from different contexts) race: enqueue them on
+ * one stream.  Nothing in it must start at zero (the work-list kernel of each call resets its
+ * dequeue counter), and it keeps the last call's contents.  Same arguments, layouts and
+ * results as ht_eval_particles.  Errors as ht_eval_particles, and HT_ERR_ARG when the call
+ * needs more than the 64 MiB (about 1800 two-hand particles over 640x480 observations, 8000
+ * one-hand particles over 128x128 ones: the size grows with the particles and the largest
+ * set observation). */
+ht_status ht_eval_particles_noalloc(ht_ctx* ctx, int n_frames, const int32_t* frame_slots,
+                                    int n_particles, const float* poses, float* cost,
+                                    void* hip_stream);
+
 /* Swarm state, all device memory owned by the caller, float32 unless noted:
  *   x, v, pbest_x [F][P][n_dof]; pbest_cost, cost [F][P]; gbest_x [F][n_dof];
  *   gbest_cost [F]; gen: int32 [F] generation counters; frame_slots: int32 [F];

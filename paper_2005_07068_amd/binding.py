@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     lib.ht_reserve.argtypes = [P, I, I]
     lib.ht_eval_particles.argtypes = [P, I, P, I, P, P, C.POINTER(Debug), P]
     lib.ht_eval_particles_grad.argtypes = [P, I, P, I, P, P, P, P, P]
+    lib.ht_eval_particles_noalloc.argtypes = [P, I, P, I, P, P, P]
     lib.ht_pso_init.argtypes = [P, C.POINTER(Swarm), P]
     lib.ht_pso_step.argtypes = [P, C.POINTER(Swarm), C.POINTER(PsoParams), P]
     lib.ht_pso_run_graph.argtypes = [P, C.POINTER(Swarm), C.POINTER(PsoParams), I, P]
@@ -114,7 +115,8 @@ def load_library(path: str = LIB_PATH):
     lib.ht_profile_begin.argtypes = [P]
     lib.ht_profile_end.argtypes = [P, C.POINTER(KernelStat)]
     for name in ("ht_profile_begin", "ht_profile_end", "ht_create", "ht_set_model", "ht_set_observation", "ht_reserve",
-                 "ht_eval_particles", "ht_eval_particles_grad", "ht_pso_init", "ht_pso_step",
+                 "ht_eval_particles", "ht_eval_particles_grad", "ht_eval_particles_noalloc",
+                 "ht_pso_init", "ht_pso_step",
                  "ht_pso_run_graph", "ht_get_launch_config", "ht_set_launch_config",
                  "ht_autotune"):
         getattr(lib, name).restype = S
@@ -276,6 +278,22 @@ class Context:
             dbg = Debug(slot, *[_ptr(debug.get(k)) for k in ("depth", "hit", "rm", "winner")])
         _check(self.lib.ht_eval_particles(self.handle, F, _ptr(frame_slots), P, _ptr(p3),
                                           _ptr(cost), C.byref(dbg) if dbg else None, _stream()))
+        return cost[0] if squeeze else cost
+
+    def eval_noalloc(self, poses, frame_slots, cost=None):
+        """eval through ht_eval_particles_noalloc (the library's fixed scratch array, no
+        allocation on the device)."""
+        import torch
+        squeeze = poses.dim() == 2
+        p3 = (poses.unsqueeze(0) if squeeze else poses).contiguous()
+        F, P, D = p3.shape
+        _dev(p3, torch.float32, (F, P, self.n_dof), "poses")
+        _dev(frame_slots, torch.int32, (F,), "frame_slots")
+        if cost is None:
+            cost = torch.empty((F, P), device=poses.device, dtype=torch.float32)
+        _dev(cost, torch.float32, (F, P), "cost")
+        _check(self.lib.ht_eval_particles_noalloc(self.handle, F, _ptr(frame_slots), P,
+                                                  _ptr(p3), _ptr(cost), _stream()))
         return cost[0] if squeeze else cost
 
     def eval_grad(self, poses, frame_slots, pixel_mask=None):

@@ -9,12 +9,22 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "handtrack.h"
 #include "ht_device.h"
+
+// Scratch of ht_eval_particles_noalloc: the evaluation workspace of one call, carved out of a
+// file-scope device array (each GPU that loads the library holds its own copy until the
+// process ends).  In host code `scratch` only names the symbol: its device address on each
+// GPU comes from hipGetSymbolAddress with that GPU current (scratch_address below) and is the
+// only form in which the array is handed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -49,6 +59,25 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `dev`, looked up once per device.
+hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 template <class T>
 void dfree(T*& p) {
@@ -111,6 +140,7 @@ struct ht_ctx {
   int* seg_partial = nullptr; // [cap_seg] per-block minima of the preprocessing
   int cap_seg = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
+  void* scratch = nullptr;    // this device's address of the no-allocation scratch array
   // tracing of eager launches
   struct ProfRec {
     int kind;
@@ -214,6 +244,43 @@ ht_status ensure_workspace(ht_ctx* c, int n_total, int max_tiles, bool grad, hip
   return HT_OK;
 }
 
+// Work items that a call over n_total particles and observations of max_tiles tiles can
+// produce (items are never shorter than kMinTilesPerItem tiles).
+long long item_bound(int n_total, int max_tiles) {
+  return std::max<long long>(
+      (long long)n_total * ((max_tiles + kMinTilesPerItem - 1) / kMinTilesPerItem), 1);
+}
+
+// Lays the forward-evaluation workspace of np particles and ni work items out from base in
+// 256-byte aligned pieces (no wrench buffer) and returns the bytes it spans; base == nullptr
+// computes the size only.
+size_t carve_workspace(unsigned char* base, long long np, long long ni, int n_prim, int n_dof,
+                       int n_seg, ht::Workspace* w) {
+  size_t off = 0;
+  auto take = [&](auto*& ptr, size_t bytes) {
+    off = (off + 255) / 256 * 256;
+    ptr = base ? reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(base + off) : nullptr;
+    off += bytes;
+  };
+  ht::Workspace t{};
+  take(t.recs, (size_t)np * n_prim * ht::kRec * sizeof(float));
+  take(t.boxes, (size_t)np * n_prim * sizeof(int4));
+  take(t.caps, (size_t)np * n_prim * sizeof(float4));
+  take(t.capr, (size_t)np * n_prim * sizeof(float2));
+  take(t.pinfo, (size_t)np * sizeof(ht::PInfo));
+  take(t.dof_frame, (size_t)np * n_dof * 8 * sizeof(float));
+  take(t.seg_org, (size_t)np * n_seg * 4 * sizeof(float));
+  take(t.tiles, (size_t)np * sizeof(int));
+  take(t.item_off, (size_t)(np + 1) * sizeof(int));
+  take(t.item_map, (size_t)ni * sizeof(int));
+  take(t.partial, (size_t)ni * sizeof(ht::Partial));
+  take(t.counters, 4 * sizeof(int));
+  t.wrench = nullptr;
+  t.max_items = (int)ni;
+  if (w) *w = t;
+  return off;
+}
+
 // Run `launch` on stream s, bracketed by HIP events when tracing (and not capturing).
 template <class F>
 hipError_t traced(ht_ctx* c, int kind, int particles, hipStream_t s, F&& launch) {
@@ -250,16 +317,22 @@ namespace ht {
 // With src, particle r of frame f reuses the kinematics that the previous evaluation (of
 // src_stride particles per frame) left for its particle src[r] of frame f: poses must equal
 // those, and the kinematics stage is skipped.
+// With `fixed` (forward only), that workspace is used as it is: nothing is allocated and the
+// launches are not traced.
 ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_particles,
                     const float* poses, float* cost, float* grad, const uint8_t* pixel_mask,
                     const ht_debug* dbg, hipStream_t s, const int32_t* frame_stop = nullptr,
-                    const int32_t* src = nullptr, int src_stride = 0) {
+                    const int32_t* src = nullptr, int src_stride = 0,
+                    const Workspace* fixed = nullptr) {
   const int n_total = n_frames * n_particles;
   if (n_total == 0) return HT_OK;
-  // reused kinematics would not survive a reallocation of the workspace: compute them again
-  if (src && !workspace_fits(c, n_total, c->max_tiles(), grad != nullptr)) src = nullptr;
-  ht_status st = ensure_workspace(c, n_total, c->max_tiles(), grad != nullptr, s);
-  if (st != HT_OK) return st;
+  if (!fixed) {
+    // reused kinematics would not survive a reallocation of the workspace: compute them again
+    if (src && !workspace_fits(c, n_total, c->max_tiles(), grad != nullptr)) src = nullptr;
+    ht_status st = ensure_workspace(c, n_total, c->max_tiles(), grad != nullptr, s);
+    if (st != HT_OK) return st;
+  }
+  const Workspace& ws = fixed ? *fixed : c->ws;
   EvalArgs a{};
   a.model = c->d_model;
   a.slots = c->d_slots;
@@ -300,8 +373,11 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
                                  HT_K_FINALIZE};
   for (int stage = 0; stage < kNumStages; ++stage) {
     if (stage == kStageFk && src) continue;   // reused from the previous evaluation
-    HT_HIP(traced(c, kinds[stage], n_total, s,
-                  [&] { return launch_eval_stage(stage, a, c->ws, s); }));
+    if (fixed)
+      HT_HIP(launch_eval_stage(stage, a, ws, s));
+    else
+      HT_HIP(traced(c, kinds[stage], n_total, s,
+                    [&] { return launch_eval_stage(stage, a, ws, s); }));
   }
   return HT_OK;
 }
@@ -334,6 +410,12 @@ ht_status ht_create(ht_ctx** out, int hip_device) {
   if (e != hipSuccess) {
     ht_destroy(c);
     return fail(HT_ERR_OOM, "context allocation failed: %s", hipGetErrorString(e));
+  }
+  // the no-allocation entry point's scratch on this device (the device is current here)
+  e = scratch_address(hip_device, &c->scratch);
+  if (e != hipSuccess) {
+    ht_destroy(c);
+    return fail(HT_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
   }
   *out = c;
   return HT_OK;
@@ -646,6 +728,34 @@ ht_status ht_eval_particles_grad(ht_ctx* c, int n_frames, const int32_t* frame_s
   DeviceGuard g(c->device);
   return ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, grad, pixel_mask,
                        nullptr, (hipStream_t)stream);
+}
+
+ht_status ht_eval_particles_noalloc(ht_ctx* c, int n_frames, const int32_t* frame_slots,
+                                    int n_particles, const float* poses, float* cost,
+                                    void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c);
+  if (st != HT_OK) return st;
+  if (n_frames < 0 || n_particles < 0) return fail(HT_ERR_ARG, "negative counts");
+  if ((long long)n_frames * n_particles > (1 << 24)) return fail(HT_ERR_ARG, "too many particles");
+  if (n_frames * n_particles == 0) return HT_OK;
+  if (!frame_slots || !poses || !cost) return fail(HT_ERR_ARG, "NULL device pointer");
+  if ((st = check_slots_set(c)) != HT_OK) return st;
+  if (!c->scratch) return fail(HT_ERR_STATE, "no scratch address on device %d", c->device);
+  const int n_total = n_frames * n_particles;
+  const long long ni = item_bound(n_total, c->max_tiles());
+  const size_t need = carve_workspace(nullptr, n_total, ni, c->n_prim, c->n_dof, c->n_seg, nullptr);
+  if (need > kScratchBytes)
+    return fail(HT_ERR_ARG,
+                "%d particles over observations of up to %d tiles need %zu bytes of scratch; "
+                "ht_eval_particles_noalloc has %zu: evaluate fewer particles per call",
+                n_total, c->max_tiles(), need, kScratchBytes);
+  ht::Workspace w{};
+  carve_workspace(static_cast<unsigned char*>(c->scratch), n_total, ni, c->n_prim, c->n_dof,
+                  c->n_seg, &w);
+  DeviceGuard g(c->device);
+  return ht::eval_impl(c, n_frames, frame_slots, n_particles, poses, cost, nullptr, nullptr,
+                       nullptr, (hipStream_t)stream, nullptr, nullptr, 0, &w);
 }
 
 }  // extern "C"
