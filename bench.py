@@ -91,19 +91,6 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def _trace_generations(ctx, sw, params, G, h_true, n_hands):
-    """Eager generations (outside any timing): the joint error and the gbest cost (mean over
-    frames) after each."""
-    ctx.pso_init(sw)
-    errs, costs = [], []
-    for _ in range(G):
-        ctx.pso_step(sw, params)
-        errs.append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
-                                    n_hands))
-        costs.append(float(sw["gbest_cost"].cpu().numpy().mean()))
-    return errs, costs
-
-
 def _first_staying(values, bound):
     """First index from which every later value is <= bound, or None."""
     hit = None
@@ -115,63 +102,131 @@ def _first_staying(values, bound):
     return hit
 
 
+# Refined swarm settings of the plain-versus-refined study: the workload's own, and a small
+# one that reaches the plain swarm's final cost in fewer evaluations (chosen by a sweep over
+# particles P, refined K and steps S on this frame; particles, K, steps).
+STUDY_SMALL_REFINED = (64, 8, 3)
+
+
+def _timed_run(ctx, torch, sw, params, gens, reps=3):
+    """Mean device ms of `reps` graph replays of a whole run and the evaluations performed
+    per run (device-counted); the first replay (capture) is not timed."""
+    ctx.pso_run_graph(sw, params, gens)
+    torch.cuda.synchronize()
+    ctx.eval_counts(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.pso_run_graph(sw, params, gens)
+    e1.record()
+    torch.cuda.synchronize()
+    f, g = ctx.eval_counts(reset=True)
+    return e0.elapsed_time(e1) / reps, (f + g) / reps
+
+
+def _trace_errors(ctx, sw, params, G, h_true, n_hands):
+    """Eager generations: per generation the joint error of the global best and the
+    evaluations performed so far (device-counted)."""
+    ctx.pso_init(sw)
+    ctx.eval_counts(reset=True)
+    errs, evals = [], []
+    for _ in range(G):
+        ctx.pso_step(sw, params)
+        errs.append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
+                                    n_hands))
+        f, g = ctx.eval_counts()
+        evals.append(f + g)
+    ctx.eval_counts(reset=True)
+    return errs, evals
+
+
 def plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16,
                      target_deg=5.0):
-    """Plain swarm (the paper's 64 particles x 30 generations) against the workload's
-    gradient-refined swarm on the same frame(s), over seeds: final joint error and gbest cost
-    (beside the cost of the true pose), ms per frame (graph replay), the evaluations after
-    which the joint error stays at or below ``target_deg``, and those the refined swarm needs
-    to reach the plain swarm's final cost."""
+    """Plain swarm (the paper's 64 particles x 30 generations) against gradient-refined
+    swarms on the same frame, seed by seed: the refined run stops (the stop rule of section
+    III.B, inside its graph) once its global-best cost is below the plain run's final cost.
+    Reported per setting: seeds that reach it, the evaluations performed until then
+    (device-counted), the device ms of a run of exactly that many generations (graph replay)
+    and of the 30-generation graph with the stop rule (its stopped generations still launch
+    their kernels), and the joint error there; the plain run's final error, cost, ms and
+    evaluations beside them.  Also the evaluations after which the joint error stays at or
+    below ``target_deg`` (eager trace)."""
     F = slots.numel()
+    settings = {"workload": (cfg.n_particles, cfg.refine_topk, cfg.refine_steps, cfg.n_generations),
+                "small": STUDY_SMALL_REFINED + (30,)}
     plain_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2)
-    ref_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, refine_topk=cfg.refine_topk,
-                          refine_steps=cfg.refine_steps)
-    P, G = cfg.n_particles, cfg.n_generations
-    per_gen = {"plain": 64,
-               "refined": P + cfg.refine_topk * (1 + 4 * cfg.refine_steps)}
     true_cost = float(ctx.eval(torch.tensor(h_true[:, None, :], dtype=torch.float32,
                                             device=slots.device), slots).cpu().numpy().mean())
-    out = {k: {"err": [], "cost": [], "ms": [], "to_target": []} for k in ("plain", "refined")}
-    out["refined"]["evals_to_plain_cost"] = []
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plain = {"err": [], "cost": [], "ms": [], "evals": [], "to_target": []}
+    ref = {k: {"reached": [], "evals": [], "ms_exact": [], "ms_stop_rule": [], "err": [],
+               "cost": [], "final_err_no_stop": [], "to_target": []} for k in settings}
     for s in range(seeds):
-        traces = {}
-        for kind, n, gens, params in (("plain", 64, 30, plain_p), ("refined", P, G, ref_p)):
-            sw = ctx.swarm(slots, n, lo, hi, seed=1000 + s)
-            ctx.pso_run_graph(sw, params, gens)
-            torch.cuda.synchronize()
-            e0.record()
-            ctx.pso_run_graph(sw, params, gens)
-            e1.record()
-            torch.cuda.synchronize()
-            out[kind]["ms"].append(e0.elapsed_time(e1) / F)
-            errs, costs = _trace_generations(ctx, sw, params, gens, h_true, cfg.n_hands)
-            traces[kind] = costs
-            out[kind]["err"].append(errs[-1])
-            out[kind]["cost"].append(costs[-1])
+        sw = ctx.swarm(slots, 64, lo, hi, seed=1000 + s)
+        ms, ev = _timed_run(ctx, torch, sw, plain_p, 30)
+        c_plain = float(sw["gbest_cost"].cpu().numpy().mean())
+        plain["cost"].append(c_plain)
+        plain["ms"].append(ms / F)
+        plain["evals"].append(ev / F)
+        plain["err"].append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64),
+                                            h_true, cfg.n_hands))
+        errs, evals = _trace_errors(ctx, sw, plain_p, 30, h_true, cfg.n_hands)
+        hit = _first_staying(errs, target_deg)
+        plain["to_target"].append(None if hit is None else evals[hit] / F)
+        for k, (P, K, S, G) in settings.items():
+            r = ref[k]
+            sw = ctx.swarm(slots, P, lo, hi, seed=1000 + s)
+            stop_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, refine_topk=K, refine_steps=S,
+                                   stop_cost=c_plain)
+            ms_stop, ev = _timed_run(ctx, torch, sw, stop_p, 30)
+            g = int(sw["stop_gen"].cpu().numpy().max())
+            r["ms_stop_rule"].append(ms_stop / F)
+            if g > 0:
+                r["reached"].append(1)
+                r["evals"].append(ev / F)
+                r["cost"].append(float(sw["gbest_cost"].cpu().numpy().mean()))
+                r["err"].append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64),
+                                                h_true, cfg.n_hands))
+                exact_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, refine_topk=K,
+                                        refine_steps=S)
+                ms_exact, _ = _timed_run(ctx, torch, sw, exact_p, g)
+                r["ms_exact"].append(ms_exact / F)
+            run_p = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, refine_topk=K, refine_steps=S)
+            errs, evals = _trace_errors(ctx, sw, run_p, G, h_true, cfg.n_hands)
+            r["final_err_no_stop"].append(errs[-1])
             hit = _first_staying(errs, target_deg)
-            out[kind]["to_target"].append(None if hit is None else (hit + 1) * per_gen[kind])
-        hit = next((g for g, c in enumerate(traces["refined"]) if c <= traces["plain"][-1]),
-                   None)
-        out["refined"]["evals_to_plain_cost"].append(None if hit is None
-                                                     else (hit + 1) * per_gen["refined"])
+            r["to_target"].append(None if hit is None else evals[hit] / F)
+
+    def mean(v):
+        return float(np.mean(v)) if len(v) else None
+
+    def reached(v):
+        return [x for x in v if x is not None]
+
     summary = {"seeds": seeds, "target_joint_error_deg": target_deg,
-               "cost_at_true_pose": true_cost, "evals_counted": "per frame"}
-    for k, v in out.items():
-        reached = [r for r in v["to_target"] if r is not None]
-        summary[k] = {"particles": 64 if k == "plain" else P,
-                      "generations": 30 if k == "plain" else G,
-                      "evals": per_gen[k] * (30 if k == "plain" else G),
-                      "mean_joint_error_deg": float(np.mean(v["err"])),
-                      "median_joint_error_deg": float(np.median(v["err"])),
-                      "mean_final_cost": float(np.mean(v["cost"])),
-                      "ms_per_frame": float(np.mean(v["ms"])),
-                      "seeds_staying_within_target": len(reached),
-                      "mean_evals_to_stay_within_target":
-                          float(np.mean(reached)) if reached else None}
-    reached = [r for r in out["refined"]["evals_to_plain_cost"] if r is not None]
-    summary["refined"]["seeds_reaching_plain_cost"] = len(reached)
-    summary["refined"]["mean_evals_to_plain_cost"] = float(np.mean(reached)) if reached else None
+               "cost_at_true_pose": true_cost, "evals_counted": "per frame, device-counted",
+               "plain": {"particles": 64, "generations": 30,
+                         "mean_evals": mean(plain["evals"]),
+                         "mean_joint_error_deg": mean(plain["err"]),
+                         "median_joint_error_deg": float(np.median(plain["err"])),
+                         "mean_final_cost": mean(plain["cost"]),
+                         "ms_per_frame": mean(plain["ms"]),
+                         "seeds_staying_within_target": len(reached(plain["to_target"])),
+                         "mean_evals_to_stay_within_target": mean(reached(plain["to_target"]))}}
+    for k, (P, K, S, G) in settings.items():
+        r = ref[k]
+        summary["refined_" + k] = {
+            "particles": P, "refine_topk": K, "refine_steps": S,
+            "stop_cost": "the plain run's final cost (same seed)",
+            "seeds_reaching_plain_cost": len(r["reached"]),
+            "mean_evals_to_plain_cost": mean(r["evals"]),
+            "ms_per_frame_to_plain_cost": mean(r["ms_exact"]),
+            "ms_per_frame_30_generation_graph_with_stop_rule": mean(r["ms_stop_rule"]),
+            "mean_joint_error_at_plain_cost_deg": mean(r["err"]),
+            "mean_cost_at_stop": mean(r["cost"]),
+            "generations_without_stop": G,
+            "mean_final_joint_error_without_stop_deg": mean(r["final_err_no_stop"]),
+            "seeds_staying_within_target": len(reached(r["to_target"])),
+            "mean_evals_to_stay_within_target": mean(reached(r["to_target"]))}
     return summary
 
 
@@ -265,9 +320,7 @@ def pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16, P=
         params = ht.pso_params(**kw)
         for s in range(seeds):
             sw = ctx.swarm(slots, P, lo, hi, seed=5000 + s)
-            ctx.pso_init(sw)
-            for _ in range(G):
-                ctx.pso_step(sw, params)
+            ctx.pso_run_graph(sw, params, G)
             errs.append(joint_error_deg(sw["gbest_x"].cpu().numpy().astype(np.float64), h_true,
                                         cfg.n_hands))
             costs.append(float(sw["gbest_cost"].cpu().numpy().mean()))
@@ -563,7 +616,8 @@ def main():
     ap.add_argument("--no-study", action="store_true",
                     help="skip the plain-versus-refined swarm comparison")
     ap.add_argument("--ablation", action="store_true",
-                    help="add the swarm-constants / mutation ablation (plain swarm)")
+                    help="the swarm-constants / mutation ablation (plain swarm) also with "
+                         "--no-study")
     ap.add_argument("--sweep", action="store_true",
                     help="forward-only roofline sweep over particle counts (own JSON line)")
     ap.add_argument("--track", action="store_true",
@@ -659,12 +713,15 @@ def main():
         tuned = {"tiles_per_item": tpi, "groups_per_cu": gpc, "cull": cull,
                  "source": "autotuner"}
 
-    # per generation: the swarm, the refined particles' gradient, 4 candidates per step
-    evals_per_step = F * P * G + F * G * (K + 4 * K * S) if K else F * P * G
+    # scheduled per generation: the swarm, the refined particles' gradient, 4 candidates per
+    # step; the candidates of a particle that has stopped refining are not evaluated, so the
+    # evaluations performed are counted on the device over the timed steps
+    evals_scheduled = F * P * G + F * G * (K + 4 * K * S) if K else F * P * G
     log(f"launch shape {tuned}; capturing and warming up")
     for _ in range(args.warmup):
         ctx.pso_run_graph(sw, params, G)
     torch.cuda.synchronize()
+    ctx.eval_counts(reset=True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
     e0.record()
@@ -673,9 +730,11 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
+    n_fwd, n_grad = ctx.eval_counts(reset=True)
     ms = e0.elapsed_time(e1)
     ms_per_step = ms / args.steps
-    value = evals_per_step * args.steps / (ms / 1e3)
+    evals_per_step = (n_fwd + n_grad) / args.steps
+    value = (n_fwd + n_grad) / (ms / 1e3)
     gbest = sw["gbest_x"].cpu().numpy().astype(np.float64)
     err = joint_error_deg(gbest, h_true, cfg.n_hands)
 
@@ -704,6 +763,9 @@ def main():
                                + (f", {S} gradient steps on the best {K}" if K else ""),
                    "frames": F, "particles": P, "generations": G, "refine_topk": K,
                    "refine_steps": S, "evals_per_step": evals_per_step,
+                   "evals_per_step_forward": n_fwd / args.steps,
+                   "evals_per_step_gradient": n_grad / args.steps,
+                   "evals_per_step_scheduled": evals_scheduled,
                    "launch": tuned, "parallelism": "1 GPU"},
         "ms_per_frame": ms_per_step / F,
         "wall_s": wall,
@@ -722,7 +784,7 @@ def main():
         log("plain versus gradient-refined swarm over seeds")
         line["plain_vs_refined"] = plain_vs_refined(ctx, ht, torch, cfg, model, slots, lo, hi,
                                                     h_true)
-    if args.ablation:
+    if args.ablation or not args.no_study:
         log("swarm constants and mutation ablation over seeds")
         line["pso_ablation"] = pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true)
     if baseline is not None:

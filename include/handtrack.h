@@ -320,6 +320,13 @@ typedef struct {
 ht_status ht_profile_begin(ht_ctx* ctx);
 ht_status ht_profile_end(ht_ctx* ctx, ht_kernel_stat* stats);
 
+/* Particle evaluations the context has performed since it was created or last reset: forward
+ * (cost only) and with gradients, counted on the device by every evaluation call, in graph
+ * replays too.  Particles that are not evaluated -- of a frame stopped by the stop rule, or the
+ * candidates of a refined particle that has stopped refining -- are not counted.  Synchronises
+ * the device; reset != 0 sets both counts to zero afterwards.  Errors: HT_ERR_ARG for NULL. */
+ht_status ht_eval_counts(ht_ctx* ctx, int64_t* forward, int64_t* gradient, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -114,11 +114,12 @@ def load_library(path: str = LIB_PATH):
     lib.ht_autotune.argtypes = [P, I, P, I, P, P, I, C.POINTER(LaunchConfig), P]
     lib.ht_profile_begin.argtypes = [P]
     lib.ht_profile_end.argtypes = [P, C.POINTER(KernelStat)]
+    lib.ht_eval_counts.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), I]
     for name in ("ht_profile_begin", "ht_profile_end", "ht_create", "ht_set_model", "ht_set_observation", "ht_reserve",
                  "ht_eval_particles", "ht_eval_particles_grad", "ht_eval_particles_noalloc",
                  "ht_pso_init", "ht_pso_step",
                  "ht_pso_run_graph", "ht_get_launch_config", "ht_set_launch_config",
-                 "ht_autotune"):
+                 "ht_autotune", "ht_eval_counts"):
         getattr(lib, name).restype = S
     _lib = lib
     return lib
@@ -398,6 +399,12 @@ class Context:
         _check(self.lib.ht_profile_end(self.handle, stats))
         return {k: {"launches": s.launches, "particles": s.particles, "ms": s.total_ms}
                 for k, s in zip(KERNEL_KINDS, stats)}
+
+    def eval_counts(self, reset: bool = False) -> tuple[int, int]:
+        """(forward, gradient) particle evaluations performed so far (synchronises)."""
+        f, g = C.c_int64(), C.c_int64()
+        _check(self.lib.ht_eval_counts(self.handle, C.byref(f), C.byref(g), int(reset)))
+        return f.value, g.value
 
     # -- launch shape -------------------------------------------------------------------
     def launch_config(self):

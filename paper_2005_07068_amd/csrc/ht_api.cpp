@@ -141,6 +141,7 @@ struct ht_ctx {
   int cap_seg = 0;
   std::map<GraphKey, hipGraphExec_t> graphs;
   void* scratch = nullptr;    // this device's address of the no-allocation scratch array
+  unsigned long long* d_eval_count = nullptr;   // [2] forward / gradient evaluations
   // tracing of eager launches
   struct ProfRec {
     int kind;
@@ -323,7 +324,8 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
                     const float* poses, float* cost, float* grad, const uint8_t* pixel_mask,
                     const ht_debug* dbg, hipStream_t s, const int32_t* frame_stop = nullptr,
                     const int32_t* src = nullptr, int src_stride = 0,
-                    const Workspace* fixed = nullptr) {
+                    const Workspace* fixed = nullptr, const int32_t* active = nullptr,
+                    int active_div = 1) {
   const int n_total = n_frames * n_particles;
   if (n_total == 0) return HT_OK;
   if (!fixed) {
@@ -346,6 +348,9 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.frame_stop = frame_stop;
   a.src = src;
   a.src_stride = src_stride;
+  a.active = active;
+  a.active_div = active_div;
+  a.eval_count = c->d_eval_count;
   if (dbg) {
     a.dbg = *dbg;
     const SlotHost& sh = c->slots[dbg->slot];
@@ -407,6 +412,8 @@ ht_status ht_create(ht_ctx** out, int hip_device) {
   hipError_t e = hipMalloc(&c->d_slots, HT_MAX_SLOTS * sizeof(ht::FrameSlot));
   if (e == hipSuccess) e = hipMemset(c->d_slots, 0, HT_MAX_SLOTS * sizeof(ht::FrameSlot));
   if (e == hipSuccess) e = hipMalloc(&c->d_model, sizeof(ht::DevModel));
+  if (e == hipSuccess) e = hipMalloc(&c->d_eval_count, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->d_eval_count, 0, 2 * sizeof(unsigned long long));
   if (e != hipSuccess) {
     ht_destroy(c);
     return fail(HT_ERR_OOM, "context allocation failed: %s", hipGetErrorString(e));
@@ -448,6 +455,7 @@ void ht_destroy(ht_ctx* c) {
   dfree(c->seg_partial);
   dfree(c->d_slots);
   dfree(c->d_model);
+  dfree(c->d_eval_count);
   delete c;
 }
 
@@ -854,8 +862,9 @@ ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, h
       }));
       if (!propose) break;
       float* cgrad_out = step + 1 < p.refine_steps ? c->r_cgrad : nullptr;
+      // the four candidates of a particle that has stopped refining are not evaluated
       st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, cgrad_out, nullptr,
-                         nullptr, s, sw.stop_gen);
+                         nullptr, s, sw.stop_gen, nullptr, 0, nullptr, c->r_active, 4);
       if (st != HT_OK) return st;
     }
   }
@@ -1093,6 +1102,19 @@ ht_status ht_profile_end(ht_ctx* c, ht_kernel_stat* stats) {
   c->prof_recs.clear();
   c->prof = false;
   return st;
+}
+
+ht_status ht_eval_counts(ht_ctx* c, int64_t* forward, int64_t* gradient, int reset) {
+  g_err.clear();
+  if (!c || !forward || !gradient) return fail(HT_ERR_ARG, "NULL argument");
+  DeviceGuard g(c->device);
+  unsigned long long v[2] = {0, 0};
+  HT_HIP(hipDeviceSynchronize());
+  HT_HIP(hipMemcpy(v, c->d_eval_count, sizeof v, hipMemcpyDeviceToHost));
+  if (reset) HT_HIP(hipMemset(c->d_eval_count, 0, sizeof v));
+  *forward = (int64_t)v[0];
+  *gradient = (int64_t)v[1];
+  return HT_OK;
 }
 
 ht_status ht_get_launch_config(ht_ctx* c, ht_launch_config* out) {

@@ -86,7 +86,8 @@ struct PInfo {
   int slot;                   // observation slot (-1: unset slot)
   float kc;                   // collision term of Eq. 5
   int valid;                  // 0: non-finite pose or unset slot
-  int skip;                   // 1: the particle's frame has stopped: nothing is written
+  int skip;                   // 1: not evaluated (its frame has stopped, or it is a candidate
+                              // of a refined particle that has stopped): nothing is written
   int kc_mask;                // collision pairs with a positive term (bit i: pair i)
   double bg_td, bg_or;        // the observation's ROI-wide background sums (copied from its
                               // slot, so the finalize kernels need no slot lookup)
@@ -110,7 +111,8 @@ struct Workspace {
   PInfo* pinfo;          // [n_total]
   float* dof_frame;      // [n_total][n_dof][8]: kind, axis xyz, point xyz (camera frame)
   float* seg_org;        // [n_total][n_seg][4]
-  int* tiles;            // [n_total] tiles of each particle (a compact copy for the scheduler)
+  int* tiles;            // [n_total] tiles of each particle (a compact copy for the
+                         // scheduler), -1 for a particle that is not evaluated (skipped)
   int* item_off;         // [n_total + 1]
   int* item_map;         // [max_items]
   Partial* partial;      // [max_items]
@@ -130,6 +132,13 @@ struct EvalArgs {
   float* grad;                 // NULL for forward only
   const uint8_t* pixel_mask;   // gradient mask of frame 0, may be NULL
   const int* frame_stop;       // [n_frames] stop flags of a swarm, may be NULL
+  // NULL, or per group of active_div consecutive particles a flag: 0 = the group is not
+  // evaluated (the candidates of a refined particle that has stopped refining)
+  const int* active;
+  int active_div;
+  // evaluations performed (not skipped), [0] forward and [1] gradient, added up by the
+  // work-list kernel of every call; may be NULL
+  unsigned long long* eval_count;
   // NULL, or per evaluated particle r its source s = src[r]: the particle reuses the kinematics
   // of workspace particle (r / n_particles) * src_stride + s from the previous evaluation
   // (same poses; the kinematics stage is skipped)

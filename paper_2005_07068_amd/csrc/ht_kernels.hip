@@ -267,8 +267,9 @@ __device__ __forceinline__ void load_tiles(const EvalArgs& a, const Workspace& w
   }
 #pragma unroll
   for (int j = 0; j < kSchedBatch; ++j) v[j] = ws.tiles[r[j]];
+  // past the chunk: not counted and no tiles (-1, as a skipped particle)
 #pragma unroll
-  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? v[j] : 0;
+  for (int j = 0; j < kSchedBatch; ++j) v[j] = i0 + j < e ? v[j] : -1;
 }
 
 // The tile counts of batch i0 of a thread whose particles start at b: the first batch (every
@@ -294,15 +295,21 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
   const int b = min(t * chunk, n_total), e = min(b + chunk, n_total);
   int v0[kSchedBatch];
   load_tiles(a, ws, b, e, v0);
-  int tiles = 0;
+  // tiles to visit, and particles evaluated (not skipped), of this thread's chunk; a skipped
+  // particle has tile count -1 and no work items
+  int tiles = 0, evaluated = 0;
   for (int i0 = b; i0 < e; i0 += kSchedBatch) {
     int v[kSchedBatch];
     batch_tiles(a, ws, i0, b, e, v0, v);
 #pragma unroll
-    for (int j = 0; j < kSchedBatch; ++j) tiles += v[j];
+    for (int j = 0; j < kSchedBatch; ++j) {
+      tiles += max(v[j], 0);
+      evaluated += v[j] >= 0 ? 1 : 0;
+    }
   }
-  int total_tiles;
+  int total_tiles, total_evaluated;
   block_scan<kNW>(s_sum, tiles, &total_tiles);
+  block_scan<kNW>(s_sum, evaluated, &total_evaluated);
   const long long target = (long long)a.grid * kItemsPerGroup;
   long long tq = ((long long)total_tiles + target - 1) / target;
   tq = (tq + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
@@ -315,7 +322,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
     int v[kSchedBatch];
     batch_tiles(a, ws, i0, b, e, v0, v);
 #pragma unroll
-    for (int j = 0; j < kSchedBatch; ++j) local += (v[j] + tpi - 1) / tpi;
+    for (int j = 0; j < kSchedBatch; ++j) local += (max(v[j], 0) + tpi - 1) / tpi;
   }
   int total_items;
   const int incl = block_scan<kNW>(s_sum, local, &total_items);
@@ -332,7 +339,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
       if (i0 + j >= e) break;
       if (staged) s_map[i0 + j] = off;
       else ws.item_off[i0 + j] = off;
-      off += (v[j] + tpi - 1) / tpi;
+      off += (max(v[j], 0) + tpi - 1) / tpi;
     }
   }
   if (staged) {
@@ -353,7 +360,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
 #pragma unroll
         for (int j = 0; j < kSchedBatch; ++j) {
           if (i0 + j >= e) break;
-          const int n = (v[j] + tpi - 1) / tpi;
+          const int n = (max(v[j], 0) + tpi - 1) / tpi;
           const int q0 = max(o, w0), q1 = min(o + n, w1);
           for (int q = q0; q < q1; ++q) s_map[q - w0] = i0 + j;
           o += n;
@@ -365,6 +372,7 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
     __syncthreads();
   }
   if (t == 0) {
+    if (a.eval_count) atomicAdd(&a.eval_count[a.grad ? 1 : 0], (unsigned long long)total_evaluated);
     ws.item_off[n_total] = total_items;
     ws.counters[0] = 0;
     ws.counters[1] = total_items;
@@ -504,7 +512,10 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   if (active) slot = a.frame_slots[p / a.n_particles];
   const bool slot_ok = active && slot >= 0 && slot < HT_MAX_SLOTS && a.slots[slot].set;
   // a particle of a stopped frame (tracking stop rule) is neither cast nor written
-  const bool skip = active && a.frame_stop && a.frame_stop[p / a.n_particles] != 0;
+  // a particle of a stopped frame (tracking stop rule), or a candidate of a refined particle
+  // that has stopped refining, is neither cast nor written
+  const bool skip = active && ((a.frame_stop && a.frame_stop[p / a.n_particles] != 0) ||
+                               (a.active && a.active[p / a.active_div] == 0));
   const bool valid = slot_ok && finite && !skip;
   // the slot's background sums, needed only by the record written at the end
   double bg_td = 0.0, bg_or = 0.0;
@@ -910,7 +921,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
     pi.n_tiles = nt;
     if (lane == 0) {
       ws.pinfo[p] = pi;
-      ws.tiles[p] = nt;
+      ws.tiles[p] = skip ? -1 : nt;
     }
   }
 }

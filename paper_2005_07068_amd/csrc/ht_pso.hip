@@ -486,7 +486,9 @@ __global__ __launch_bounds__(kPsoBlock) void refine_select_small_kernel(
 //             accepted one's becomes the particle's gradient; no step lowers E: the particle
 //             stops refining;
 //   propose - four candidates x - eta * (g_s / max|g_s|) / 2^j, j = 0..3, g_s = eta * dE/dh,
-//             clamped to the bounds (a stopped particle proposes its own position four times);
+//             clamped to the bounds; a particle that has stopped (or whose g_s is zero or not
+//             finite, which stops it) writes its own position four times, and its candidates
+//             are skipped by the evaluation (its active flag is 0);
 //   gather  - write the refined positions and costs back into the swarm.
 struct RefineOp {
   int accept, propose, gather;
@@ -556,6 +558,8 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(
     for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o));
     fin = __ballot(!fin) == 0ull;
     const bool ok = act && fin && gmax > 0.0f;
+    // a particle without a usable step stops refining: its candidates are not evaluated
+    if (act && !ok && lane == 0) active[r] = 0;
     if (on) {
       for (int j = 0; j < 4; ++j) {
         float xn = x;

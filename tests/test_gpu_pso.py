@@ -383,3 +383,47 @@ def test_refinement_matches_the_oracle_step_by_step():
     x_chain = sw["x"].cpu().numpy()[0].astype(np.float64)
     ctx.close()
     assert np.all(np.abs(x_chain - x_steps) <= 1e-3 * eta)
+
+
+def test_eval_counts_and_skipped_refinement_candidates():
+    """The device evaluation counts: every evaluated particle once (forward or with
+    gradients), in eager calls and graph replays; the candidates of refined particles that
+    have stopped refining are not evaluated.  Particles placed out of view render nothing and
+    have no collision term, so their gradient is zero and their refinement stops at once: a
+    generation then evaluates the swarm (forward) and the K selected (with gradients) only."""
+    torch, ctx, model, fr, sw, lo, hi = _setup(P=64)
+    ctx.eval_counts(reset=True)
+    ctx.pso_init(sw)
+    x = sw["x"].clone()
+    ctx.eval(x[0], sw["frame_slots"])
+    ctx.eval_grad(x[0, :10], sw["frame_slots"])
+    assert ctx.eval_counts(reset=True) == (64, 10)
+    # refinement: K = 8, 2 steps; in view, every candidate of an active particle is evaluated
+    p = ht.pso_params(mutate_every=0, refine_topk=8, refine_steps=2)
+    ctx.pso_step(sw, p)
+    f, g = ctx.eval_counts(reset=True)
+    assert g >= 8 and f >= 64 and f + g <= 64 + 8 + 4 * 8 * 2
+    # out of view (x far to the side, angles with kc = 0): gradients vanish, nothing proposed
+    far = sw["x"].clone()
+    far[0, :, 20] += 5000.0
+    sw["x"].copy_(far)
+    c_far = ctx.eval(far[0], sw["frame_slots"]).cpu().numpy()
+    _, g_far = ctx.eval_grad(far[0], sw["frame_slots"])
+    ctx.eval_counts(reset=True)
+    kc_free = np.all(g_far.cpu().numpy() == 0.0, axis=1)
+    assert kc_free.sum() >= 8
+    ctx.pso_step(sw, p)
+    torch.cuda.synchronize()
+    # the 8 selected (lowest costs: nothing rendered, so E = D + lambda_k kc is lowest where
+    # kc = 0) have zero gradients, stop at once and propose nothing
+    assert ctx.eval_counts(reset=True) == (64, 8)
+    assert np.array_equal(sw["cost"].cpu().numpy()[0], c_far)
+    # graph replays count every replay
+    ctx.reserve(64 * 4, fr["depth"].size)
+    plain = ht.pso_params(mutate_every=0)
+    ctx.pso_run_graph(sw, plain, 3)
+    ctx.eval_counts(reset=True)
+    for _ in range(2):
+        ctx.pso_run_graph(sw, plain, 3)
+    assert ctx.eval_counts(reset=True) == (2 * 3 * 64, 0)
+    ctx.close()
