@@ -333,11 +333,14 @@ def pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true, seeds=16, P=
     return out
 
 
-def track_sequence(ht, torch, idx=6, stop_factor=None):
+def track_sequence(ht, torch, idx=6, stop_factor=None, box=None, refine=(0, 0)):
     """Tracking over the stored sequence: frame t's swarm starts in the box around frame t-1's
     global best (frame 0: around its true pose), all frames enqueued back to back (one graph
-    replay per frame, no host synchronisation in between).  With ``stop_factor`` the stop rule
-    is on with stop_cost = stop_factor x the median cost of the true poses."""
+    replay per frame, no host synchronisation in between); the swarm's Philox key is a device
+    value rewritten per frame, so every frame draws new random numbers from the same graph.
+    ``box``: (deg, mm) half-widths (default: the workload's); ``refine``: (K, steps).  With
+    ``stop_factor`` the stop rule is on with stop_cost = stop_factor x the median cost of the
+    true poses.  Reports the per-frame joint error."""
     from workload.handmodel import init_halfwidth
     cfg, model, frames, _ = load_workload(idx)
     dev = torch.device("cuda:0")
@@ -346,7 +349,8 @@ def track_sequence(ht, torch, idx=6, stop_factor=None):
     for t, fr in enumerate(frames):
         ctx.set_observation(t, fr["depth"], fr["skin"], fr["cam"], fr["bg"])
     T, P, G, D = cfg.n_frames, cfg.n_particles, cfg.n_generations, model["n_dof"]
-    ctx.reserve(P, max(fr["depth"].size for fr in frames))
+    K, S = refine
+    ctx.reserve(max(P, 4 * K), max(fr["depth"].size for fr in frames))
     h_true = np.stack([fr["h_true"] for fr in frames])
     stop_cost = 0.0
     if stop_factor:
@@ -355,12 +359,13 @@ def track_sequence(ht, torch, idx=6, stop_factor=None):
                                           torch.tensor([t], dtype=torch.int32, device=dev))
                                  .cpu().numpy() for t in range(T)])
         stop_cost = float(stop_factor * np.median(e_true))
-    hw = torch.tensor(init_halfwidth(D, cfg.init_angle_deg, cfg.init_trans_mm),
-                      dtype=torch.float32, device=dev)
+    ang, mm = box if box else (cfg.init_angle_deg, cfg.init_trans_mm)
+    hw = torch.tensor(init_halfwidth(D, ang, mm), dtype=torch.float32, device=dev)
     slots = torch.zeros(1, dtype=torch.int32, device=dev)
     lo = torch.tensor(h_true[:1] - hw.cpu().numpy(), dtype=torch.float32)
-    sw = ctx.swarm(slots, P, lo, lo.clone(), seed=606)
-    params = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, stop_cost=stop_cost)
+    sw = ctx.swarm(slots, P, lo, lo.clone(), seed=606, device_seed=True)
+    params = ht.pso_params(w=cfg.w, c1=cfg.c1, c2=cfg.c2, stop_cost=stop_cost, refine_topk=K,
+                           refine_steps=S)
     start = torch.tensor(h_true[:1], dtype=torch.float32, device=dev)
     out = torch.zeros((T, D), dtype=torch.float32, device=dev)
     gens = torch.zeros(T, dtype=torch.int32, device=dev)
@@ -369,6 +374,7 @@ def track_sequence(ht, torch, idx=6, stop_factor=None):
         center = start
         for t in range(T):
             sw["frame_slots"].fill_(t)
+            sw["seed_dev"].fill_(606 + 7919 * t)
             ctx.box_around(center, hw, sw["init_lo"], sw["init_hi"])
             ctx.pso_run_graph(sw, params, G)
             out[t].copy_(sw["gbest_x"][0])
@@ -378,18 +384,22 @@ def track_sequence(ht, torch, idx=6, stop_factor=None):
     run_sequence()                      # capture + warm-up
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.eval_counts(reset=True)
     e0.record()
     run_sequence()
     e1.record()
     torch.cuda.synchronize()
+    n_f, n_g = ctx.eval_counts(reset=True)
     est = out.cpu().numpy().astype(np.float64)
     err = [joint_error_deg(est[t], h_true[t], 1) for t in range(T)]
     ctx.close()
-    return {"frames": T, "particles": P, "max_generations": G, "stop_cost": stop_cost,
-            "ms_per_frame": e0.elapsed_time(e1) / T,
+    return {"frames": T, "particles": P, "max_generations": G, "box_deg_mm": [ang, mm],
+            "refine_topk": K, "refine_steps": S, "stop_cost": stop_cost,
+            "ms_per_frame": e0.elapsed_time(e1) / T, "evals_per_frame": (n_f + n_g) / T,
             "mean_generations": float(gens.float().mean().item()),
             "mean_joint_error_deg": float(np.mean(err)), "max_joint_error_deg": float(np.max(err)),
-            "last_frame_error_deg": float(err[-1])}
+            "mean_joint_error_last_10_frames_deg": float(np.mean(err[-10:])),
+            "joint_error_per_frame_deg": [round(e, 2) for e in err]}
 
 
 def roofline_sweep(ht, torch, totals=(256, 4096, 65536), min_ms=10.0):
@@ -655,12 +665,14 @@ def main():
         elif args.sweep:
             print(json.dumps({"roofline_sweep": roofline_sweep(ht, torch)}), flush=True)
         else:
-            log("tracking the 30-frame sequence, stop rule off")
+            log("tracking the 30-frame sequence: the workload's box, stop rule off")
             plain = track_sequence(ht, torch)
-            log("tracking the 30-frame sequence, stop rule on")
+            log("tracking: the workload's box, stop rule on")
             stop = track_sequence(ht, torch, stop_factor=1.02)
-            print(json.dumps({"tracking": {"fixed_generations": plain, "stop_rule": stop}}),
-                  flush=True)
+            log("tracking: a 3 deg / 6 mm box with 3 gradient steps on the best 8")
+            narrow = track_sequence(ht, torch, box=(3.0, 6.0), refine=(8, 3))
+            print(json.dumps({"tracking": {"fixed_generations": plain, "stop_rule": stop,
+                                           "narrow_box_refined": narrow}}), flush=True)
         return
 
     from workload.handmodel import init_halfwidth

@@ -213,7 +213,8 @@ ht_status ht_eval_particles_noalloc(ht_ctx* ctx, int n_frames, const int32_t* fr
 /* Swarm state, all device memory owned by the caller, float32 unless noted:
  *   x, v, pbest_x [F][P][n_dof]; pbest_cost, cost [F][P]; gbest_x [F][n_dof];
  *   gbest_cost [F]; gen: int32 [F] generation counters; frame_slots: int32 [F];
- *   init_lo, init_hi [F][n_dof]: box of the initial positions (ht_pso_init);
+ *   init_lo, init_hi [F][n_dof]: box of the initial positions (ht_pso_init); seed: the 64-bit
+ *   Philox key (or, with seed_dev, read from device memory);
  *   stop_gen: int32 [F] or NULL, needed for the stop rule (ht_pso_params.stop_cost): 0 while
  *   a frame runs, else the generation count at which its best cost fell below stop_cost;
  *   from then on nothing of that frame's swarm changes (its particles are not evaluated). */
@@ -225,6 +226,10 @@ typedef struct {
   const float *init_lo, *init_hi;
   uint64_t seed;
   int32_t* stop_gen;
+  /* NULL, or a device uint64: the Philox key is read from it by every swarm kernel instead of
+   * `seed`, so a captured run (ht_pso_run_graph, cached per swarm struct) replays with new
+   * random numbers once the caller writes a new value there (e.g. one per tracked frame). */
+  const uint64_t* seed_dev;
 } ht_swarm;
 
 /* Swarm constants.  Plain PSO of the paper: c1 = 2.8, c2 = 1.3, w = 2/|2 - psi -

@@ -52,7 +52,7 @@ class Swarm(C.Structure):
         ("x", C.c_void_p), ("v", C.c_void_p), ("pbest_x", C.c_void_p), ("pbest_cost", C.c_void_p),
         ("gbest_x", C.c_void_p), ("gbest_cost", C.c_void_p), ("cost", C.c_void_p),
         ("gen", C.c_void_p), ("init_lo", C.c_void_p), ("init_hi", C.c_void_p),
-        ("seed", C.c_uint64), ("stop_gen", C.c_void_p),
+        ("seed", C.c_uint64), ("stop_gen", C.c_void_p), ("seed_dev", C.c_void_p),
     ]
 
 
@@ -320,8 +320,11 @@ class Context:
         return cost, grad
 
     # -- swarm --------------------------------------------------------------------------
-    def swarm(self, frame_slots, n_particles: int, init_lo, init_hi, seed: int):
-        """Allocate swarm state tensors; returns a dict (tensors) and its ctypes struct."""
+    def swarm(self, frame_slots, n_particles: int, init_lo, init_hi, seed: int,
+              device_seed: bool = False):
+        """Allocate swarm state tensors; returns a dict (tensors) and its ctypes struct.
+        With device_seed the Philox key is the int64 tensor t["seed_dev"] (initialised to seed),
+        which the caller may rewrite between graph replays."""
         import torch
         dev = frame_slots.device
         F, D = int(frame_slots.numel()), self.n_dof
@@ -339,10 +342,13 @@ class Context:
             "init_hi": init_hi.to(dev, torch.float32).reshape(F, D).contiguous(),
             "stop_gen": torch.zeros((F,), device=dev, dtype=torch.int32),
         }
+        if device_seed:
+            t["seed_dev"] = torch.tensor([seed], device=dev, dtype=torch.int64)
         s = Swarm(F, n_particles, _ptr(t["frame_slots"]), _ptr(t["x"]), _ptr(t["v"]),
                   _ptr(t["pbest_x"]), _ptr(t["pbest_cost"]), _ptr(t["gbest_x"]),
                   _ptr(t["gbest_cost"]), _ptr(t["cost"]), _ptr(t["gen"]), _ptr(t["init_lo"]),
-                  _ptr(t["init_hi"]), C.c_uint64(seed), _ptr(t["stop_gen"]))
+                  _ptr(t["init_hi"]), C.c_uint64(seed), _ptr(t["stop_gen"]),
+                  _ptr(t.get("seed_dev")))
         t["_struct"] = s
         return t
 

@@ -41,6 +41,12 @@ __device__ __forceinline__ uint4 draw(uint64_t seed, int dim, int gpart, int gen
                        (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
+// The swarm's Philox key: read from device memory when the swarm has a device seed (so that a
+// captured run replays with new random numbers once the caller writes it), else the seed.
+__device__ __forceinline__ uint64_t swarm_key(const ht_swarm& sw) {
+  return sw.seed_dev ? *sw.seed_dev : sw.seed;
+}
+
 __device__ __forceinline__ float cost_key(float c) { return isnan(c) ? INFINITY : c; }
 
 // A (cost, index) pair as one 64-bit key: the cost's bits mapped to an unsigned integer of the
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void pso_init_kernel(const DevModel* __rest
     const int f = gp / P;
     const float lo = fmaxf(sw.init_lo[(size_t)f * n_dof + d], M->lo[d]);
     const float hi = fminf(sw.init_hi[(size_t)f * n_dof + d], M->hi[d]);
-    const float u = unit(draw(sw.seed, d, gp, 0, 1).x);
+    const float u = unit(draw(swarm_key(sw), d, gp, 0, 1).x);
     const float x = fminf(fmaxf(fmaf(u, hi - lo, lo), lo), hi);
     sw.x[i] = x;
     sw.v[i] = 0.0f;
@@ -325,13 +331,13 @@ __global__ __launch_bounds__(kBlock) void pso_move_kernel(const DevModel* __rest
   const float lo = M->lo[d], hi = M->hi[d];
   if (fl & kFlagMutated) {
     if (M->mutate[d]) {
-      const float u = unit(draw(sw.seed, d, gp, gen, 2).x);
+      const float u = unit(draw(swarm_key(sw), d, gp, gen, 2).x);
       sw.x[i] = fmaf(u, hi - lo, lo);
       sw.v[i] = 0.0f;
     }
     return;
   }
-  const uint4 r = draw(sw.seed, d, gp, gen, 0);
+  const uint4 r = draw(swarm_key(sw), d, gp, gen, 0);
   const float r1 = unit(r.x), r2 = unit(r.y);
   const float gb = sw.gbest_x[(size_t)f * n_dof + d];
   const float t = fmaf(prm.c2 * r2, gb - xd, fmaf(prm.c1 * r1, pb - xd, sw.v[i]));

@@ -427,3 +427,28 @@ def test_eval_counts_and_skipped_refinement_candidates():
         ctx.pso_run_graph(sw, plain, 3)
     assert ctx.eval_counts(reset=True) == (2 * 3 * 64, 0)
     ctx.close()
+
+
+def test_device_seed_replays_with_new_random_numbers():
+    """A swarm whose Philox key is read from device memory: after one capture, rewriting the
+    key makes the same cached graph replay the run of a swarm seeded with the new key (bit for
+    bit), without a new capture."""
+    torch, ctx, model, fr, sw, lo, hi = _setup(P=32)
+    ctx.reserve(32 * 4, fr["depth"].size)
+    dev = sw["x"].device
+    slots = sw["frame_slots"]
+    params = ht.pso_params()
+    dsw = ctx.swarm(slots, 32, torch.tensor(lo), torch.tensor(hi), seed=5, device_seed=True)
+    ctx.pso_run_graph(dsw, params, 4)
+    for key in (9, 123456789):
+        dsw["seed_dev"].fill_(key)
+        ctx.pso_run_graph(dsw, params, 4)
+        ref = ctx.swarm(slots, 32, torch.tensor(lo), torch.tensor(hi), seed=key)
+        ctx.pso_init(ref)
+        for _ in range(4):
+            ctx.pso_step(ref, params)
+        torch.cuda.synchronize()
+        for k in ("x", "v", "pbest_x", "pbest_cost", "gbest_x", "gbest_cost"):
+            assert torch.equal(dsw[k], ref[k]), (key, k)
+    assert dev.type == "cuda"
+    ctx.close()
