@@ -1415,7 +1415,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       const float dd = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
       const float inv_dd = fast_rcp(dd);
       float tmin = INFINITY;
-      int win = -1;
+      int win = -1;   // tracked for the gradient and the debug images only
       float wnx = 0, wny = 0, wnz = 0, wrx = 0, wry = 0, wrz = 0;
 
 #pragma unroll
@@ -1438,7 +1438,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
             // camera) exceed +inf; exact ties keep the first tested (branch-free selects)
             const bool take = h.ok & (__float_as_uint(h.t) < __float_as_uint(tmin));
             tmin = take ? h.t : tmin;
-            win = take ? k : win;
+            if (GRAD || DEBUG) win = take ? k : win;
             if (GRAD) {
               wnx = take ? h.nx : wnx;
               wny = take ? h.ny : wny;
@@ -1452,7 +1452,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       }
       // depth of the nearest entry; behind the background plane it is hidden
       const float zmin = tmin * dz;
-      const bool hit = (win >= 0) & !(fs.bg > 0.0f && zmin >= fs.bg);
+      const bool any = (GRAD || DEBUG) ? win >= 0 : __float_as_uint(tmin) < 0x7F800000u;
+      const bool hit = any & !(fs.bg > 0.0f && zmin >= fs.bg);
       win = hit ? win : -1;
       const float rd = hit ? zmin : (fs.bg > 0.0f ? fs.bg : 0.0f);
       const float diff = fabsf(od - rd);
