@@ -325,7 +325,7 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
                     const ht_debug* dbg, hipStream_t s, const int32_t* frame_stop = nullptr,
                     const int32_t* src = nullptr, int src_stride = 0,
                     const Workspace* fixed = nullptr, const int32_t* active = nullptr,
-                    int active_div = 1) {
+                    int active_div = 1, bool assemble = true, EvalArgs* args_out = nullptr) {
   const int n_total = n_frames * n_particles;
   if (n_total == 0) return HT_OK;
   if (!fixed) {
@@ -376,8 +376,10 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.n_dof = c->n_dof;
   const int kinds[kNumStages] = {HT_K_FK, HT_K_SCHED, grad ? HT_K_RAYCAST_GRAD : HT_K_RAYCAST,
                                  HT_K_FINALIZE};
+  if (args_out) *args_out = a;
   for (int stage = 0; stage < kNumStages; ++stage) {
     if (stage == kStageFk && src) continue;   // reused from the previous evaluation
+    if (stage == kStageFinalize && !assemble) continue;   // assembled by the next kernel
     if (fixed)
       HT_HIP(launch_eval_stage(stage, a, ws, s));
     else
@@ -842,30 +844,45 @@ ht_status pso_step_impl(ht_ctx* c, const ht_swarm& sw, const ht_pso_params& p, h
     HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] { return ht::launch_refine_select(sw, K, D, c->r_sel, c->r_x, c->r_cost, c->r_active, s); }));
     // the gradient at the start (the selected particles' kinematics are the swarm
     // evaluation's, still in the workspace); afterwards each step's candidates are evaluated
-    // with their gradients (except in the last step), so the accepted candidate brings its own
+    // with their gradients (except in the last step), so the accepted candidate brings its own.
+    // No evaluation of the chain is assembled by a finalize kernel: each update kernel
+    // assembles the evaluation before it (the particle's own, then its four candidates').
+    ht::EvalArgs prev{};
     st = ht::eval_impl(c, F, sw.frame_slots, K, c->r_x, c->r_cost, c->r_grad, nullptr, nullptr, s,
-                       sw.stop_gen, c->r_sel, P);
+                       sw.stop_gen, c->r_sel, P, nullptr, nullptr, 1, false, &prev);
     if (st != HT_OK) return st;
-    // step s: candidates from the current positions and gradients (fused with accepting the
-    // previous step's), their evaluation (with gradients but in the last step), and after the
-    // last step the accept fused with writing the refined particles back into the swarm
+    bool prev_grad = true;
+    // step s: accept the previous step's best candidate (after the first), propose four new
+    // ones and evaluate them; after the last step the accept is fused with writing the
+    // refined particles back into the swarm
     for (int step = 0; step <= p.refine_steps; ++step) {
       const bool accept = step > 0, propose = step < p.refine_steps;
       const bool gather = step == p.refine_steps;
-      // the gradients of the candidates being accepted now (evaluated in step - 1)
-      const float* cgrad_in = accept && step < p.refine_steps ? c->r_cgrad : nullptr;
-      HT_HIP(traced(c, HT_K_REFINE, n_ref, s, [&] {
-        return ht::launch_refine_update(c->d_model, sw, K, D, p.eta_rot, p.eta_trans, accept,
-                                        propose, gather, c->r_sel, c->r_x, c->r_cost,
-                                        c->r_active, c->r_cand, c->r_ccost, cgrad_in, c->r_grad,
-                                        s);
-      }));
+      ht::RefineArgs ra{};
+      ra.n_ref = n_ref;
+      ra.K = K;
+      ra.n_dof = D;
+      ra.eta_rot = p.eta_rot;
+      ra.eta_trans = p.eta_trans;
+      ra.op = ht::RefineOp{accept ? 1 : 0, propose ? 1 : 0, gather ? 1 : 0};
+      ra.eval_grad = prev_grad ? 1 : 0;
+      ra.sw = sw;
+      ra.sel = c->r_sel;
+      ra.rx = c->r_x;
+      ra.rcost = c->r_cost;
+      ra.active = c->r_active;
+      ra.cand = c->r_cand;
+      ra.grad = c->r_grad;
+      HT_HIP(traced(c, HT_K_REFINE, n_ref, s,
+                    [&] { return ht::launch_refine_update(prev, c->ws, ra, s); }));
       if (!propose) break;
-      float* cgrad_out = step + 1 < p.refine_steps ? c->r_cgrad : nullptr;
+      const bool g = step + 1 < p.refine_steps;
       // the four candidates of a particle that has stopped refining are not evaluated
-      st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost, cgrad_out, nullptr,
-                         nullptr, s, sw.stop_gen, nullptr, 0, nullptr, c->r_active, 4);
+      st = ht::eval_impl(c, F, sw.frame_slots, 4 * K, c->r_cand, c->r_ccost,
+                         g ? c->r_cgrad : nullptr, nullptr, nullptr, s, sw.stop_gen, nullptr, 0,
+                         nullptr, c->r_active, 4, false, &prev);
       if (st != HT_OK) return st;
+      prev_grad = g;
     }
   }
   if (F * P > c->cap_flags) {

@@ -172,10 +172,26 @@ hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht
                              int n_dof, int* flags, hipStream_t s);
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
                                 float* rcost, int* active, hipStream_t s);
-hipError_t launch_refine_update(const DevModel* model, const ht_swarm& sw, int K, int n_dof,
-                                float eta_rot, float eta_trans, bool accept, bool propose,
-                                bool gather, const int* sel, float* rx, float* rcost,
-                                int* active, float* cand, const float* ccost,
-                                const float* cgrad, float* grad, hipStream_t s);
+// One refinement update (ht_kernels.hip), fused with the assembly of the evaluation before
+// it (whose arguments and workspace it reads): the gradient evaluation of the selected
+// particles (propose only) or the evaluation of their candidates, four per particle.
+struct RefineOp {
+  int accept, propose, gather;
+};
+struct RefineArgs {
+  int n_ref, K, n_dof;
+  float eta_rot, eta_trans;
+  RefineOp op;
+  int eval_grad;             // the preceding evaluation computed gradients
+  ht_swarm sw;
+  const int* sel;            // [n_ref] swarm index of each refined particle
+  float* rx;                 // [n_ref][n_dof] positions
+  float* rcost;              // [n_ref] costs
+  int* active;               // [n_ref] 1 while refining
+  float* cand;               // [4 n_ref][n_dof] candidates
+  float* grad;               // [n_ref][n_dof] gradients at rx
+};
+hipError_t launch_refine_update(const EvalArgs& a, const Workspace& ws, const RefineArgs& ra,
+                                hipStream_t s);
 
 }  // namespace ht

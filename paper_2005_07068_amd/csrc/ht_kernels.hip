@@ -214,6 +214,32 @@ constexpr int kItemsPerGroup = 1;
 // Inclusive scan over the workgroup; every thread gets its own prefix and the total: a scan
 // within each wavefront by lane shifts, then the wavefront totals through LDS (two barriers
 // instead of two per doubling step).
+// The same for a pair: v is scanned, w only totalled, through the same two barriers.
+template <int NW>
+__device__ int block_scan2(int2* s_sum, int v, int w, int* total_v, int* total_w) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+    w += __shfl_xor(w, o);
+  }
+  if (lane == kWave - 1) s_sum[wv] = make_int2(v, w);
+  __syncthreads();
+  int before = 0, all = 0, all_w = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const int2 t = s_sum[q];
+    before += q < wv ? t.x : 0;
+    all += t.x;
+    all_w += t.y;
+  }
+  __syncthreads();
+  *total_v = all;
+  *total_w = all_w;
+  return v + before;
+}
+
 template <int NW>
 __device__ int block_scan(int* s_sum, int v, int* total) {
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
@@ -307,9 +333,9 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
       evaluated += v[j] >= 0 ? 1 : 0;
     }
   }
+  __shared__ int2 s_sum2[kNW];
   int total_tiles, total_evaluated;
-  block_scan<kNW>(s_sum, tiles, &total_tiles);
-  block_scan<kNW>(s_sum, evaluated, &total_evaluated);
+  block_scan2<kNW>(s_sum2, tiles, evaluated, &total_tiles, &total_evaluated);
   const long long target = (long long)a.grid * kItemsPerGroup;
   long long tq = ((long long)total_tiles + target - 1) / target;
   tq = (tq + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
@@ -1740,6 +1766,224 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
     }
     a.grad[(size_t)p * n_dof + j] = (float)g;
   }
+}
+
+// ------------------------------------------------------------------------------------
+// gradient refinement update, fused with the assembly of the preceding evaluation
+//
+// One workgroup per refined particle r.  First the evaluation that precedes this update is
+// assembled, one wavefront per evaluated particle, as the finalize kernels would (the cost of
+// Eq. 4-5 from the item partials; with gradients the per-segment wrench sums in item order
+// and the kinematic adjoint, one lane per pose parameter): the particle itself after the
+// gradient evaluation of the selected particles (wavefront 0), or its four candidates after a
+// candidate evaluation (wavefront j: candidate j).  Then wavefront 0, one lane per dimension:
+//   accept  - take the longest of the four steps that lowers E (the first in halving order);
+//             when the candidates were evaluated with gradients the accepted one's becomes
+//             the particle's gradient; no step lowers E: the particle stops refining;
+//   propose - four candidates x - eta * (g_s / max|g_s|) / 2^j, j = 0..3, g_s = eta * dE/dh,
+//             clamped to the bounds; a particle that has stopped (or whose g_s is zero or not
+//             finite, which stops it) writes its own position four times, and its candidates
+//             are skipped by the evaluation (its active flag is 0);
+//   gather  - write the refined positions and costs back into the swarm.
+
+// Cost of evaluated particle p and, with grad, lane j's component of its gradient (lanes past
+// n_dof: 0), assembled by one wavefront.  W, org: this wavefront's LDS rows ([n_seg * 6]
+// wrench sums, [n_seg * 4] segment origins).  Returns false for a particle that was skipped
+// (not evaluated).  Holds no barrier.
+__device__ bool assemble_wave(const EvalArgs& a, const Workspace& ws, int p, bool grad,
+                              double* W, float* org, float& cost, float& g) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int n_seg = a.n_seg, n_dof = a.n_dof, nv = n_seg * 6;
+  const int ps = uni(src_of(a, p));
+  const int b = uni(ws.item_off[p]), e = uni(ws.item_off[p + 1]);
+  // loads that depend on the particle alone, issued before any branch: the record, the first
+  // partials, this lane's pose-parameter frame and segment-origin values (clamped indices)
+  const PInfo pi = ws.pinfo[ps];
+  const Partial pr0 = first_partial(ws, b, e, lane);
+  const int jc = min(lane, n_dof - 1);
+  const float4* f4 = reinterpret_cast<const float4*>(ws.dof_frame + ((size_t)ps * n_dof + jc) * 8);
+  const float4 f0 = f4[0], f1 = f4[1];
+  const uint32_t desc = lane < n_dof ? a.model->dof_desc[jc] : 0u;
+  const float* org_src = ws.seg_org + (size_t)ps * n_seg * 4;
+  const float o0 = org_src[min(lane, n_seg * 4 - 1)];
+  const float o1 = org_src[min(lane + kWave, n_seg * 4 - 1)];
+  double S_d;
+  long long S_and, S_or;
+  wave_partial_sums(pi, ws, b, e, lane, pr0, S_d, S_and, S_or);
+  g = 0.0f;
+  if (pi.skip) return false;
+  if (!pi.valid) {
+    cost = pi.slot < 0 ? NAN : INFINITY;
+    return true;
+  }
+  cost = cost_from_sums(S_d, S_and, S_or, pi.kc);
+  if (!grad) return true;
+  // wrench rows summed in item order (lane l: values l, l + 64, l + 128), four items' loads in
+  // flight at a time (indices clamped into the particle's items; past the end adds zero)
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int i0 = b; i0 < e; i0 += 4) {
+    float v[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float* src = ws.wrench + (size_t)min(i0 + u, e - 1) * nv;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[u][k] = src[min(lane + k * kWave, nv - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        acc[k] += (i0 + u < e && lane + k * kWave < nv) ? (double)v[u][k] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (lane + k * kWave < nv) W[lane + k * kWave] = acc[k];
+  if (lane < n_seg * 4) org[lane] = o0;
+  if (lane + kWave < n_seg * 4) org[lane + kWave] = o1;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // the kinematic adjoint of the finalize kernel, lane j = pose parameter j
+  const int j = lane;
+  if (j < n_dof) {
+    const double inv_or = S_or > 0 ? 1.0 / (double)S_or : 0.0;
+    const bool trans = f0.x != 0.0f;
+    const double ax = f0.y, ay = f0.z, az = f0.w;
+    double acc_g = 0.0;
+    for (uint32_t m = desc; m; m &= m - 1) {
+      const int sg = __builtin_ctz(m);
+      const double* Ws = W + sg * 6;
+      if (trans) {
+        acc_g += ax * Ws[3] + ay * Ws[4] + az * Ws[5];
+      } else {
+        const double lx = (double)org[sg * 4 + 0] - f1.x;
+        const double ly = (double)org[sg * 4 + 1] - f1.y;
+        const double lz = (double)org[sg * 4 + 2] - f1.z;
+        const double mx = Ws[0] + (ly * Ws[5] - lz * Ws[4]);
+        const double my = Ws[1] + (lz * Ws[3] - lx * Ws[5]);
+        const double mz = Ws[2] + (lx * Ws[4] - ly * Ws[3]);
+        acc_g += ax * mx + ay * my + az * mz;
+      }
+    }
+    acc_g *= inv_or;
+    for (int m = pi.kc_mask; m; m &= m - 1) {
+      const int i = __builtin_ctz(m);
+      if (a.model->kc_a[i] == j) acc_g -= kLambdaK;
+      if (a.model->kc_b[i] == j) acc_g += kLambdaK;
+    }
+    g = (float)acc_g;
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kBlock) void refine_update_kernel(EvalArgs a, Workspace ws,
+                                                               RefineArgs ra) {
+  __shared__ double s_W[kWavesPerBlock][HT_MAX_SEG * 6];
+  __shared__ float s_org[kWavesPerBlock][HT_MAX_SEG * 4];
+  __shared__ float s_cost[kWavesPerBlock];
+  __shared__ float s_g[kWavesPerBlock][HT_MAX_DOF];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = blockIdx.x;                       // refined particle (frame * K + rank)
+  const int n_dof = ra.n_dof;
+  // 1. the preceding evaluation: the particle itself (propose only), else its candidates
+  const bool mine = ra.op.accept ? true : w == 0;
+  if (mine) {
+    const int p = ra.op.accept ? r * 4 + w : r;
+    float c = INFINITY, g = 0.0f;
+    if (!assemble_wave(a, ws, p, ra.eval_grad, s_W[w], s_org[w], c, g)) c = INFINITY;
+    if (lane == 0) s_cost[w] = c;
+    if (lane < HT_MAX_DOF) s_g[w][lane] = g;
+  }
+  __syncthreads();
+  if (w != 0) return;
+  const bool on = lane < n_dof;
+  const int d = on ? lane : 0;
+  const size_t xi = (size_t)r * n_dof + d;
+  bool act = ra.active[r] != 0;
+  float x = ra.rx[xi];
+  float c, gd;
+  if (!ra.op.accept) {
+    // the gradient evaluation of the selected particle: its cost and gradient
+    c = s_cost[0];
+    gd = s_g[0][d];
+    if (on) ra.grad[xi] = gd;
+    if (lane == 0) ra.rcost[r] = c;
+  } else {
+    c = ra.rcost[r];
+    gd = ra.grad[xi];
+  }
+  if (ra.op.accept && act) {
+    // the four candidates' costs (a skipped one counts as +inf) and positions
+    float cc[4], cx[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cc[j] = s_cost[j];
+      cx[j] = ra.cand[((size_t)r * 4 + j) * n_dof + d];
+    }
+    int pick = -1;
+#pragma unroll
+    for (int j = 3; j >= 0; --j)
+      if (cc[j] < c) pick = j;
+    if (pick < 0) {
+      act = false;
+      if (lane == 0) ra.active[r] = 0;
+    } else {
+      float nx = cx[0], ng = s_g[0][d];
+      c = cc[0];
+#pragma unroll
+      for (int j = 1; j < 4; ++j) {
+        nx = pick == j ? cx[j] : nx;
+        ng = pick == j ? s_g[j][d] : ng;
+        c = pick == j ? cc[j] : c;
+      }
+      x = nx;
+      if (on) {
+        ra.rx[xi] = x;
+        if (ra.eval_grad) {
+          gd = ng;
+          ra.grad[xi] = gd;
+        }
+      }
+      if (lane == 0) ra.rcost[r] = c;
+    }
+  }
+  if (ra.op.propose) {
+    const float eta = a.model->dof_trans[d] ? ra.eta_trans : ra.eta_rot;
+    const float gs = on ? eta * gd : 0.0f;
+    float gmax = fabsf(gs);
+    bool fin = isfinite(gs);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o));
+    fin = __ballot(!fin) == 0ull;
+    const bool ok = act && fin && gmax > 0.0f;
+    // a particle without a usable step stops refining: its candidates are not evaluated
+    if (act && !ok && lane == 0) ra.active[r] = 0;
+    if (on) {
+      for (int j = 0; j < 4; ++j) {
+        float xn = x;
+        if (ok) {
+          const float step = eta * (gs / gmax) * ldexpf(1.0f, -j);
+          xn = fminf(fmaxf(x - step, a.model->lo[d]), a.model->hi[d]);
+        }
+        ra.cand[((size_t)r * 4 + j) * n_dof + d] = xn;
+      }
+    }
+  }
+  if (ra.op.gather) {
+    const int f = r / ra.K;
+    if (ra.sw.stop_gen && ra.sw.stop_gen[f] != 0) return;
+    const size_t gp = (size_t)f * ra.sw.n_particles + ra.sel[r];
+    if (on) ra.sw.x[gp * n_dof + d] = x;
+    if (lane == 0) ra.sw.cost[gp] = c;
+  }
+}
+
+hipError_t launch_refine_update(const EvalArgs& a, const Workspace& ws, const RefineArgs& ra,
+                                hipStream_t s) {
+  if (ra.n_ref == 0) return hipSuccess;
+  hipLaunchKernelGGL(refine_update_kernel, dim3(ra.n_ref), dim3(kBlock), 0, s, a, ws, ra);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------

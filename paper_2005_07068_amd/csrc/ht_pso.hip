@@ -1,5 +1,6 @@
 // Particle swarm kernels: initialisation, the generation update of Eq. 6-7 with the mutation
-// of section III.B, and the stages of gradient refinement (select, propose, accept, gather).
+// of section III.B, and the selection of the particles that gradient refinement starts from
+// (its update kernel, fused with assembling the evaluations, is in ht_kernels.hip).
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed, counter
 // (dimension, frame * P + particle, generation, stream); uniform = (word >> 8) * 2^-24.
@@ -371,9 +372,10 @@ hipError_t launch_pso_update(const DevModel* model, const ht_swarm& sw, const ht
 // gradient refinement
 //
 // select: the K lowest current costs of each frame (ties: lower index first), copied into
-// the refinement buffers; propose: four step lengths (1, 1/2, 1/4, 1/8) of the normalised
-// steepest-descent step in the eta-scaled space; accept: the first length whose cost is lower
-// than the current one, else the particle stops refining; gather: back into the swarm.
+// the refinement buffers.  The steps that follow (propose four step lengths 1, 1/2, 1/4, 1/8
+// of the normalised steepest-descent step in the eta-scaled space; accept the first length
+// whose cost is lower than the current one, else stop refining; gather back into the swarm)
+// are the update kernel in ht_kernels.hip.
 
 __global__ __launch_bounds__(kPsoBlock) void refine_select_kernel(ht_swarm sw, int K, int n_dof,
                                                                   int n_pad,
@@ -486,106 +488,6 @@ __global__ __launch_bounds__(kPsoBlock) void refine_select_small_kernel(
   }
 }
 
-// One refinement update, one wavefront per refined particle and one lane per dimension:
-//   accept  - take the longest of the four steps that lowers E (the first in halving order);
-//             with cgrad the candidates' gradients were evaluated with their costs and the
-//             accepted one's becomes the particle's gradient; no step lowers E: the particle
-//             stops refining;
-//   propose - four candidates x - eta * (g_s / max|g_s|) / 2^j, j = 0..3, g_s = eta * dE/dh,
-//             clamped to the bounds; a particle that has stopped (or whose g_s is zero or not
-//             finite, which stops it) writes its own position four times, and its candidates
-//             are skipped by the evaluation (its active flag is 0);
-//   gather  - write the refined positions and costs back into the swarm.
-struct RefineOp {
-  int accept, propose, gather;
-};
-
-__global__ __launch_bounds__(kBlock) void refine_update_kernel(
-    const DevModel* __restrict__ M, int n_ref, int n_dof, float eta_rot, float eta_trans,
-    RefineOp op, ht_swarm sw, int K, const int* __restrict__ sel, float* __restrict__ rx,
-    float* __restrict__ rcost, int* __restrict__ active, float* __restrict__ cand,
-    const float* __restrict__ ccost, const float* __restrict__ cgrad, float* __restrict__ grad) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int r = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (r >= n_ref) return;
-  const bool on = lane < n_dof;
-  const int d = on ? lane : 0;
-  const size_t xi = (size_t)r * n_dof + d;
-  bool act = active[r] != 0;
-  float x = rx[xi];
-  float c = rcost[r];
-  float g = grad[xi];
-  if (op.accept) {
-    // the four candidates' costs, positions and gradients are loaded together (lanes past
-    // n_dof read dimension 0 and store nothing), then the accepted one is selected
-    float cc[4], cx[4], cg[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const size_t src = ((size_t)r * 4 + j) * n_dof + d;
-      cc[j] = ccost[(size_t)r * 4 + j];
-      cx[j] = cand[src];
-      cg[j] = cgrad ? cgrad[src] : 0.0f;
-    }
-    if (act) {
-      int pick = -1;
-#pragma unroll
-      for (int j = 3; j >= 0; --j)
-        if (cc[j] < c) pick = j;
-      if (pick < 0) {
-        act = false;
-        if (lane == 0) active[r] = 0;
-      } else {
-        float nx = cx[0], ng = cg[0];
-        c = cc[0];
-#pragma unroll
-        for (int j = 1; j < 4; ++j) {
-          nx = pick == j ? cx[j] : nx;
-          ng = pick == j ? cg[j] : ng;
-          c = pick == j ? cc[j] : c;
-        }
-        x = nx;
-        if (on) {
-          rx[xi] = x;
-          if (cgrad) {
-            g = ng;
-            grad[xi] = g;
-          }
-        }
-        if (lane == 0) rcost[r] = c;
-      }
-    }
-  }
-  if (op.propose) {
-    const float eta = M->dof_trans[d] ? eta_trans : eta_rot;
-    const float gs = on ? eta * g : 0.0f;
-    float gmax = fabsf(gs);
-    bool fin = isfinite(gs);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o));
-    fin = __ballot(!fin) == 0ull;
-    const bool ok = act && fin && gmax > 0.0f;
-    // a particle without a usable step stops refining: its candidates are not evaluated
-    if (act && !ok && lane == 0) active[r] = 0;
-    if (on) {
-      for (int j = 0; j < 4; ++j) {
-        float xn = x;
-        if (ok) {
-          const float step = eta * (gs / gmax) * ldexpf(1.0f, -j);
-          xn = fminf(fmaxf(x - step, M->lo[d]), M->hi[d]);
-        }
-        cand[((size_t)r * 4 + j) * n_dof + d] = xn;
-      }
-    }
-  }
-  if (op.gather) {
-    const int f = r / K;
-    if (sw.stop_gen && sw.stop_gen[f] != 0) return;
-    const size_t gp = (size_t)f * sw.n_particles + sel[r];
-    if (on) sw.x[gp * n_dof + d] = x;
-    if (lane == 0) sw.cost[gp] = c;
-  }
-}
-
 hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, float* rx,
                                 float* rcost, int* active, hipStream_t s) {
   if (sw.n_particles <= kPsoBlock && K <= kWave) {
@@ -597,19 +499,6 @@ hipError_t launch_refine_select(const ht_swarm& sw, int K, int n_dof, int* sel, 
   const int n_pad = pow2_at_least(sw.n_particles);
   hipLaunchKernelGGL(refine_select_kernel, dim3(sw.n_frames), dim3(threads_for(sw.n_particles)),
                      (size_t)n_pad * 8, s, sw, K, n_dof, n_pad, sel, rx, rcost, active);
-  return hipGetLastError();
-}
-
-hipError_t launch_refine_update(const DevModel* model, const ht_swarm& sw, int K, int n_dof,
-                                float eta_rot, float eta_trans, bool accept, bool propose,
-                                bool gather, const int* sel, float* rx, float* rcost,
-                                int* active, float* cand, const float* ccost,
-                                const float* cgrad, float* grad, hipStream_t s) {
-  const int n_ref = sw.n_frames * K;
-  const RefineOp op{accept ? 1 : 0, propose ? 1 : 0, gather ? 1 : 0};
-  hipLaunchKernelGGL(refine_update_kernel, dim3((n_ref + kWavesPerBlock - 1) / kWavesPerBlock),
-                     dim3(kBlock), 0, s, model, n_ref, n_dof, eta_rot, eta_trans, op, sw, K, sel,
-                     rx, rcost, active, cand, ccost, cgrad, grad);
   return hipGetLastError();
 }
 

@@ -266,7 +266,8 @@ def test_kernel_tracing_counts_one_refined_generation():
     """The per-kernel trace of one generation with refinement (K = 8, 2 steps, workspace
     reserved, so the first gradient evaluation reuses the swarm's kinematics): the swarm
     evaluation, the gradient evaluation of the 8 best, a gradient and a forward evaluation of
-    the 32 candidates, the select and three updates, and the swarm update."""
+    the 32 candidates (each of these three assembled by the update kernel that follows it, not
+    by a finalize launch), the select and three updates, and the swarm update."""
     torch, ctx, model, fr, sw, lo, hi = _setup(P=64)
     ctx.reserve(64 * 4, fr["depth"].size)
     ctx.pso_init(sw)
@@ -276,7 +277,7 @@ def test_kernel_tracing_counts_one_refined_generation():
     st = ctx.profile_end()
     ctx.close()
     launches = {k: v["launches"] for k, v in st.items()}
-    assert launches == {"fk": 3, "sched": 4, "raycast": 2, "raycast_grad": 2, "finalize": 4,
+    assert launches == {"fk": 3, "sched": 4, "raycast": 2, "raycast_grad": 2, "finalize": 1,
                         "pso": 1, "refine": 4}, launches
     assert st["fk"]["particles"] == 64 + 2 * 32
     assert st["raycast_grad"]["particles"] == 8 + 32
