@@ -37,9 +37,9 @@ METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at 
 # FP32 operations (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes).  Keyed by the SHA-256 of the kernel
 # sources they were measured on: any later change of the kernel reports null.
 MEASURED_COUNTERS = {
-    "c34b2e4233c13428fd68f7935d6c5419419118d04269dd5ed7b575bd3f680af6": {
-        "config": 4, "fetch_kib": 15146.664, "write_kib": 303.679, "fetch_scale": 2.0,
-        "write_scale": 1.0, "fp32_flop": 2.318e9},
+    "4fa6e7a1ba4ae2000d19da44a0838b3077b88988807e9aa2736fd074771d3fa3": {
+        "config": 4, "fetch_kib": 15126.407, "write_kib": 304.814, "fetch_scale": 2.0,
+        "write_scale": 1.0, "fp32_flop": 2.317e9},
 }
 KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",
                   "paper_2005_07068_amd/csrc/ht_device.h")
@@ -799,6 +799,12 @@ def main():
     if args.ablation or not args.no_study:
         log("swarm constants and mutation ablation over seeds")
         line["pso_ablation"] = pso_ablation(ctx, ht, torch, cfg, model, slots, lo, hi, h_true)
+    if not args.no_study:
+        log("tracking the 30-frame sequence (the workload's box; a 3 deg / 6 mm box with "
+            "3 gradient steps on the best 8)")
+        line["tracking"] = {"workload_box": track_sequence(ht, torch),
+                            "narrow_box_refined": track_sequence(ht, torch, box=(3.0, 6.0),
+                                                                 refine=(8, 3))}
     if baseline is not None:
         line["cpu_baseline"] = baseline
     print(json.dumps(line), flush=True)
