@@ -1311,6 +1311,18 @@ struct TileWalk {
 // ------------------------------------------------------------------------------------
 // persistent ray cast + cost terms + reduction
 
+// Workgroups are dispatched to the chip's 8 XCDs round-robin (workgroup b on XCD b mod 8), each
+// XCD with its own L2.  The first item of workgroup b is taken XCD-major: XCD x's workgroups
+// take the x-th eighth of the items in order, so the consecutive items of one particle (and
+// its staged tables) stay on one XCD instead of spreading over all eight.  A bijection of
+// 0 .. G-1 for any grid size G.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_major_item(int b, int G) {
+  const int q = G / kXcds, rem = G % kXcds;
+  const int x = b % kXcds, j = b / kXcds;
+  return x * q + min(x, rem) + j;
+}
+
 // NT: primitive types the model uses (3: spheres, cylinders, ellipsoids; kNumTypes: also
 // cones and elliptic cylinders), so a model without the latter keeps the smaller register
 // footprint.  (Forcing more wavefronts per SIMD than the natural register count allows
@@ -1345,7 +1357,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
   for (;;) {
     int item;
     if (first) {
-      item = blockIdx.x;
+      item = xcd_major_item(blockIdx.x, gridDim.x);
       first = false;
     } else {
       if (tid == 0) s_item = (int)gridDim.x + atomicAdd(&ws.counters[0], 1);
