@@ -157,14 +157,18 @@ def test_batched_frames_equal_per_frame_calls_and_the_oracle():
 
 
 def test_full_size_adjoint_shape_sampled_particles():
-    """320x240 workload (256 particles): every cost computed, 6 sampled vs oracle."""
+    """320x240 workload (256 particles in one launch): every cost computed, every 8th
+    particle (32, first and last included) against the resolved oracle."""
     cfg, model, fr = frame_for(2)
     poses = particles_for(model, fr, cfg.n_particles, seed=11)
     ctx = make_ctx(model, [fr])
     cost, dbg = eval_debug(ctx, poses, 0, 320, 240)
+    ctx.close()
     assert np.all(np.isfinite(cost))
-    for i in (0, 37, 101, 180, 222, 255):
-        check_particle(model, fr, poses[i], cost[i], dbg, i)
+    idx = list(range(0, 256, 8)) + [255]
+    rendered = oracle_renders(model, [(fr, poses[i]) for i in idx])
+    for i, rd in zip(idx, rendered):
+        check_particle(model, fr, poses[i], cost[i], dbg, i, rendered=rd)
 
 
 def test_full_frame_two_hands_sampled_particles():

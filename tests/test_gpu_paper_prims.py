@@ -4,8 +4,8 @@ against the FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
 
-from gpu_util import (check_particle, eval_debug, frame_for, make_ctx, particles_for,
-                      torch_cuda)
+from gpu_util import (check_particle, eval_debug, frame_for, make_ctx, oracle_renders,
+                      particles_for, torch_cuda)
 from oracle import cost as ocost
 from oracle import grad as ograd
 from oracle import raycast, synth
@@ -14,19 +14,26 @@ from workload import CONE, ECYLINDER, make_hand_model, seed_sequence
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg_idx,n", [(0, 16), (2, 6)])
+@pytest.mark.parametrize("cfg_idx,n", [(0, 16), (2, 16), (5, 16)])
 def test_paper_model_parity_masks_depths_costs(cfg_idx, n):
+    """The paper's primitive set at 64x64 and 320x240 (one hand) and 640x480 (two hands, the
+    workload-5 frame): every particle against the resolved oracle."""
     cfg, model, fr = frame_for(cfg_idx, primitive_set="paper")
-    assert (model["prim_type"] == CONE).sum() == 14 and (model["prim_type"] == ECYLINDER).sum() == 1
+    per_hand = 1 if cfg_idx != 5 else 2
+    assert (model["prim_type"] == CONE).sum() == 14 * per_hand
+    assert (model["prim_type"] == ECYLINDER).sum() == per_hand
     poses = particles_for(model, fr, n, seed=11)
     poses[0] = fr["h_true"].astype(np.float32)
     H, W = fr["depth"].shape
     ctx = make_ctx(model, [fr])
     cost, dbg = eval_debug(ctx, poses, 0, W, H)
-    diags = [check_particle(model, fr, poses[i], cost[i], dbg, i) for i in range(n)]
+    ctx.close()
+    rendered = oracle_renders(model, [(fr, poses[i]) for i in range(n)])
+    diags = [check_particle(model, fr, poses[i], cost[i], dbg, i, rendered=rendered[i])
+             for i in range(n)]
     print("paper model", cfg_idx, diags[:3])
     # the cones and the palm are really seen
-    res = raycast.render(model, poses[0].astype(np.float64), W, H, fr["cam"], fr["bg"])
+    res = rendered[0][0]
     seen = model["prim_type"][res["winner"][res["hit"]]]
     assert (seen == CONE).sum() > 0.01 * W * H and (seen == ECYLINDER).sum() > 0.002 * W * H
 
