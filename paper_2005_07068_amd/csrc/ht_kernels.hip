@@ -489,6 +489,11 @@ __device__ __forceinline__ void load_prim(const DevModel* __restrict__ G, int o,
   }
 }
 
+// WPP wavefronts per particle: 1, or 2 for models of more than 64 primitives, whose set-up then
+// takes one round on each of the two wavefronts instead of two rounds on one (the second
+// wavefront waits for the first one's trigonometry and chains at the barriers, and sets up
+// primitives 64..127; the first writes the record).
+template <int WPP>
 __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws) {
   __shared__ double s_T[kWavesPerBlock][HT_MAX_SEG][12];
   __shared__ double s_h[kWavesPerBlock][HT_MAX_DOF];
@@ -512,79 +517,84 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   // (scalar instructions and branches)
   const int lane = threadIdx.x & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int kPpb = kWavesPerBlock / WPP;     // particles per workgroup
+  const int pb = w / WPP, h = w % WPP;           // particle in the workgroup, its wavefront
   const int n_total = a.n_frames * a.n_particles;
-  const int p = blockIdx.x * kWavesPerBlock + w;
+  const int p = blockIdx.x * kPpb + pb;
   const bool active = p < n_total;
   const int n_dof = a.n_dof, n_seg = a.n_seg, n_prim = a.n_prim;
+  __shared__ int s_fin[kWavesPerBlock];
   PrimIn pin0;
-  if (active && lane < n_prim) load_prim(G, lane, pin0);
+  if (active && lane + h * kWave < n_prim) load_prim(G, lane + h * kWave, pin0);
 
   // every angle's sine and cosine at once (one lane per pose parameter), so the tree walk
   // below is trigonometry-free
   bool finite = true;
-  if (active) {
+  if (active && h == 0) {
     for (int i = lane; i < n_dof; i += kWave) {
       const float x = a.poses[(size_t)p * n_dof + i];
-      s_h[w][i] = (double)x;
+      s_h[pb][i] = (double)x;
       finite = finite && isfinite(x);
       double sv = 0.0, cv = 1.0;
       if (isfinite(x)) sincos((double)x, &sv, &cv);
-      s_sin[w][i] = sv;
-      s_cos[w][i] = cv;
+      s_sin[pb][i] = sv;
+      s_cos[pb][i] = cv;
     }
   }
   finite = __ballot(!finite) == 0ull;
+  if (h == 0 && lane == 0) s_fin[pb] = finite ? 1 : 0;
   int slot = -1;
   if (active) slot = a.frame_slots[p / a.n_particles];
   const bool slot_ok = active && slot >= 0 && slot < HT_MAX_SLOTS && a.slots[slot].set;
-  // a particle of a stopped frame (tracking stop rule) is neither cast nor written
   // a particle of a stopped frame (tracking stop rule), or a candidate of a refined particle
   // that has stopped refining, is neither cast nor written
   const bool skip = active && ((a.frame_stop && a.frame_stop[p / a.n_particles] != 0) ||
                                (a.active && a.active[p / a.active_div] == 0));
-  const bool valid = slot_ok && finite && !skip;
   // the slot's background sums, needed only by the record written at the end
   double bg_td = 0.0, bg_or = 0.0;
-  if (valid) {
+  if (slot_ok && h == 0) {
     const double* tot = a.slots[slot].totals;
     bg_td = tot[0];
     bg_or = tot[1];
   }
   __syncthreads();
+  // the first wavefront's finiteness test, for every wavefront of the particle
+  if (WPP > 1) finite = __builtin_amdgcn_readfirstlane(s_fin[pb]) != 0;
+  const bool valid = slot_ok && finite && !skip;
 
   // segment transforms, T_s = W L_root ... L_parent(s) L_s with L_s = Off_s Rot(a1, q1)
   // Rot(a2, q2) and W the wrist of s's tree: every lane forms its own L_s once and stages it
   // in LDS, then multiplies its ancestors' staged transforms right to left (the tree is
   // shallow: palm and three phalanges), so no joint rotation is computed twice.
   __shared__ double s_L[kWavesPerBlock][HT_MAX_SEG][12];
-  const bool seg_lane = valid && lane < n_seg;
+  const bool seg_lane = valid && h == 0 && lane < n_seg;
   if (seg_lane) {
     double Lm[12];
     for (int i = 0; i < 12; ++i) Lm[i] = M.seg_off[lane][i];
     for (int j = 0; j < 2; ++j) {
       const int dof = M.seg_dof[lane][j];
-      if (dof >= 0) post_rotate(Lm, M.seg_axis[lane][j], s_sin[w][dof], s_cos[w][dof]);
+      if (dof >= 0) post_rotate(Lm, M.seg_axis[lane][j], s_sin[pb][dof], s_cos[pb][dof]);
     }
-    for (int i = 0; i < 12; ++i) s_L[w][lane][i] = Lm[i];
+    for (int i = 0; i < 12; ++i) s_L[pb][lane][i] = Lm[i];
   }
   __syncthreads();
   if (seg_lane) {
     double P[12];
-    for (int i = 0; i < 12; ++i) P[i] = s_L[w][lane][i];
+    for (int i = 0; i < 12; ++i) P[i] = s_L[pb][lane][i];
     int q = M.seg_parent[lane], root = lane;
     while (q >= 0) {
       double Q[12];
-      mul34(s_L[w][q], P, Q);
+      mul34(s_L[pb][q], P, Q);
       for (int i = 0; i < 12; ++i) P[i] = Q[i];
       root = q;
       q = M.seg_parent[q];
     }
     // wrist: Trans(x, y, z) Rz(tz) Ry(ty) Rx(tx)
     const int b = M.seg_root_dof[root];
-    const double* hq = &s_h[w][b];
-    const double sx = s_sin[w][b + 3], cx = s_cos[w][b + 3];
-    const double sy = s_sin[w][b + 4], cy = s_cos[w][b + 4];
-    const double sz = s_sin[w][b + 5], cz = s_cos[w][b + 5];
+    const double* hq = &s_h[pb][b];
+    const double sx = s_sin[pb][b + 3], cx = s_cos[pb][b + 3];
+    const double sy = s_sin[pb][b + 4], cy = s_cos[pb][b + 4];
+    const double sz = s_sin[pb][b + 5], cz = s_cos[pb][b + 5];
     const double Rzy[9] = {cz * cy, -sz, cz * sy, sz * cy, cz, sz * sy, -sy, 0.0, cy};
     double W0[12];
     W0[0] = Rzy[0];
@@ -626,7 +636,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
     }
     double T[12];
     mul34(W0, P, T);
-    for (int i = 0; i < 12; ++i) s_T[w][lane][i] = T[i];
+    for (int i = 0; i < 12; ++i) s_T[pb][lane][i] = T[i];
     // joint axes in the camera frame: the second joint's axis is R_s a2; the first's is
     // R_s Rot(a2, q2)^T a1 (each rotation leaves its own axis fixed); both pass through the
     // segment origin
@@ -638,7 +648,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
       if (j == 0 && dof2 >= 0) {
         // Rot(a2, q2)^T v = c v - s (a2 x v) + (1 - c)(a2 . v) a2
         const double* a2 = M.seg_axis[lane][1];
-        const double sn = s_sin[w][dof2], cs = s_cos[w][dof2];
+        const double sn = s_sin[pb][dof2], cs = s_cos[pb][dof2];
         const double dt = (1.0 - cs) * (a2[0] * v[0] + a2[1] * v[1] + a2[2] * v[2]);
         const double cr[3] = {a2[1] * v[2] - a2[2] * v[1], a2[2] * v[0] - a2[0] * v[2],
                               a2[0] * v[1] - a2[1] * v[0]};
@@ -660,9 +670,9 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   }
   // collision terms of Eq. 5, one per spare lane (summed in order below)
   __shared__ double s_kc[kWavesPerBlock][HT_MAX_KC];
-  if (valid && lane >= kWave - HT_MAX_KC && lane - (kWave - HT_MAX_KC) < M.n_kc) {
+  if (valid && h == 0 && lane >= kWave - HT_MAX_KC && lane - (kWave - HT_MAX_KC) < M.n_kc) {
     const int i = lane - (kWave - HT_MAX_KC);
-    s_kc[w][i] = fmax(-(s_h[w][G->kc_a[i]] - s_h[w][G->kc_b[i]]), 0.0);
+    s_kc[pb][i] = fmax(-(s_h[pb][G->kc_a[i]] - s_h[pb][G->kc_b[i]]), 0.0);
   }
   __syncthreads();
 
@@ -670,24 +680,25 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   // of the three set-up paths per round); per-tree unions of the primitive boxes (u0, v0 minima; u1, v1 maxima), accumulated with
   // LDS atomics (cheaper than sixteen wave reductions)
   __shared__ int s_rect[kWavesPerBlock][kMaxRects][4];
-  if (lane < kMaxRects * 4) s_rect[w][lane >> 2][lane & 3] = (lane & 1) ? INT_MIN : INT_MAX;
+  if (h == 0 && lane < kMaxRects * 4)
+    s_rect[pb][lane >> 2][lane & 3] = (lane & 1) ? INT_MIN : INT_MAX;
   __syncthreads();
   if (valid) {
     const FrameSlot fs = a.slots[slot];
-    for (int o = lane; o < n_prim; o += kWave) {
+    for (int o = lane + h * kWave; o < n_prim; o += kWave * WPP) {
       PrimIn pin;
-      if (o == lane) pin = pin0;
+      if (o == lane + h * kWave) pin = pin0;
       else load_prim(G, o, pin);
       const int k = pin.k;
       const int s = pin.seg;
       double F[12];
-      mul34(s_T[w][s], pin.frame, F);
+      mul34(s_T[pb][s], pin.frame, F);
       const double* sz = pin.size;
       const int typ = pin.type;
       float rec[kRec];
       for (int i = 0; i < kRec; ++i) rec[i] = 0.0f;
       const double c[3] = {F[3], F[7], F[11]};
-      const double* T = s_T[w][s];
+      const double* T = s_T[pb][s];
       split(c[0], rec[0], rec[4]);
       split(c[1], rec[1], rec[5]);
       split(c[2], rec[2], rec[6]);
@@ -863,7 +874,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
       if (box.x > box.y || box.z > box.w) box = make_int4(1, 0, 1, 0);
       ws.boxes[(size_t)p * n_prim + k] = box;
       if (box.x <= box.y) {
-        int* rq = s_rect[w][pin.root];
+        int* rq = s_rect[pb][pin.root];
         atomicMin(rq + 0, box.x);
         atomicMax(rq + 1, box.y);
         atomicMin(rq + 2, box.z);
@@ -872,7 +883,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
     }
   }
   __syncthreads();
-  if (active) {
+  if (active && h == 0) {
     // every lane computes the record from wave-uniform values (scalar instructions); lane 0
     // stores it
     PInfo pi{};
@@ -886,7 +897,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
       const int n_kc = __builtin_amdgcn_readfirstlane(M.n_kc);
 #pragma unroll
       for (int i = 0; i < HT_MAX_KC; ++i) {
-        const double v = i < n_kc ? s_kc[w][i] : 0.0;
+        const double v = i < n_kc ? s_kc[pb][i] : 0.0;
         kc += v;
         kc_mask |= v > 0.0 ? 1 << i : 0;
       }
@@ -902,10 +913,10 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
     bool live[kMaxRects];
 #pragma unroll
     for (int r = 0; r < kMaxRects; ++r) {
-      const int x0 = __builtin_amdgcn_readfirstlane(s_rect[w][r][0]);
-      const int x1 = __builtin_amdgcn_readfirstlane(s_rect[w][r][1]);
-      const int y0 = __builtin_amdgcn_readfirstlane(s_rect[w][r][2]);
-      const int y1 = __builtin_amdgcn_readfirstlane(s_rect[w][r][3]);
+      const int x0 = __builtin_amdgcn_readfirstlane(s_rect[pb][r][0]);
+      const int x1 = __builtin_amdgcn_readfirstlane(s_rect[pb][r][1]);
+      const int y0 = __builtin_amdgcn_readfirstlane(s_rect[pb][r][2]);
+      const int y1 = __builtin_amdgcn_readfirstlane(s_rect[pb][r][3]);
       live[r] = valid && x0 <= x1;
       R[r] = make_int4(x0 / kTile, y0 / kTile, x1 / kTile, y1 / kTile);
     }
@@ -2038,8 +2049,12 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
   switch (stage) {
     case kStageFk:
       if (a.src) break;   // the kinematics of the previous evaluation are reused
-      hipLaunchKernelGGL(fk_kernel, dim3((n_total + kWavesPerBlock - 1) / kWavesPerBlock),
-                         dim3(kBlock), 0, s, a, ws);
+      if (a.n_prim > kWave)
+        hipLaunchKernelGGL(fk_kernel<2>, dim3((n_total + kWavesPerBlock / 2 - 1) / (kWavesPerBlock / 2)),
+                           dim3(kBlock), 0, s, a, ws);
+      else
+        hipLaunchKernelGGL(fk_kernel<1>, dim3((n_total + kWavesPerBlock - 1) / kWavesPerBlock),
+                           dim3(kBlock), 0, s, a, ws);
       break;
     case kStageSched:
       if (n_total <= kSchedSmall)
