@@ -165,7 +165,8 @@ ht_status ht_preprocess_rgbd(ht_ctx* ctx, int W, int H, const uint8_t* rgb,
 ht_status ht_reserve(ht_ctx* ctx, int max_particles, int max_pixels);
 
 /* Optional per-pixel outputs of ht_eval_particles for a single frame (n_frames == 1); each
- * pointer may be NULL.  Device memory, [n_particles][H][W].  `slot` must repeat, on the host,
+ * pointer may be NULL.  Device memory, [n_particles][H][W].  Pixels of tiles that no primitive
+ * reaches keep the background (r_d = B or 0, no hit, winner -1, margin -inf).  `slot` must repeat, on the host,
  * the observation slot held in frame_slots[0] (it gives W, H and B for the images). */
 typedef struct {
   int32_t slot;
@@ -173,6 +174,12 @@ typedef struct {
   uint8_t* hit;      /* model hit (nearest entry in front of B)      */
   uint8_t* rm;       /* r_m of Eq. 4                                 */
   int32_t* winner;   /* index of the nearest primitive, -1 on a miss */
+  float* margin;     /* ray-surface margin (dimensionless, > 0 inside the silhouette): of the
+                        primitive with the nearest entry; where no primitive is entered, the
+                        largest over the primitives tested at the pixel (-inf if none was).
+                        Sphere (r^2 - rho^2) / r^2, ellipsoid 1 - rho'^2, closed cylinders and
+                        cones the largest of their side's and caps' slacks (radial and axial),
+                        in FP32; a pixel within 1e-5 of 0 is decided by rounding. */
 } ht_debug;
 
 /* E(h, O) (Eq. 5) for n_frames x n_particles poses.  frame_slots: device int32 [n_frames],

@@ -43,7 +43,7 @@ class Camera(C.Structure):
 
 class Debug(C.Structure):
     _fields_ = [("slot", C.c_int32), ("depth", C.c_void_p), ("hit", C.c_void_p),
-                ("rm", C.c_void_p), ("winner", C.c_void_p)]
+                ("rm", C.c_void_p), ("winner", C.c_void_p), ("margin", C.c_void_p)]
 
 
 class Swarm(C.Structure):
@@ -273,10 +273,11 @@ class Context:
             if F != 1 or slot not in self.slots:
                 raise ValueError("debug images need one frame whose slot is set")
             W, H, _ = self.slots[slot]
-            for k, dt in (("depth", torch.float32), ("hit", torch.uint8), ("rm", torch.uint8),
-                          ("winner", torch.int32)):
+            keys = ("depth", "hit", "rm", "winner", "margin")
+            for k, dt in zip(keys, (torch.float32, torch.uint8, torch.uint8, torch.int32,
+                                    torch.float32)):
                 _dev(debug.get(k), dt, (P, H, W), "debug " + k)
-            dbg = Debug(slot, *[_ptr(debug.get(k)) for k in ("depth", "hit", "rm", "winner")])
+            dbg = Debug(slot, *[_ptr(debug.get(k)) for k in keys])
         _check(self.lib.ht_eval_particles(self.handle, F, _ptr(frame_slots), P, _ptr(p3),
                                           _ptr(cost), C.byref(dbg) if dbg else None, _stream()))
         return cost[0] if squeeze else cost

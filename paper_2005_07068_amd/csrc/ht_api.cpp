@@ -365,7 +365,7 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.cull = c->lc.cull;
   const long long bound = (long long)n_total *
                           ((c->max_tiles() + kMinTilesPerItem - 1) / kMinTilesPerItem);
-  const bool dbg_on = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner;
+  const bool dbg_on = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner || a.dbg.margin;
   const bool all_types = (c->tmask.m[HT_CONE][0] | c->tmask.m[HT_CONE][1] |
                           c->tmask.m[HT_ECYLINDER][0] | c->tmask.m[HT_ECYLINDER][1]) != 0ull;
   const int gpc = std::min(c->lc.groups_per_cu,
@@ -711,7 +711,7 @@ ht_status ht_eval_particles(ht_ctx* c, int n_frames, const int32_t* frame_slots,
   if (n_frames * n_particles == 0) return HT_OK;
   if (!frame_slots || !poses || !cost) return fail(HT_ERR_ARG, "NULL device pointer");
   if ((st = check_slots_set(c)) != HT_OK) return st;
-  if (dbg && (dbg->depth || dbg->hit || dbg->rm || dbg->winner)) {
+  if (dbg && (dbg->depth || dbg->hit || dbg->rm || dbg->winner || dbg->margin)) {
     if (n_frames != 1) return fail(HT_ERR_UNSUPPORTED, "debug images need n_frames == 1");
     if (dbg->slot < 0 || dbg->slot >= HT_MAX_SLOTS || !c->slots[dbg->slot].set)
       return fail(HT_ERR_STATE, "debug slot %d is not set", dbg->slot);

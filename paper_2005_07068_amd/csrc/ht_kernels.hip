@@ -981,6 +981,7 @@ __global__ __launch_bounds__(kBlock) void debug_fill_kernel(ht_debug dbg, size_t
   if (dbg.hit) dbg.hit[i] = 0;
   if (dbg.rm) dbg.rm[i] = 0;
   if (dbg.winner) dbg.winner[i] = -1;
+  if (dbg.margin) dbg.margin[i] = -INFINITY;
 }
 
 // ------------------------------------------------------------------------------------
@@ -996,9 +997,24 @@ struct Hit {
   bool ok;
   float nx, ny, nz;   // outward normal direction at the entry (unnormalised)
   float rx, ry, rz;   // entry point minus the primitive reference point
+  float m;            // ray-surface margin (debug images only, MRG)
 };
 
-template <bool GRAD>
+// Margin of a capped side and its two caps (the survey's rule, as the oracle computes it): a
+// side root's slack is the least of the radial slack and the axial slacks s/L, (L - s)/L at the
+// root (the radial slack alone when the ray misses the side); a cap's slack is its disc's
+// radial slack at the cap point; the margin is the largest of the four.  radial: the side's
+// radial slack; s_a, s_b: axial coordinates of the two side roots; cap0, cap1: the caps'.
+__device__ __forceinline__ float capped_margin(float radial, bool side_hit, float s_a, float s_b,
+                                               float L, float cap0, float cap1) {
+  const float iL = 1.0f / L;
+  const float sa = fminf(radial, fminf(s_a * iL, (L - s_a) * iL));
+  const float sb = fminf(radial, fminf(s_b * iL, (L - s_b) * iL));
+  const float side = side_hit ? fmaxf(sa, sb) : radial;
+  return fmaxf(fmaxf(side, cap0), cap1);
+}
+
+template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void sphere_test(const float* r, float dx, float dy, float dz,
                                             float inv_dd, Hit& h) {
   const float b = fmaf(dx, r[0], fmaf(dy, r[1], dz * r[2]));
@@ -1011,6 +1027,7 @@ __device__ __forceinline__ void sphere_test(const float* r, float dx, float dy, 
   h.ok = h2 >= 0.0f;
   const float hs = fast_sqrt(fmaxf(h2, 0.0f) * inv_dd);
   h.t = t0 - hs;
+  if (MRG) h.m = h2 / r[3];
   if (GRAD) {
     h.rx = fmaf(-hs, dx, vx);
     h.ry = fmaf(-hs, dy, vy);
@@ -1021,7 +1038,7 @@ __device__ __forceinline__ void sphere_test(const float* r, float dx, float dy, 
   }
 }
 
-template <bool GRAD>
+template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void ellipsoid_test(const float* r, float dx, float dy, float dz,
                                                Hit& h) {
   const float q00 = r[3], q01 = r[7], q02 = r[8], q11 = r[9], q12 = r[10], q22 = r[11];
@@ -1045,6 +1062,7 @@ __device__ __forceinline__ void ellipsoid_test(const float* r, float dx, float d
   h.ok = m >= 0.0f;
   const float tin = cc - fast_sqrt(fmaxf(m, 0.0f) * inv);
   h.t = t0 + tin;
+  if (MRG) h.m = m;
   if (GRAD) {
     h.rx = fmaf(tin, dx, vx);
     h.ry = fmaf(tin, dy, vy);
@@ -1058,7 +1076,7 @@ __device__ __forceinline__ void ellipsoid_test(const float* r, float dx, float d
 // Closed cylinder as the intersection of the infinite cylinder and the slab 0 <= s <= L:
 // both intervals are expressed as offsets from the reference parameter t_r (the closest
 // approach to the axis), so the hit test compares small accurate numbers.
-template <bool GRAD>
+template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy, float dz,
                                               float dd, Hit& h) {
   const float ux = r[8], uy = r[9], uz = r[10], L = r[7];
@@ -1095,6 +1113,19 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   const float tin = fmaxf(cc - hs, din), tout = fminf(cc + hs, dout);
   h.ok = (h2 >= 0.0f) & (tin <= tout);
   h.t = tr + tin;
+  if (MRG) {
+    // offsets tau from t_r: radius^2 at tau is rho2 + 2 tau B + tau^2 A, axial s = a3 + tau da
+    const float ir2 = 1.0f / r[3];
+    const float hsf = fast_sqrt(fmaxf(h2, 0.0f) * invA);
+    const float sa = fmaf(cc - hsf, da, a3), sb = fmaf(cc + hsf, da, a3);
+    const float c0 = -a3 * inv_da, c1 = (L - a3) * inv_da;
+    const float q0 = fmaf(c0, fmaf(c0, A, 2.0f * B), rho2);
+    const float q1 = fmaf(c1, fmaf(c1, A, 2.0f * B), rho2);
+    const bool axial = da != 0.0f;
+    h.m = capped_margin(par ? -INFINITY : h2 * ir2, !par && h2 >= 0.0f, sa, sb, L,
+                        axial ? (r[3] - q0) * ir2 : -INFINITY,
+                        axial ? (r[3] - q1) * ir2 : -INFINITY);
+  }
   if (GRAD) {
     // entry point relative to p0 and the outward normal of the entry surface
     const bool cap = din > cc - hs;
@@ -1117,7 +1148,7 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
 // for alpha < 0 (a ray steeper than the cone's flank) they are the two rays outside the roots,
 // of which the slab meets at most one (the solid is convex).  The roots come from
 // q = -(beta + sign(beta) sqrt(disc)), tau = q / alpha and gamma / q, finite as alpha -> 0.
-template <bool GRAD>
+template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void cone_test(const float* r, float dx, float dy, float dz,
                                           float dd, Hit& h) {
   const float ux = r[8], uy = r[9], uz = r[10], L = r[7], r0 = r[3], k = r[11];
@@ -1166,6 +1197,24 @@ __device__ __forceinline__ void cone_test(const float* r, float dx, float dy, fl
     h.ok = first ? (din <= dout) : (t2 <= dout);
   }
   h.t = tr + tin;
+  if (MRG) {
+    // the oracle's cone margin: disc / (|alpha| r_max^2) for the side (slack at each root the
+    // least of it and the axial slacks), the caps' disc slacks with their own radii
+    const float r1 = fmaf(k, L, r0), rmax2 = fmaxf(r0 * r0, r1 * r1);
+    const float dsl = alpha != 0.0f ? disc / (fabsf(alpha) * rmax2) : INFINITY;
+    const float s_a = fmaf(ra, da, a3), s_b = fmaf(rb, da, a3);
+    const float c0 = -a3 * inv_da, c1 = (L - a3) * inv_da;
+    const float q0 = fmaf(c0, fmaf(c0, A, 2.0f * B), rho2);
+    const float q1 = fmaf(c1, fmaf(c1, A, 2.0f * B), rho2);
+    const bool axial = da != 0.0f;
+    const float iL = 1.0f / L;
+    const bool fa = isfinite(ra), fb = isfinite(rb);
+    const float sla = fa ? fminf(dsl, fminf(s_a * iL, (L - s_a) * iL)) : -INFINITY;
+    const float slb = fb ? fminf(dsl, fminf(s_b * iL, (L - s_b) * iL)) : -INFINITY;
+    const float side = has ? fmaxf(sla, slb) : ((fa || fb) ? dsl : -INFINITY);
+    h.m = fmaxf(fmaxf(side, axial ? (r0 * r0 - q0) / (r0 * r0) : -INFINITY),
+                axial ? (r1 * r1 - q1) / (r1 * r1) : -INFINITY);
+  }
   if (GRAD) {
     h.rx = fmaf(tin, dx, vx);
     h.ry = fmaf(tin, dy, vy);
@@ -1182,7 +1231,7 @@ __device__ __forceinline__ void cone_test(const float* r, float dx, float dy, fl
 // Closed elliptic cylinder: the side is x^T Q x <= 1 for the offset x from the first cap
 // centre (Q = ex ex^T / a^2 + ey ey^T / b^2, Q u = 0), intersected with the slab 0 <= s <= L.
 // The reference parameter is the closest approach to the axis in the Q metric.
-template <bool GRAD>
+template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void ecylinder_test(const float* r, float dx, float dy, float dz,
                                                float dd, Hit& h) {
   const float q00 = r[3], q01 = r[7], q02 = r[8], q11 = r[9], q12 = r[10], q22 = r[11];
@@ -1216,6 +1265,18 @@ __device__ __forceinline__ void ecylinder_test(const float* r, float dx, float d
   const float tin = fmaxf(cc - hs, din), tout = fminf(cc + hs, dout);
   h.ok = (m >= 0.0f) & (tin <= tout);
   h.t = tr + tin;
+  if (MRG) {
+    // in the unit-radius frame of the Q metric: radius^2 at offset tau is
+    // vQv + 2 tau B + tau^2 dQd
+    const float hsf = fast_sqrt(fmaxf(m, 0.0f) * inv);
+    const float sa = fmaf(cc - hsf, da, a3), sb = fmaf(cc + hsf, da, a3);
+    const float c0 = -a3 * inv_da, c1 = (L - a3) * inv_da;
+    const float q0 = fmaf(c0, fmaf(c0, dqd, 2.0f * B), vqv);
+    const float q1 = fmaf(c1, fmaf(c1, dqd, 2.0f * B), vqv);
+    const bool axial = da != 0.0f;
+    h.m = capped_margin(par ? -INFINITY : m, !par && m >= 0.0f, sa, sb, L,
+                        axial ? 1.0f - q0 : -INFINITY, axial ? 1.0f - q1 : -INFINITY);
+  }
   if (GRAD) {
     const bool cap = din > cc - hs;
     h.rx = fmaf(tin, dx, vx);
@@ -1466,6 +1527,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       float tmin = INFINITY;
       int win = -1;   // tracked for the gradient and the debug images only
       float wnx = 0, wny = 0, wnz = 0, wrx = 0, wry = 0, wrz = 0;
+      float wm = -INFINITY, mmax = -INFINITY;   // margins (debug images only)
 
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
@@ -1477,17 +1539,22 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
             m &= m - 1;
             const float* r = recs + k * kRec;
             Hit h;
-            if (typ == HT_SPHERE) sphere_test<GRAD>(r, dx, dy, dz, inv_dd, h);
-            else if (typ == HT_CYLINDER) cylinder_test<GRAD>(r, dx, dy, dz, dd, h);
-            else if (typ == HT_ELLIPSOID) ellipsoid_test<GRAD>(r, dx, dy, dz, h);
-            else if (typ == HT_CONE) cone_test<GRAD>(r, dx, dy, dz, dd, h);
-            else ecylinder_test<GRAD>(r, dx, dy, dz, dd, h);
+            if (typ == HT_SPHERE) sphere_test<GRAD, DEBUG>(r, dx, dy, dz, inv_dd, h);
+            else if (typ == HT_CYLINDER) cylinder_test<GRAD, DEBUG>(r, dx, dy, dz, dd, h);
+            else if (typ == HT_ELLIPSOID) ellipsoid_test<GRAD, DEBUG>(r, dx, dy, dz, h);
+            else if (typ == HT_CONE) cone_test<GRAD, DEBUG>(r, dx, dy, dz, dd, h);
+            else ecylinder_test<GRAD, DEBUG>(r, dx, dy, dz, dd, h);
             // nearest entry in front of the camera: as unsigned integers the bit patterns of
             // non-negative floats keep their order and negative ones (entries behind the
             // camera) exceed +inf; exact ties keep the first tested (branch-free selects)
             const bool take = h.ok & (__float_as_uint(h.t) < __float_as_uint(tmin));
             tmin = take ? h.t : tmin;
             if (GRAD || DEBUG) win = take ? k : win;
+            if (DEBUG) {
+              // the nearest primitive's margin, and the largest of the tested ones (misses)
+              wm = take ? h.m : wm;
+              mmax = fmaxf(mmax, h.m);
+            }
             if (GRAD) {
               wnx = take ? h.nx : wnx;
               wny = take ? h.ny : wny;
@@ -1531,6 +1598,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
         if (a.dbg.hit) a.dbg.hit[pix] = hit ? 1 : 0;
         if (a.dbg.rm) a.dbg.rm[pix] = rm ? 1 : 0;
         if (a.dbg.winner) a.dbg.winner[pix] = win;
+        if (a.dbg.margin) a.dbg.margin[pix] = any ? wm : mmax;
       }
       if (GRAD) {
         // adjoint: coefficient of the depth term, then the per-segment wrench
@@ -2045,7 +2113,7 @@ int raycast_groups_per_cu(bool grad, bool dbg, bool all_types) {
 hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s) {
   const int n_total = a.n_frames * a.n_particles;
   if (n_total == 0) return hipSuccess;
-  const bool dbg = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner;
+  const bool dbg = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner || a.dbg.margin;
   switch (stage) {
     case kStageFk:
       if (a.src) break;   // the kinematics of the previous evaluation are reused

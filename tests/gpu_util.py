@@ -12,6 +12,7 @@ from workload import WORKLOADS, make_hand_model, seed_sequence
 from workload.handmodel import perturbed_particles
 
 MARGIN_TAU = 1e-5          # pixels whose ray-surface margin is below this are ambiguous
+MARGIN_ATOL = 1e-4         # FP32 evaluation of the margin in the debug images
 DEPTH_TOL_MM = 1e-3
 COST_RTOL = 1e-5
 RM_AMBIG_MM = 1e-3         # | |o_d - r_d| - d_m | below this: r_m decided by float rounding
@@ -60,7 +61,8 @@ def eval_debug(ctx, poses, slot, W, H):
            "depth": torch.empty((P, H, W), device=dev, dtype=torch.float32),
            "hit": torch.empty((P, H, W), device=dev, dtype=torch.uint8),
            "rm": torch.empty((P, H, W), device=dev, dtype=torch.uint8),
-           "winner": torch.empty((P, H, W), device=dev, dtype=torch.int32)}
+           "winner": torch.empty((P, H, W), device=dev, dtype=torch.int32),
+           "margin": torch.empty((P, H, W), device=dev, dtype=torch.float32)}
     slots = torch.tensor([slot], dtype=torch.int32, device=dev)
     p = torch.tensor(np.asarray(poses, np.float32), device=dev)
     cost = ctx.eval(p, slots, debug=dbg)
@@ -119,6 +121,19 @@ def check_particle(model, fr, pose, gpu_cost, gdbg, i, depth_rounding_atol=False
         f"particle {i}: depth error {derr.max():.3e} mm on robust pixels"
     miss = cls["robust_miss"]
     assert np.all(g_depth[miss] == res["depth"][miss])
+    # the margin of the debug images: the winner's on robust hits (FP32 evaluation of the
+    # oracle's definition), at most the robust-miss bound elsewhere
+    if "margin" in gdbg:
+        g_m = gdbg["margin"][i].astype(np.float64)
+        # the GPU's nearest primitive (two entries within rounding of each other may order
+        # differently from the oracle's)
+        win = gdbg["winner"][i]
+        yy, xx = np.nonzero(rob & (win >= 0))
+        m_ref = res["prim_margin"][win[yy, xx], yy, xx]
+        merr = np.abs(g_m[yy, xx] - m_ref)
+        assert merr.size == 0 or merr.max() <= MARGIN_ATOL, \
+            f"particle {i}: margin error {merr.max():.3e} on robust pixels"
+        assert np.all(g_m[miss] < MARGIN_TAU), f"particle {i}: positive margin at a miss"
     # r_m exact where neither the hit nor the d_m test is decided by rounding
     o_d = fr["depth"].astype(np.float64)
     t_d, r_m, _, _ = ocost.pixel_terms(o_d, fr["skin"], res["depth"], res["hit"])
