@@ -368,8 +368,12 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   const bool dbg_on = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner || a.dbg.margin;
   const bool all_types = (c->tmask.m[HT_CONE][0] | c->tmask.m[HT_CONE][1] |
                           c->tmask.m[HT_ECYLINDER][0] | c->tmask.m[HT_ECYLINDER][1]) != 0ull;
+  // launches of at most kSelfSchedMax particles without debug images build their work list
+  // in the ray cast (no work-list launch)
+  a.self_sched = n_total <= ht::kSelfSchedMax && !dbg_on ? 1 : 0;
   const int gpc = std::min(c->lc.groups_per_cu,
-                           ht::raycast_groups_per_cu(grad != nullptr, dbg_on, all_types));
+                           ht::raycast_groups_per_cu(grad != nullptr, dbg_on, all_types,
+                                                     a.self_sched != 0));
   a.grid = (int)std::max<long long>(1, std::min<long long>((long long)c->n_cu * gpc, bound));
   a.n_prim = c->n_prim;
   a.n_seg = c->n_seg;
@@ -380,6 +384,7 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   for (int stage = 0; stage < kNumStages; ++stage) {
     if (stage == kStageFk && src) continue;   // reused from the previous evaluation
     if (stage == kStageFinalize && !assemble) continue;   // assembled by the next kernel
+    if (stage == kStageSched && a.self_sched) continue;   // built by the ray cast
     if (fixed)
       HT_HIP(launch_eval_stage(stage, a, ws, s));
     else

@@ -151,6 +151,8 @@ struct EvalArgs {
   int tiles_per_item;
   int cull;                    // 1: screen boxes clipped to the bounding capsule's image extent
   int grid;                    // persistent workgroups
+  int self_sched;              // 1: the ray cast builds the work list (at most kSelfSchedMax
+                               // particles, no debug images)
   int n_prim, n_seg, n_dof;
 };
 
@@ -159,8 +161,9 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
                                    int TW, int TH, uint32_t* words, float* tile_td,
                                    int* tile_skin, double* totals, float bg, hipStream_t s);
 enum { kStageFk = 0, kStageSched = 1, kStageRaycast = 2, kStageFinalize = 3, kNumStages = 4 };
+constexpr int kSelfSchedMax = 256;   // launches of at most this many particles self-schedule
 hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s);
-int raycast_groups_per_cu(bool grad, bool dbg, bool all_types);
+int raycast_groups_per_cu(bool grad, bool dbg, bool all_types, bool self_sched);
 hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s);
 int preprocess_partials(int W, int H);
 hipError_t launch_preprocess(int W, int H, const uint8_t* rgb, const uint16_t* depth,

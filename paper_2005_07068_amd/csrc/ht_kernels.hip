@@ -1395,11 +1395,72 @@ __device__ __forceinline__ int xcd_major_item(int b, int G) {
   return x * q + min(x, rem) + j;
 }
 
+// Launches of at most kSelfSched particles build their work list in every ray-cast workgroup
+// (no work-list launch before them): one thread per particle reads its tile count, two block
+// scans give the item size (the work-list kernel's rule) and the item offsets in LDS, and the
+// workgroups take items in a static stride of the grid size (the items are sized to about
+// one per workgroup, so there is nothing to balance dynamically).  Workgroup 0 stores the
+// offsets for the finalize and refinement kernels and adds the launch's evaluations to the
+// counts.
+constexpr int kSelfSched = kBlock;
+static_assert(kSelfSched == kSelfSchedMax, "one thread per particle of a self-scheduled launch");
+
+__device__ void self_schedule(const EvalArgs& a, const Workspace& ws, int* s_off, int& total,
+                              int& tpi, bool& interleave) {
+  __shared__ int2 s_sum2[kWavesPerBlock];
+  __shared__ int s_sum[kWavesPerBlock];
+  const int n_total = a.n_frames * a.n_particles;
+  const int t = threadIdx.x;
+  const int v = t < n_total ? ws.tiles[src_of(a, min(t, n_total - 1))] : -1;
+  int total_tiles, total_evaluated;
+  block_scan2<kWavesPerBlock>(s_sum2, max(v, 0), v >= 0 ? 1 : 0, &total_tiles,
+                              &total_evaluated);
+  const long long target = (long long)a.grid * kItemsPerGroup;
+  long long tq = ((long long)total_tiles + target - 1) / target;
+  tq = (tq + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
+  const long long lo = a.grad ? (long long)kFloorTilesGrad : (long long)kFloorTilesFwd;
+  tpi = (int)max(min(lo, (long long)a.tiles_per_item), min(tq, (long long)a.tiles_per_item));
+  const int items = (max(v, 0) + tpi - 1) / tpi;
+  int total_items;
+  const int incl = block_scan<kWavesPerBlock>(s_sum, items, &total_items);
+  if (t < n_total) s_off[t + 1] = incl;
+  if (t == 0) s_off[0] = 0;
+  __syncthreads();
+  total = total_items;
+  interleave = a.grad && total_items <= 2 * a.grid;
+  if (blockIdx.x == 0) {
+    // n_total + 1 offsets: one per thread, the end offset by thread 0
+    if (t < n_total) ws.item_off[t] = s_off[t];
+    if (t == 0) {
+      ws.item_off[n_total] = total_items;
+      if (a.eval_count)
+        atomicAdd(&a.eval_count[a.grad ? 1 : 0], (unsigned long long)total_evaluated);
+      ws.counters[1] = total_items;
+      ws.counters[2] = tpi;
+      ws.counters[3] = interleave ? 1 : 0;
+    }
+  }
+}
+
+// The evaluated particle r of item i in a self-scheduled launch: s_off[r] <= i < s_off[r + 1]
+// (a binary search over the LDS offsets; wave-uniform).
+__device__ __forceinline__ int self_item_particle(const int* s_off, int n_total, int i) {
+  int lo = 0, hi = n_total;   // s_off[lo] <= i < s_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (uni(s_off[mid]) <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // NT: primitive types the model uses (3: spheres, cylinders, ellipsoids; kNumTypes: also
 // cones and elliptic cylinders), so a model without the latter keeps the smaller register
 // footprint.  (Forcing more wavefronts per SIMD than the natural register count allows
-// spills registers and measured slower.)
-template <bool GRAD, bool DEBUG, int NT>
+// spills registers and measured slower.)  SELF: the launch builds its own work list (at most
+// kSelfSched particles, no debug images); a variant of its own, so the larger launches keep
+// the dequeue loop without the self-scheduling code (which cost them about 5%).
+template <bool GRAD, bool DEBUG, int NT, bool SELF>
 __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace ws,
                                                       TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
@@ -1415,9 +1476,19 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   const int n_prim = a.n_prim, n_seg = a.n_seg;
-  const int total = uni(ws.counters[1]);
-  const int tpi = uni(ws.counters[2]);
-  const bool interleave = uni(ws.counters[3]) != 0;
+  static_assert(!(SELF && DEBUG), "debug launches take the work-list kernel");
+  constexpr bool self = SELF;
+  __shared__ int s_off[SELF ? kSelfSched + 1 : 1];
+  int total, tpi;
+  bool interleave;
+  if constexpr (SELF) {
+    self_schedule(a, ws, s_off, total, tpi, interleave);
+  } else {
+    total = uni(ws.counters[1]);
+    tpi = uni(ws.counters[2]);
+    interleave = uni(ws.counters[3]) != 0;
+  }
+  const int n_eval = a.n_frames * a.n_particles;
   int cur_p = -1;
   FrameSlot fs{};
   const PInfo& pi = s_pi;
@@ -1426,11 +1497,13 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
   // counter (offset by the grid size), so the launch does not start with one atomic per
   // workgroup on a single address (which stalls the memory channel that holds it)
   bool first = true;
+  int item = 0;
   for (;;) {
-    int item;
     if (first) {
       item = xcd_major_item(blockIdx.x, gridDim.x);
       first = false;
+    } else if constexpr (SELF) {
+      item += gridDim.x;
     } else {
       if (tid == 0) s_item = (int)gridDim.x + atomicAdd(&ws.counters[0], 1);
       __syncthreads();
@@ -1438,7 +1511,8 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       __syncthreads();
     }
     if (item >= total) break;
-    const int r = uni(ws.item_map[item]);     // evaluated particle
+    // evaluated particle
+    const int r = self ? self_item_particle(s_off, n_eval, item) : uni(ws.item_map[item]);
     const int p = a.src ? uni(src_of(a, r)) : r;   // the workspace particle of its kinematics
     if (p != cur_p) {
       const float4* src = reinterpret_cast<const float4*>(ws.recs + (size_t)p * n_prim * kRec);
@@ -1462,9 +1536,9 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
     // and carries about equal work (runs of consecutive tiles differed threefold, and a launch
     // with about one item per workgroup lasts as long as its longest item); wavefront w takes
     // every fourth of an item's tiles
-    const int off = uni(ws.item_off[r]);
+    const int off = self ? uni(s_off[r]) : uni(ws.item_off[r]);
     const int c = item - off;
-    const int n_it = uni(ws.item_off[r + 1]) - off;
+    const int n_it = (self ? uni(s_off[r + 1]) : uni(ws.item_off[r + 1])) - off;
     const int n_tiles = uni(pi.n_tiles);
     const int first = interleave ? c : c * tpi;
     const int gap = interleave ? n_it : 1;
@@ -2083,22 +2157,27 @@ hipError_t launch_refine_update(const EvalArgs& a, const Workspace& ws, const Re
 // LDS decide).  The persistent grid is capped at this many per CU: a workgroup beyond it
 // starts only when another has finished, and its statically assigned first item then
 // finishes late (a 128-particle launch spent half its time in that tail).
-int raycast_groups_per_cu(bool grad, bool dbg, bool all_types) {
-  static int cache[2][2][2] = {};
-  int& n = cache[grad][dbg][all_types];
+// The ray-cast variant of a launch.
+template <bool GRAD, int NT>
+static const void* raycast_fn_nt(bool dbg, bool self) {
+  if (dbg) return reinterpret_cast<const void*>(&raycast_kernel<GRAD, true, NT, false>);
+  return self ? reinterpret_cast<const void*>(&raycast_kernel<GRAD, false, NT, true>)
+              : reinterpret_cast<const void*>(&raycast_kernel<GRAD, false, NT, false>);
+}
+
+static const void* raycast_fn(bool grad, bool dbg, bool all_types, bool self) {
+  if (all_types)
+    return grad ? raycast_fn_nt<true, kNumTypes>(dbg, self)
+                : raycast_fn_nt<false, kNumTypes>(dbg, self);
+  return grad ? raycast_fn_nt<true, 3>(dbg, self) : raycast_fn_nt<false, 3>(dbg, self);
+}
+
+int raycast_groups_per_cu(bool grad, bool dbg, bool all_types, bool self) {
+  self = self && !dbg;
+  static int cache[2][2][2][2] = {};
+  int& n = cache[grad][dbg][all_types][self];
   if (n > 0) return n;
-  const void* f;
-  if (all_types) {
-    f = grad ? (dbg ? reinterpret_cast<const void*>(&raycast_kernel<true, true, kNumTypes>)
-                    : reinterpret_cast<const void*>(&raycast_kernel<true, false, kNumTypes>))
-             : (dbg ? reinterpret_cast<const void*>(&raycast_kernel<false, true, kNumTypes>)
-                    : reinterpret_cast<const void*>(&raycast_kernel<false, false, kNumTypes>));
-  } else {
-    f = grad ? (dbg ? reinterpret_cast<const void*>(&raycast_kernel<true, true, 3>)
-                    : reinterpret_cast<const void*>(&raycast_kernel<true, false, 3>))
-             : (dbg ? reinterpret_cast<const void*>(&raycast_kernel<false, true, 3>)
-                    : reinterpret_cast<const void*>(&raycast_kernel<false, false, 3>));
-  }
+  const void* f = raycast_fn(grad, dbg, all_types, self);
   int r = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, f, kBlock, 0) != hipSuccess || r < 1) {
     (void)hipGetLastError();
@@ -2125,6 +2204,7 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
                            dim3(kBlock), 0, s, a, ws);
       break;
     case kStageSched:
+      if (a.self_sched) return hipErrorInvalidValue;   // the ray cast builds its work list
       if (n_total <= kSchedSmall)
         hipLaunchKernelGGL(sched_kernel<kSchedSmall>, dim3(1), dim3(kSchedSmall), 0, s, a, ws);
       else
@@ -2137,27 +2217,15 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
       break;
     case kStageRaycast: {
       const TypeMasks tm = a.type_masks;
-      const dim3 grid(a.grid), block(kBlock);
       const bool all = (tm.m[HT_CONE][0] | tm.m[HT_CONE][1] | tm.m[HT_ECYLINDER][0] |
                         tm.m[HT_ECYLINDER][1]) != 0ull;
-      if (all) {
-        if (a.grad) {
-          if (dbg) hipLaunchKernelGGL((raycast_kernel<true, true, kNumTypes>), grid, block, 0, s, a, ws, tm);
-          else hipLaunchKernelGGL((raycast_kernel<true, false, kNumTypes>), grid, block, 0, s, a, ws, tm);
-        } else {
-          if (dbg) hipLaunchKernelGGL((raycast_kernel<false, true, kNumTypes>), grid, block, 0, s, a, ws, tm);
-          else hipLaunchKernelGGL((raycast_kernel<false, false, kNumTypes>), grid, block, 0, s, a, ws, tm);
-        }
-      } else {
-        if (a.grad) {
-          if (dbg) hipLaunchKernelGGL((raycast_kernel<true, true, 3>), grid, block, 0, s, a, ws, tm);
-          else hipLaunchKernelGGL((raycast_kernel<true, false, 3>), grid, block, 0, s, a, ws, tm);
-        } else {
-          if (dbg) hipLaunchKernelGGL((raycast_kernel<false, true, 3>), grid, block, 0, s, a, ws, tm);
-          else hipLaunchKernelGGL((raycast_kernel<false, false, 3>), grid, block, 0, s, a, ws, tm);
-        }
-      }
-      break;
+      if (a.self_sched && (dbg || n_total > kSelfSched)) return hipErrorInvalidValue;
+      const void* f = raycast_fn(a.grad != nullptr, dbg, all, a.self_sched != 0);
+      EvalArgs ka = a;
+      Workspace kw = ws;
+      TypeMasks kt = tm;
+      void* args[] = {&ka, &kw, &kt};
+      return hipLaunchKernel(f, dim3(a.grid), dim3(kBlock), args, 0, s);
     }
     case kStageFinalize:
       if (a.grad)

@@ -277,12 +277,14 @@ def test_kernel_tracing_counts_one_refined_generation():
     st = ctx.profile_end()
     ctx.close()
     launches = {k: v["launches"] for k, v in st.items()}
-    assert launches == {"fk": 3, "sched": 4, "raycast": 2, "raycast_grad": 2, "finalize": 1,
+    # every evaluation here has at most 256 particles, so the ray casts build their own work
+    # lists (no work-list launch)
+    assert launches == {"fk": 3, "sched": 0, "raycast": 2, "raycast_grad": 2, "finalize": 1,
                         "pso": 1, "refine": 4}, launches
     assert st["fk"]["particles"] == 64 + 2 * 32
     assert st["raycast_grad"]["particles"] == 8 + 32
     assert st["raycast"]["particles"] == 64 + 32
-    assert all(v["ms"] > 0.0 for v in st.values())
+    assert all(v["ms"] > 0.0 for v in st.values() if v["launches"])
 
 
 def test_refinement_matches_the_oracle_step_by_step():
