@@ -20,7 +20,7 @@ constexpr int kNumTypes = 5;        // HT_SPHERE .. HT_ECYLINDER
 // aims at kFloorTilesFwd / kFloorTilesGrad at least, capped by the configured value.
 constexpr int kMinTilesPerItem = 4;
 constexpr int kFloorTilesFwd = 8;
-constexpr int kFloorTilesGrad = 16;
+constexpr int kFloorTilesGrad = 8;  // 16 left a 32-particle gradient launch at 22.5 us (19.2)
 constexpr float kDMatch = 10.0f;    // d_m, mm
 constexpr float kDClamp = 40.0f;    // d_M, mm
 constexpr double kLambda = 20.0;

@@ -2153,10 +2153,6 @@ hipError_t launch_refine_update(const EvalArgs& a, const Workspace& ws, const Re
 
 // ------------------------------------------------------------------------------------
 
-// Workgroups of a ray-cast variant that are resident on one CU at once (its registers and
-// LDS decide).  The persistent grid is capped at this many per CU: a workgroup beyond it
-// starts only when another has finished, and its statically assigned first item then
-// finishes late (a 128-particle launch spent half its time in that tail).
 // The ray-cast variant of a launch.
 template <bool GRAD, int NT>
 static const void* raycast_fn_nt(bool dbg, bool self) {
@@ -2172,6 +2168,10 @@ static const void* raycast_fn(bool grad, bool dbg, bool all_types, bool self) {
   return grad ? raycast_fn_nt<true, 3>(dbg, self) : raycast_fn_nt<false, 3>(dbg, self);
 }
 
+// Workgroups of a ray-cast variant that are resident on one CU at once (its registers and
+// LDS decide).  The persistent grid is capped at this many per CU: a workgroup beyond it
+// starts only when another has finished, and its statically assigned first item then
+// finishes late (a 128-particle launch spent half its time in that tail).
 int raycast_groups_per_cu(bool grad, bool dbg, bool all_types, bool self) {
   self = self && !dbg;
   static int cache[2][2][2][2] = {};
