@@ -37,9 +37,9 @@ METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at 
 # FP32 operations (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes).  Keyed by the SHA-256 of the kernel
 # sources they were measured on: any later change of the kernel reports null.
 MEASURED_COUNTERS = {
-    "4fa6e7a1ba4ae2000d19da44a0838b3077b88988807e9aa2736fd074771d3fa3": {
-        "config": 4, "fetch_kib": 15126.407, "write_kib": 304.814, "fetch_scale": 2.0,
-        "write_scale": 1.0, "fp32_flop": 2.317e9},
+    "ee93cc4f456ae6a6335c2b036509f5ccb3787d89b04a4c706af10a4b6cb8153b": {
+        "config": 4, "fetch_kib": 9464.687, "write_kib": 237.129, "fetch_scale": 2.0,
+        "write_scale": 1.0, "fp32_flop": 2.318e9},
 }
 KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",
                   "paper_2005_07068_amd/csrc/ht_device.h")
@@ -497,8 +497,9 @@ def roofline_figures(work, avg_ms, particles_per_launch, model, frames, counters
     alg_bytes = particles_per_launch * (pose_b + 4) + obs_b
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": traffic,
-            "kernel": "raycast_kernel<false,false,%d>" % (5 if model["prim_type"].max() > 2
-                                                          else 3),
+            # both variants: the swarm's launches and the self-scheduled small ones
+            "kernel": "raycast_kernel<false,false,%d,*>" % (5 if model["prim_type"].max() > 2
+                                                            else 3),
             "avg_launch_ms": avg_ms, "particles_per_launch": particles_per_launch,
             "achieved_definition": definition / 1e12,
             "frac_definition": definition / PEAK_FP32_VALU,

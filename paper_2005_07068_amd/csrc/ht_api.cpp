@@ -371,9 +371,10 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   // launches of at most kSelfSchedMax particles without debug images build their work list
   // in the ray cast (no work-list launch)
   a.self_sched = n_total <= ht::kSelfSchedMax && !dbg_on ? 1 : 0;
-  const int gpc = std::min(c->lc.groups_per_cu,
-                           ht::raycast_groups_per_cu(grad != nullptr, dbg_on, all_types,
-                                                     a.self_sched != 0));
+  int gpc = std::min(c->lc.groups_per_cu,
+                     ht::raycast_groups_per_cu(grad != nullptr, dbg_on, all_types,
+                                               a.self_sched != 0));
+  if (a.self_sched) gpc = std::min(gpc, ht::kSelfGroupsPerCu);
   a.grid = (int)std::max<long long>(1, std::min<long long>((long long)c->n_cu * gpc, bound));
   a.n_prim = c->n_prim;
   a.n_seg = c->n_seg;

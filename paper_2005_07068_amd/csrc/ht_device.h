@@ -162,6 +162,9 @@ hipError_t launch_pack_observation(const uint16_t* depth, const uint8_t* skin, i
                                    int* tile_skin, double* totals, float bg, hipStream_t s);
 enum { kStageFk = 0, kStageSched = 1, kStageRaycast = 2, kStageFinalize = 3, kNumStages = 4 };
 constexpr int kSelfSchedMax = 256;   // launches of at most this many particles self-schedule
+// persistent workgroups per CU of a self-scheduled launch, at most: on the two-hand 640x480
+// workload the 128-particle forward launch took 31.5, 27.9, 26.9, 30.5 and 30.7 us at 4..8
+constexpr int kSelfGroupsPerCu = 6;
 hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, hipStream_t s);
 int raycast_groups_per_cu(bool grad, bool dbg, bool all_types, bool self_sched);
 hipError_t launch_pso_init(const DevModel* model, const ht_swarm& sw, int n_dof, hipStream_t s);

@@ -1474,7 +1474,10 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
   // gradient: per wavefront, segment and 16-lane row, the six wrench components of the item
   __shared__ float s_wr[GRAD ? kWavesPerBlock : 1][GRAD ? HT_MAX_SEG : 1][GRAD ? 4 : 1][6];
 
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+  // the wavefront index as a scalar, so that the tile walk, the tile's coordinates and the
+  // observation addresses are wave-uniform (scalar instructions)
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n_prim = a.n_prim, n_seg = a.n_seg;
   static_assert(!(SELF && DEBUG), "debug launches take the work-list kernel");
   constexpr bool self = SELF;
