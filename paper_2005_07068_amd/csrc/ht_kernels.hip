@@ -709,8 +709,12 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
       // the frame's columns are unit vectors to FP64 rounding, so the axis needs no
       // normalisation
       const double u[3] = {F[2], F[6], F[10]};
+      // terms of the ray tests that do not depend on the pixel are formed here once, as the
+      // same FP32 operations the tests would perform (so the tests' results are unchanged):
+      // products with the ray's z component sz, and the cylinder's mid-axis parameter
       if (typ == HT_SPHERE) {
         rec[3] = (float)(sz[0] * sz[0]);
+        rec[7] = fs.sz * rec[2];
       } else if (typ == HT_CYLINDER || typ == HT_CONE) {
         // circular cylinder (radius r0) or truncated cone (radius r0 at s = 0, r1 at s = L)
         const double r0 = sz[0], L = sz[1], r1 = typ == HT_CONE ? sz[2] : sz[0];
@@ -721,6 +725,10 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
         rec[10] = (float)u[2];
         rec[11] = typ == HT_CONE ? (float)((r1 - r0) / L)
                                  : (float)(c[0] * u[0] + c[1] * u[1] + c[2] * u[2]);
+        if (typ == HT_CYLINDER) {
+          rec[16] = fs.sz * rec[10];
+          rec[17] = fmaf(0.5f, rec[7], rec[11]);
+        }
       } else {
         // ellipsoid: Q = R diag(1/s^2) R^T with R the rotation part of F; elliptic cylinder:
         // the same without the axis term, Q = ex ex^T / a^2 + ey ey^T / b^2
@@ -748,6 +756,10 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
           rec[17] = (float)u[1];
           rec[18] = (float)u[2];
           rec[19] = (float)sz[1];
+        } else {
+          rec[16] = rec[8] * fs.sz;
+          rec[17] = rec[10] * fs.sz;
+          rec[18] = rec[11] * fs.sz;
         }
       }
       float4* dst = reinterpret_cast<float4*>(ws.recs + ((size_t)p * n_prim + k) * kRec);
@@ -1017,7 +1029,7 @@ __device__ __forceinline__ float capped_margin(float radial, bool side_hit, floa
 template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void sphere_test(const float* r, float dx, float dy, float dz,
                                             float inv_dd, Hit& h) {
-  const float b = fmaf(dx, r[0], fmaf(dy, r[1], dz * r[2]));
+  const float b = fmaf(dx, r[0], fmaf(dy, r[1], r[7]));   // r[7] = dz r[2]
   const float t0 = b * inv_dd;
   const float vx = fmaf(t0, dx, -r[0]) - r[4];
   const float vy = fmaf(t0, dy, -r[1]) - r[5];
@@ -1042,9 +1054,10 @@ template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void ellipsoid_test(const float* r, float dx, float dy, float dz,
                                                Hit& h) {
   const float q00 = r[3], q01 = r[7], q02 = r[8], q11 = r[9], q12 = r[10], q22 = r[11];
-  const float qdx = fmaf(q00, dx, fmaf(q01, dy, q02 * dz));
-  const float qdy = fmaf(q01, dx, fmaf(q11, dy, q12 * dz));
-  const float qdz = fmaf(q02, dx, fmaf(q12, dy, q22 * dz));
+  // r[16..18] = (q02, q12, q22) dz
+  const float qdx = fmaf(q00, dx, fmaf(q01, dy, r[16]));
+  const float qdy = fmaf(q01, dx, fmaf(q11, dy, r[17]));
+  const float qdz = fmaf(q02, dx, fmaf(q12, dy, r[18]));
   const float dqd = fmaf(dx, qdx, fmaf(dy, qdy, dz * qdz));
   const float cqd = fmaf(r[0], qdx, fmaf(r[1], qdy, r[2] * qdz));
   const float inv = fast_rcp(dqd);
@@ -1080,14 +1093,14 @@ template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy, float dz,
                                               float dd, Hit& h) {
   const float ux = r[8], uy = r[9], uz = r[10], L = r[7];
-  const float da = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
+  const float da = fmaf(dx, ux, fmaf(dy, uy, r[16]));   // r[16] = dz uz
   const float px = fmaf(-da, ux, dx), py = fmaf(-da, uy, dy), pz = fmaf(-da, uz, dz);
   const float A = fmaf(px, px, fmaf(py, py, pz * pz));
   const bool par = A < 1.0e-6f * dd;          // ray within ~1e-3 rad of the axis
   const float inv_da = fast_rcp(da);
   const float invA = fast_rcp(A);
   const float t_side = fmaf(px, r[0], fmaf(py, r[1], pz * r[2])) * invA;
-  const float t_mid = (r[11] + 0.5f * L) * inv_da;
+  const float t_mid = r[17] * inv_da;                    // r[17] = r[11] + L / 2
   const float tr = par ? t_mid : t_side;
   const float vx = fmaf(tr, dx, -r[0]) - r[4];
   const float vy = fmaf(tr, dy, -r[1]) - r[5];
@@ -1688,7 +1701,9 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
           const float* r = recs + win * kRec;
           seg = __float_as_int(r[15]);
           const float nd = fmaf(wnx, dx, fmaf(wny, dy, wnz * dz));
-          kap = (rd > od ? 1.0f : -1.0f) * dz / nd;
+          // (the hardware reciprocal: a quotient would expand into a range-safe sequence of
+          // ten instructions; nd is a dot product of normal and ray, far from the range ends)
+          kap = ((rd > od ? dz : -dz)) * fast_rcp(nd);
           // lever arm from the segment origin: (entry - ref) + (ref - origin)
           const float lx = wrx + r[12], ly = wry + r[13], lz = wrz + r[14];
           mx = kap * (ly * wnz - lz * wny);
