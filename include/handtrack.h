@@ -133,6 +133,19 @@ ht_status ht_set_observation(ht_ctx* ctx, int frame_slot, int W, int H, const ui
                              const uint8_t* skin, ht_camera cam, float bg_depth_mm,
                              int ptr_kind, void* hip_stream);
 
+/* Gradient pixel mask of frame slot `frame_slot`: mask [H][W] with the slot's ROI size (the W,
+ * H of its ht_set_observation), nonzero = the pixel contributes to dE/dh (the cost is never
+ * masked).  Every gradient evaluation of a frame held in this slot (ht_eval_particles_grad with
+ * any n_frames, the swarm's refinement) then leaves out the pixels it excludes; a call's own
+ * pixel_mask, where given, is used instead.  This is the per-frame mask of the finite-difference
+ * protocol of the gradient (the gradient is not in the paper; its cost is Eq. 4-5).  NULL clears
+ * the mask; ht_set_observation on the slot clears it too.  `ptr_kind` as for
+ * ht_set_observation; the data are copied (stream-ordered on hip_stream).  May allocate (set-up
+ * call: not for graph capture).
+ * Errors: HT_ERR_ARG for a bad slot or ptr_kind; HT_ERR_STATE for a slot without observation. */
+ht_status ht_set_pixel_mask(ht_ctx* ctx, int frame_slot, const uint8_t* mask, int ptr_kind,
+                            void* hip_stream);
+
 /* Observation preprocessing (section II.B: the hand is extracted from the RGB-D frame by
  * skin-colour detection and depth segmentation; the paper names no method, this is the
  * library's, in exact integer arithmetic):
@@ -195,8 +208,9 @@ ht_status ht_eval_particles(ht_ctx* ctx, int n_frames, const int32_t* frame_slot
 /* E and dE/dh.  The gradient is that of the clamped depth sum of Eq. 4 over the hit pixels
  * (with sum(o_s or r_m) held fixed; it and the Dice term are piecewise constant) plus
  * lambda_k dkc/dh.  grad: device float32 [n_frames][n_particles][n_dof].  pixel_mask: NULL for
- * every pixel, else device uint8 [H][W] (n_frames must be 1): pixels with 0 are left out of
- * the gradient (not of the cost).  Errors as ht_eval_particles. */
+ * the frames' slot masks (ht_set_pixel_mask; every pixel where a slot has none), else device
+ * uint8 [H][W] of the frame's slot (n_frames must be 1): pixels with 0 are left out of the
+ * gradient (not of the cost).  Errors as ht_eval_particles. */
 ht_status ht_eval_particles_grad(ht_ctx* ctx, int n_frames, const int32_t* frame_slots,
                                  int n_particles, const float* poses, float* cost, float* grad,
                                  const uint8_t* pixel_mask, void* hip_stream);

@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.ht_check_model.argtypes = [C.POINTER(Model)]
     lib.ht_check_model.restype = S
     lib.ht_set_observation.argtypes = [P, I, I, I, P, P, Camera, F, I, P]
+    lib.ht_set_pixel_mask.argtypes = [P, I, P, I, P]
     lib.ht_reserve.argtypes = [P, I, I]
     lib.ht_eval_particles.argtypes = [P, I, P, I, P, P, C.POINTER(Debug), P]
     lib.ht_eval_particles_grad.argtypes = [P, I, P, I, P, P, P, P, P]
@@ -115,7 +116,8 @@ def load_library(path: str = LIB_PATH):
     lib.ht_profile_begin.argtypes = [P]
     lib.ht_profile_end.argtypes = [P, C.POINTER(KernelStat)]
     lib.ht_eval_counts.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), I]
-    for name in ("ht_profile_begin", "ht_profile_end", "ht_create", "ht_set_model", "ht_set_observation", "ht_reserve",
+    for name in ("ht_profile_begin", "ht_profile_end", "ht_create", "ht_set_model", "ht_set_observation", "ht_set_pixel_mask",
+                 "ht_reserve",
                  "ht_eval_particles", "ht_eval_particles_grad", "ht_eval_particles_noalloc",
                  "ht_pso_init", "ht_pso_step",
                  "ht_pso_run_graph", "ht_get_launch_config", "ht_set_launch_config",
@@ -248,6 +250,26 @@ class Context:
                                            C.c_void_p(sp), Camera(fx, fy, cx, cy), float(bg),
                                            kind, _stream()))
         self.slots[slot] = (W, H, float(bg))
+
+    def set_pixel_mask(self, slot: int, mask=None):
+        """Gradient pixel mask of a frame slot: uint8 [H, W] of the slot's ROI (numpy array, or
+        torch tensor on the host or the device); None clears it."""
+        import torch
+        if mask is None:
+            _check(self.lib.ht_set_pixel_mask(self.handle, slot, None, HT_PTR_HOST, _stream()))
+            return
+        if slot not in self.slots:
+            raise ValueError(f"frame slot {slot} has no observation")
+        W, H = self.slots[slot][:2]
+        if isinstance(mask, torch.Tensor):
+            m = mask.to(torch.uint8).contiguous()
+            kind, ptr = (HT_PTR_DEVICE if m.is_cuda else HT_PTR_HOST), m.data_ptr()
+        else:
+            m = np.ascontiguousarray(mask, np.uint8)
+            kind, ptr = HT_PTR_HOST, m.ctypes.data
+        if tuple(m.shape) != (H, W):
+            raise ValueError(f"mask shape {tuple(m.shape)} is not the slot's ({H}, {W})")
+        _check(self.lib.ht_set_pixel_mask(self.handle, slot, C.c_void_p(ptr), kind, _stream()))
 
     def reserve(self, max_particles: int, max_pixels: int):
         _check(self.lib.ht_reserve(self.handle, max_particles, max_pixels))

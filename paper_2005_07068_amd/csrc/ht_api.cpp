@@ -95,6 +95,8 @@ struct SlotHost {
   double* totals = nullptr;
   uint16_t* stage_depth = nullptr;
   uint8_t* stage_skin = nullptr;
+  uint8_t* mask = nullptr;       // gradient pixel mask (ht_set_pixel_mask)
+  size_t cap_mask = 0;
   ht::FrameSlot entry{};
 };
 
@@ -449,6 +451,7 @@ void ht_destroy(ht_ctx* c) {
     dfree(s.totals);
     dfree(s.stage_depth);
     dfree(s.stage_skin);
+    dfree(s.mask);
   }
   dfree(c->r_x);
   dfree(c->r_cost);
@@ -686,6 +689,7 @@ ht_status ht_set_observation(ht_ctx* c, int slot, int W, int H, const uint16_t* 
   e.tile_td = sh.tile_td;
   e.tile_skin = sh.tile_skin;
   e.totals = sh.totals;
+  e.grad_mask = nullptr;   // a new observation clears the slot's gradient mask
   HT_HIP(hipMemcpyAsync(&c->d_slots[slot], &e, sizeof e, hipMemcpyHostToDevice, s));
   HT_HIP(hipStreamSynchronize(s));
   sh.set = true;
@@ -917,6 +921,38 @@ ht_status ht_pso_init(ht_ctx* c, const ht_swarm* sw, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HT_HIP(traced(c, HT_K_PSO, sw->n_frames * sw->n_particles, s,
                 [&] { return ht::launch_pso_init(c->d_model, *sw, c->n_dof, s); }));
+  return HT_OK;
+}
+
+ht_status ht_set_pixel_mask(ht_ctx* c, int slot, const uint8_t* mask, int ptr_kind,
+                            void* stream) {
+  g_err.clear();
+  ht_status st = check_ctx(c, false);
+  if (st != HT_OK) return st;
+  if (slot < 0 || slot >= HT_MAX_SLOTS) return fail(HT_ERR_ARG, "frame slot %d out of 0..%d", slot, HT_MAX_SLOTS - 1);
+  if (ptr_kind != HT_PTR_HOST && ptr_kind != HT_PTR_DEVICE) return fail(HT_ERR_ARG, "bad ptr_kind %d", ptr_kind);
+  SlotHost& sh = c->slots[slot];
+  if (!sh.set) return fail(HT_ERR_STATE, "frame slot %d has no observation", slot);
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  ht::FrameSlot& e = sh.entry;
+  if (mask) {
+    const size_t n_px = (size_t)e.W * e.H;
+    if (n_px > sh.cap_mask) {
+      HT_HIP(hipDeviceSynchronize());
+      dfree(sh.mask);
+      HT_HIP(hipMalloc(&sh.mask, n_px));
+      sh.cap_mask = n_px;
+    }
+    HT_HIP(hipMemcpyAsync(sh.mask, mask, n_px,
+                          ptr_kind == HT_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                          s));
+    e.grad_mask = sh.mask;
+  } else {
+    e.grad_mask = nullptr;
+  }
+  HT_HIP(hipMemcpyAsync(&c->d_slots[slot], &e, sizeof e, hipMemcpyHostToDevice, s));
+  HT_HIP(hipStreamSynchronize(s));
   return HT_OK;
 }
 

@@ -74,6 +74,7 @@ struct FrameSlot {
   const float* tile_td;      // [TH*TW] sum of min(|o_d - r_bg|, d_M) over the tile
   const int* tile_skin;      // [TH*TW] skin pixels of the tile
   const double* totals;      // [2]: the same two sums over the whole ROI
+  const uint8_t* grad_mask;  // [H][W] gradient pixel mask of the slot, NULL: every pixel
 };
 
 // Per-particle summary written by the kinematics kernel.  The tiles to visit are the union of

@@ -1337,6 +1337,7 @@ __device__ __forceinline__ FrameSlot uni(const FrameSlot& f) {
   u.tile_td = uni(f.tile_td);
   u.tile_skin = uni(f.tile_skin);
   u.totals = uni(f.totals);
+  u.grad_mask = uni(f.grad_mask);
   return u;
 }
 
@@ -1693,7 +1694,9 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       if (GRAD) {
         // adjoint: coefficient of the depth term, then the per-segment wrench
         bool act = valid && hit && diff < kDClamp && od != rd;
-        if (act && a.pixel_mask) act = a.pixel_mask[(size_t)v * fs.W + u] != 0;
+        // the call's mask (one frame), else the frame's slot mask
+        const uint8_t* gmask = a.pixel_mask ? a.pixel_mask : fs.grad_mask;
+        if (act && gmask) act = global_ptr(gmask)[(size_t)v * fs.W + u] != 0;
         int seg = -1;
         float kap = 0.0f;
         float mx = 0, my = 0, mz = 0;
