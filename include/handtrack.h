@@ -200,7 +200,8 @@ typedef struct {
  * cost: device float32 [n_frames][n_particles].  dbg may be NULL.
  * Errors: HT_ERR_STATE before set_model, HT_ERR_ARG for NULL pointers or counts < 0,
  * HT_ERR_UNSUPPORTED for dbg with n_frames != 1.  n_frames * n_particles == 0 is a no-op.
- * The frame slots are read on the device: every slot used must have been set. */
+ * The frame slots are read on the device: every slot used must have been set; a particle of an
+ * unset slot scores NaN and raises HT_DEVERR_UNSET_SLOT (ht_device_errors). */
 ht_status ht_eval_particles(ht_ctx* ctx, int n_frames, const int32_t* frame_slots,
                             int n_particles, const float* poses, float* cost,
                             const ht_debug* dbg, void* hip_stream);
@@ -352,6 +353,14 @@ ht_status ht_profile_end(ht_ctx* ctx, ht_kernel_stat* stats);
  * candidates of a refined particle that has stopped refining -- are not counted.  Synchronises
  * the device; reset != 0 sets both counts to zero afterwards.  Errors: HT_ERR_ARG for NULL. */
 ht_status ht_eval_counts(ht_ctx* ctx, int64_t* forward, int64_t* gradient, int reset);
+
+/* Errors that the device met in enqueued work since the context was created or last reset, as
+ * bit flags (the evaluation calls return before their kernels run; frame slots are device
+ * data).  HT_DEVERR_UNSET_SLOT: a particle's frame slot held no observation (or was out of
+ * 0..HT_MAX_SLOTS-1); its cost is NaN and its gradient zero.  Synchronises the device; reset != 0
+ * clears the flags afterwards.  Errors: HT_ERR_ARG for NULL. */
+#define HT_DEVERR_UNSET_SLOT 1u
+ht_status ht_device_errors(ht_ctx* ctx, uint32_t* flags, int reset);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,6 @@ The compute lives in ``libhandtrack.so`` (HIP kernels behind the C ABI of
 ``torch.autograd.Function`` around the adjoint kernel.
 """
 from .binding import (  # noqa: F401
-    Context, HandtrackError, load_library, pso_params, header_functions,
+    HT_DEVERR_UNSET_SLOT, Context, HandtrackError, load_library, pso_params, header_functions,
 )
 from .autograd import HandCost  # noqa: F401

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libhandtrack.so")
 
 HT_OK, HT_ERR_ARG, HT_ERR_STATE, HT_ERR_OOM, HT_ERR_HIP, HT_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 HT_PTR_HOST, HT_PTR_DEVICE = 0, 1
+HT_DEVERR_UNSET_SLOT = 1
 _NAMES = {0: "HT_OK", -1: "HT_ERR_ARG", -2: "HT_ERR_STATE", -3: "HT_ERR_OOM", -4: "HT_ERR_HIP",
           -5: "HT_ERR_UNSUPPORTED"}
 
@@ -116,12 +117,13 @@ def load_library(path: str = LIB_PATH):
     lib.ht_profile_begin.argtypes = [P]
     lib.ht_profile_end.argtypes = [P, C.POINTER(KernelStat)]
     lib.ht_eval_counts.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), I]
+    lib.ht_device_errors.argtypes = [P, C.POINTER(C.c_uint32), I]
     for name in ("ht_profile_begin", "ht_profile_end", "ht_create", "ht_set_model", "ht_set_observation", "ht_set_pixel_mask",
                  "ht_reserve",
                  "ht_eval_particles", "ht_eval_particles_grad", "ht_eval_particles_noalloc",
                  "ht_pso_init", "ht_pso_step",
                  "ht_pso_run_graph", "ht_get_launch_config", "ht_set_launch_config",
-                 "ht_autotune", "ht_eval_counts"):
+                 "ht_autotune", "ht_eval_counts", "ht_device_errors"):
         getattr(lib, name).restype = S
     _lib = lib
     return lib
@@ -434,6 +436,12 @@ class Context:
         f, g = C.c_int64(), C.c_int64()
         _check(self.lib.ht_eval_counts(self.handle, C.byref(f), C.byref(g), int(reset)))
         return f.value, g.value
+
+    def device_errors(self, reset: bool = False) -> int:
+        """HT_DEVERR_* flags the device raised in enqueued work so far (synchronises)."""
+        v = C.c_uint32()
+        _check(self.lib.ht_device_errors(self.handle, C.byref(v), int(reset)))
+        return v.value
 
     # -- launch shape -------------------------------------------------------------------
     def launch_config(self):

@@ -144,6 +144,7 @@ struct ht_ctx {
   std::map<GraphKey, hipGraphExec_t> graphs;
   void* scratch = nullptr;    // this device's address of the no-allocation scratch array
   unsigned long long* d_eval_count = nullptr;   // [2] forward / gradient evaluations
+  unsigned int* d_errors = nullptr;              // HT_DEVERR_* flags
   // tracing of eager launches
   struct ProfRec {
     int kind;
@@ -353,6 +354,7 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   a.active = active;
   a.active_div = active_div;
   a.eval_count = c->d_eval_count;
+  a.dev_errors = c->d_errors;
   if (dbg) {
     a.dbg = *dbg;
     const SlotHost& sh = c->slots[dbg->slot];
@@ -424,6 +426,8 @@ ht_status ht_create(ht_ctx** out, int hip_device) {
   if (e == hipSuccess) e = hipMalloc(&c->d_model, sizeof(ht::DevModel));
   if (e == hipSuccess) e = hipMalloc(&c->d_eval_count, 2 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(c->d_eval_count, 0, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&c->d_errors, sizeof(unsigned int));
+  if (e == hipSuccess) e = hipMemset(c->d_errors, 0, sizeof(unsigned int));
   if (e != hipSuccess) {
     ht_destroy(c);
     return fail(HT_ERR_OOM, "context allocation failed: %s", hipGetErrorString(e));
@@ -467,6 +471,7 @@ void ht_destroy(ht_ctx* c) {
   dfree(c->d_slots);
   dfree(c->d_model);
   dfree(c->d_eval_count);
+  dfree(c->d_errors);
   delete c;
 }
 
@@ -1173,6 +1178,18 @@ ht_status ht_eval_counts(ht_ctx* c, int64_t* forward, int64_t* gradient, int res
   if (reset) HT_HIP(hipMemset(c->d_eval_count, 0, sizeof v));
   *forward = (int64_t)v[0];
   *gradient = (int64_t)v[1];
+  return HT_OK;
+}
+
+ht_status ht_device_errors(ht_ctx* c, uint32_t* flags, int reset) {
+  g_err.clear();
+  if (!c || !flags) return fail(HT_ERR_ARG, "NULL argument");
+  DeviceGuard g(c->device);
+  unsigned int v = 0;
+  HT_HIP(hipDeviceSynchronize());
+  HT_HIP(hipMemcpy(&v, c->d_errors, sizeof v, hipMemcpyDeviceToHost));
+  if (reset) HT_HIP(hipMemset(c->d_errors, 0, sizeof v));
+  *flags = v;
   return HT_OK;
 }
 

@@ -140,6 +140,7 @@ struct EvalArgs {
   // evaluations performed (not skipped), [0] forward and [1] gradient, added up by the
   // work-list kernel of every call; may be NULL
   unsigned long long* eval_count;
+  unsigned int* dev_errors;    // HT_DEVERR_* flags raised on the device, may be NULL
   // NULL, or per evaluated particle r its source s = src[r]: the particle reuses the kinematics
   // of workspace particle (r / n_particles) * src_stride + s from the previous evaluation
   // (same poses; the kinematics stage is skipped)

@@ -546,6 +546,8 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   int slot = -1;
   if (active) slot = a.frame_slots[p / a.n_particles];
   const bool slot_ok = active && slot >= 0 && slot < HT_MAX_SLOTS && a.slots[slot].set;
+  if (active && !slot_ok && h == 0 && lane == 0 && a.dev_errors)
+    atomicOr(a.dev_errors, HT_DEVERR_UNSET_SLOT);
   // a particle of a stopped frame (tracking stop rule), or a candidate of a refined particle
   // that has stopped refining, is neither cast nor written
   const bool skip = active && ((a.frame_stop && a.frame_stop[p / a.n_particles] != 0) ||

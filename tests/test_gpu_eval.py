@@ -3,6 +3,8 @@ the FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
 
+import paper_2005_07068_amd as ht
+
 from gpu_util import (check_particle, eval_debug, frame_for, make_ctx, oracle_renders,
                       particles_for, torch_cuda)
 from oracle import synth
@@ -110,10 +112,17 @@ def test_nonfinite_pose_unset_slot_and_empty_call():
     c = ctx.eval(torch.tensor(poses, device=dev), torch.zeros(1, dtype=torch.int32, device=dev))
     c = c.cpu().numpy()
     assert np.isfinite(c[0]) and c[1] == np.inf and c[2] == np.inf
-    # a frame slot that was never set scores NaN (no fault)
+    # a frame slot that was never set scores NaN (no fault) and raises the device error flag;
+    # slot numbers out of range too
+    assert ctx.device_errors() == 0
     c = ctx.eval(torch.tensor(poses[:1], device=dev),
                  torch.full((1,), 5, dtype=torch.int32, device=dev)).cpu().numpy()
     assert np.isnan(c[0])
+    assert ctx.device_errors(reset=True) == ht.HT_DEVERR_UNSET_SLOT
+    assert ctx.device_errors() == 0
+    c = ctx.eval(torch.tensor(poses[:1], device=dev),
+                 torch.full((1,), -3, dtype=torch.int32, device=dev)).cpu().numpy()
+    assert np.isnan(c[0]) and ctx.device_errors(reset=True) == ht.HT_DEVERR_UNSET_SLOT
     empty = torch.zeros((0, model["n_dof"]), device=dev)
     out = ctx.eval(empty, torch.zeros(1, dtype=torch.int32, device=dev))
     assert out.numel() == 0
