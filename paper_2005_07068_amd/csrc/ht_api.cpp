@@ -372,16 +372,13 @@ ht_status eval_impl(ht_ctx* c, int n_frames, const int32_t* frame_slots, int n_p
   const bool dbg_on = a.dbg.depth || a.dbg.hit || a.dbg.rm || a.dbg.winner || a.dbg.margin;
   const bool all_types = (c->tmask.m[HT_CONE][0] | c->tmask.m[HT_CONE][1] |
                           c->tmask.m[HT_ECYLINDER][0] | c->tmask.m[HT_ECYLINDER][1]) != 0ull;
-  // launches without debug images build their work list in the ray cast (no work-list
-  // launch): at most kSelfSchedMax particles, or kSelfSchedLargeMax whose kinematics this
-  // evaluation computes (its kinematics kernel resets the dequeue counter)
-  a.self_sched = dbg_on ? 0
-                 : n_total <= ht::kSelfSchedMax ? 1
-                 : (n_total <= ht::kSelfSchedLargeMax && !src) ? 4 : 0;
+  // launches of at most kSelfSchedMax particles without debug images build their work list
+  // in the ray cast (no work-list launch)
+  a.self_sched = n_total <= ht::kSelfSchedMax && !dbg_on ? 1 : 0;
   int gpc = std::min(c->lc.groups_per_cu,
                      ht::raycast_groups_per_cu(grad != nullptr, dbg_on, all_types,
-                                               a.self_sched));
-  if (a.self_sched == 1) gpc = std::min(gpc, ht::kSelfGroupsPerCu);
+                                               a.self_sched != 0));
+  if (a.self_sched) gpc = std::min(gpc, ht::kSelfGroupsPerCu);
   a.grid = (int)std::max<long long>(1, std::min<long long>((long long)c->n_cu * gpc, bound));
   a.n_prim = c->n_prim;
   a.n_seg = c->n_seg;

@@ -545,9 +545,6 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   if (h == 0 && lane == 0) s_fin[pb] = finite ? 1 : 0;
   int slot = -1;
   if (active) slot = a.frame_slots[p / a.n_particles];
-  // the dequeue counter of a self-scheduled ray cast that follows (launches with a work-list
-  // kernel have it reset there)
-  if (blockIdx.x == 0 && threadIdx.x == 0) ws.counters[0] = 0;
   const bool slot_ok = active && slot >= 0 && slot < HT_MAX_SLOTS && a.slots[slot].set;
   if (active && !slot_ok && h == 0 && lane == 0 && a.dev_errors)
     atomicOr(a.dev_errors, HT_DEVERR_UNSET_SLOT);
@@ -1414,66 +1411,42 @@ __device__ __forceinline__ int xcd_major_item(int b, int G) {
   return x * q + min(x, rem) + j;
 }
 
-// Launches of at most kSelfSchedLarge particles build their work list in every ray-cast
-// workgroup (no work-list launch before them): each thread reads the tile counts of PPT
-// consecutive particles, two block scans give the item size (the work-list kernel's rule) and
-// the item offsets in LDS.  With one particle per thread (at most kSelfSched) the workgroups
-// take items in a static stride of the grid size (the items are sized to about one per
-// workgroup, so there is nothing to balance dynamically); with more, the first item is static
-// and later ones come from the dequeue counter (reset by the kinematics kernel).  Workgroup 0
-// stores the offsets for the finalize and refinement kernels and adds the launch's
-// evaluations to the counts.
+// Launches of at most kSelfSched particles build their work list in every ray-cast workgroup
+// (no work-list launch before them): one thread per particle reads its tile count, two block
+// scans give the item size (the work-list kernel's rule) and the item offsets in LDS, and the
+// workgroups take items in a static stride of the grid size (the items are sized to about
+// one per workgroup, so there is nothing to balance dynamically).  Workgroup 0 stores the
+// offsets for the finalize and refinement kernels and adds the launch's evaluations to the
+// counts.
 constexpr int kSelfSched = kBlock;
-constexpr int kSelfPpt = 4;                       // particles per thread of the larger launches
-constexpr int kSelfSchedLarge = kBlock * kSelfPpt;
-static_assert(kSelfSched == kSelfSchedMax && kSelfSchedLarge == kSelfSchedLargeMax,
-              "self-scheduled launch sizes");
+static_assert(kSelfSched == kSelfSchedMax, "one thread per particle of a self-scheduled launch");
 
-template <int PPT>
 __device__ void self_schedule(const EvalArgs& a, const Workspace& ws, int* s_off, int& total,
                               int& tpi, bool& interleave) {
   __shared__ int2 s_sum2[kWavesPerBlock];
   __shared__ int s_sum[kWavesPerBlock];
   const int n_total = a.n_frames * a.n_particles;
   const int t = threadIdx.x;
-  int v[PPT];
-  int tiles = 0, evaluated = 0;
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    const int r = t * PPT + j;
-    v[j] = r < n_total ? ws.tiles[src_of(a, min(r, n_total - 1))] : -1;
-    tiles += max(v[j], 0);
-    evaluated += v[j] >= 0 ? 1 : 0;
-  }
+  const int v = t < n_total ? ws.tiles[src_of(a, min(t, n_total - 1))] : -1;
   int total_tiles, total_evaluated;
-  block_scan2<kWavesPerBlock>(s_sum2, tiles, evaluated, &total_tiles, &total_evaluated);
+  block_scan2<kWavesPerBlock>(s_sum2, max(v, 0), v >= 0 ? 1 : 0, &total_tiles,
+                              &total_evaluated);
   const long long target = (long long)a.grid * kItemsPerGroup;
   long long tq = ((long long)total_tiles + target - 1) / target;
   tq = (tq + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
   const long long lo = a.grad ? (long long)kFloorTilesGrad : (long long)kFloorTilesFwd;
   tpi = (int)max(min(lo, (long long)a.tiles_per_item), min(tq, (long long)a.tiles_per_item));
-  int items[PPT], my_items = 0;
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    items[j] = (max(v[j], 0) + tpi - 1) / tpi;
-    my_items += items[j];
-  }
+  const int items = (max(v, 0) + tpi - 1) / tpi;
   int total_items;
-  int run = block_scan<kWavesPerBlock>(s_sum, my_items, &total_items) - my_items;
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    run += items[j];
-    if (t * PPT + j < n_total) s_off[t * PPT + j + 1] = run;
-  }
+  const int incl = block_scan<kWavesPerBlock>(s_sum, items, &total_items);
+  if (t < n_total) s_off[t + 1] = incl;
   if (t == 0) s_off[0] = 0;
   __syncthreads();
   total = total_items;
   interleave = a.grad && total_items <= 2 * a.grid;
   if (blockIdx.x == 0) {
-    // n_total + 1 offsets: PPT per thread, the end offset by thread 0
-#pragma unroll
-    for (int j = 0; j < PPT; ++j)
-      if (t * PPT + j < n_total) ws.item_off[t * PPT + j] = s_off[t * PPT + j];
+    // n_total + 1 offsets: one per thread, the end offset by thread 0
+    if (t < n_total) ws.item_off[t] = s_off[t];
     if (t == 0) {
       ws.item_off[n_total] = total_items;
       if (a.eval_count)
@@ -1500,11 +1473,10 @@ __device__ __forceinline__ int self_item_particle(const int* s_off, int n_total,
 // NT: primitive types the model uses (3: spheres, cylinders, ellipsoids; kNumTypes: also
 // cones and elliptic cylinders), so a model without the latter keeps the smaller register
 // footprint.  (Forcing more wavefronts per SIMD than the natural register count allows
-// spills registers and measured slower.)  SELF: 0, or the particles per thread with which
-// the launch builds its own work list (1: at most kSelfSched particles, static items; kSelfPpt:
-// at most kSelfSchedLarge, dequeued items; no debug images); variants of their own, so that
-// the launches with a work-list kernel carry none of this code (which cost them about 5%).
-template <bool GRAD, bool DEBUG, int NT, int SELF>
+// spills registers and measured slower.)  SELF: the launch builds its own work list (at most
+// kSelfSched particles, no debug images); a variant of its own, so the larger launches keep
+// the dequeue loop without the self-scheduling code (which cost them about 5%).
+template <bool GRAD, bool DEBUG, int NT, bool SELF>
 __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace ws,
                                                       TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
@@ -1524,12 +1496,12 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n_prim = a.n_prim, n_seg = a.n_seg;
   static_assert(!(SELF && DEBUG), "debug launches take the work-list kernel");
-  constexpr bool self = SELF != 0;
-  __shared__ int s_off[SELF ? kBlock * SELF + 1 : 1];
+  constexpr bool self = SELF;
+  __shared__ int s_off[SELF ? kSelfSched + 1 : 1];
   int total, tpi;
   bool interleave;
-  if constexpr (SELF != 0) {
-    self_schedule<SELF>(a, ws, s_off, total, tpi, interleave);
+  if constexpr (SELF) {
+    self_schedule(a, ws, s_off, total, tpi, interleave);
   } else {
     total = uni(ws.counters[1]);
     tpi = uni(ws.counters[2]);
@@ -1549,7 +1521,7 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
     if (first) {
       item = xcd_major_item(blockIdx.x, gridDim.x);
       first = false;
-    } else if constexpr (SELF == 1) {
+    } else if constexpr (SELF) {
       item += gridDim.x;
     } else {
       if (tid == 0) s_item = (int)gridDim.x + atomicAdd(&ws.counters[0], 1);
@@ -2206,15 +2178,13 @@ hipError_t launch_refine_update(const EvalArgs& a, const Workspace& ws, const Re
 
 // The ray-cast variant of a launch.
 template <bool GRAD, int NT>
-static const void* raycast_fn_nt(bool dbg, int self) {
-  if (dbg) return reinterpret_cast<const void*>(&raycast_kernel<GRAD, true, NT, 0>);
-  if (self == 1) return reinterpret_cast<const void*>(&raycast_kernel<GRAD, false, NT, 1>);
-  if (self == kSelfPpt)
-    return reinterpret_cast<const void*>(&raycast_kernel<GRAD, false, NT, kSelfPpt>);
-  return reinterpret_cast<const void*>(&raycast_kernel<GRAD, false, NT, 0>);
+static const void* raycast_fn_nt(bool dbg, bool self) {
+  if (dbg) return reinterpret_cast<const void*>(&raycast_kernel<GRAD, true, NT, false>);
+  return self ? reinterpret_cast<const void*>(&raycast_kernel<GRAD, false, NT, true>)
+              : reinterpret_cast<const void*>(&raycast_kernel<GRAD, false, NT, false>);
 }
 
-static const void* raycast_fn(bool grad, bool dbg, bool all_types, int self) {
+static const void* raycast_fn(bool grad, bool dbg, bool all_types, bool self) {
   if (all_types)
     return grad ? raycast_fn_nt<true, kNumTypes>(dbg, self)
                 : raycast_fn_nt<false, kNumTypes>(dbg, self);
@@ -2225,10 +2195,10 @@ static const void* raycast_fn(bool grad, bool dbg, bool all_types, int self) {
 // LDS decide).  The persistent grid is capped at this many per CU: a workgroup beyond it
 // starts only when another has finished, and its statically assigned first item then
 // finishes late (a 128-particle launch spent half its time in that tail).
-int raycast_groups_per_cu(bool grad, bool dbg, bool all_types, int self) {
-  self = dbg ? 0 : self;
-  static int cache[2][2][2][3] = {};
-  int& n = cache[grad][dbg][all_types][self == 0 ? 0 : (self == 1 ? 1 : 2)];
+int raycast_groups_per_cu(bool grad, bool dbg, bool all_types, bool self) {
+  self = self && !dbg;
+  static int cache[2][2][2][2] = {};
+  int& n = cache[grad][dbg][all_types][self];
   if (n > 0) return n;
   const void* f = raycast_fn(grad, dbg, all_types, self);
   int r = 0;
@@ -2272,11 +2242,8 @@ hipError_t launch_eval_stage(int stage, const EvalArgs& a, const Workspace& ws, 
       const TypeMasks tm = a.type_masks;
       const bool all = (tm.m[HT_CONE][0] | tm.m[HT_CONE][1] | tm.m[HT_ECYLINDER][0] |
                         tm.m[HT_ECYLINDER][1]) != 0ull;
-      if (a.self_sched &&
-          (dbg || (a.self_sched != 1 && a.self_sched != kSelfPpt) ||
-           n_total > kBlock * a.self_sched || (a.self_sched > 1 && a.src)))
-        return hipErrorInvalidValue;
-      const void* f = raycast_fn(a.grad != nullptr, dbg, all, a.self_sched);
+      if (a.self_sched && (dbg || n_total > kSelfSched)) return hipErrorInvalidValue;
+      const void* f = raycast_fn(a.grad != nullptr, dbg, all, a.self_sched != 0);
       EvalArgs ka = a;
       Workspace kw = ws;
       TypeMasks kt = tm;
