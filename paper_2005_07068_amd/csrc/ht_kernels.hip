@@ -416,7 +416,10 @@ __device__ void schedule_items(const EvalArgs& a, int n_total, const Workspace& 
 // Z > r, have a = (X Z -/+ r sqrt(X^2 + Z^2 - r^2)) / (Z^2 - r^2), and likewise in y.  The
 // capsule's support along a plane normal is the larger of its end spheres', so no interior
 // point lies outside.  Writes pixel coordinates (u0, u1, v0, v1), padded by a quarter pixel
-// for the FP32 rounding; returns false when a sphere reaches the camera plane.
+// for the FP32 rounding; returns false when a sphere reaches the camera plane.  The culling
+// geometry takes the hardware reciprocal and square root (errors of about 1e-7 relative,
+// 1e-4 pixel at most, far inside the pads; the quotients' range-safe sequences made the
+// primitive set-up a long chain of latencies).
 __device__ bool capsule_extent(const double* q0, const double* q1, double r,
                                const FrameSlot& fs, float* e) {
   float amin = INFINITY, amax = -INFINITY, bmin = INFINITY, bmax = -INFINITY;
@@ -426,8 +429,8 @@ __device__ bool capsule_extent(const double* q0, const double* q1, double r,
     const float X = (float)q[0], Y = (float)q[1], Z = (float)q[2];
     if (!(Z > 1.001f * rr + 1.0f)) return false;
     const float den = (Z - rr) * (Z + rr);
-    const float inv = 1.0f / den;
-    const float hx = rr * sqrtf(fmaf(X, X, den)), hy = rr * sqrtf(fmaf(Y, Y, den));
+    const float inv = fast_rcp(den);
+    const float hx = rr * fast_sqrt(fmaf(X, X, den)), hy = rr * fast_sqrt(fmaf(Y, Y, den));
     const float xz = X * Z, yz = Y * Z;
     amin = fminf(amin, (xz - hx) * inv);
     amax = fmaxf(amax, (xz + hx) * inv);
@@ -449,14 +452,15 @@ __device__ bool capsule_extent(const double* q0, const double* q1, double r,
 __device__ void sphere_image_disc(const double* q, double r, const FrameSlot& fs, float* D,
                                   float& rho) {
   const float X = (float)q[0], Y = (float)q[1], Z = (float)q[2], R = (float)r;
-  const float rad = sqrtf(fmaf(X, X, Y * Y));
-  const float inv_n = 1.0f / sqrtf(fmaf(rad, rad, Z * Z));
+  const float rad = fast_sqrt(fmaf(X, X, Y * Y));
+  const float inv_n = __builtin_amdgcn_rsqf(fmaf(rad, rad, Z * Z));
   const float st = rad * inv_n, ct = Z * inv_n, sa = R * inv_n;
-  const float ca = sqrtf(fmaxf(0.0f, 1.0f - sa * sa));
-  const float tp = fmaf(st, ca, ct * sa) / fmaf(ct, ca, -st * sa);   // tan(theta + alpha)
-  const float tm = fmaf(st, ca, -ct * sa) / fmaf(ct, ca, st * sa);   // tan(theta - alpha)
+  const float ca = fast_sqrt(fmaxf(0.0f, 1.0f - sa * sa));
+  const float tp = fmaf(st, ca, ct * sa) * fast_rcp(fmaf(ct, ca, -st * sa));   // tan(theta + alpha)
+  const float tm = fmaf(st, ca, -ct * sa) * fast_rcp(fmaf(ct, ca, st * sa));   // tan(theta - alpha)
   const float m = 0.5f * (tp + tm), h = 0.5f * (tp - tm);
-  const float ex = rad > 0.0f ? X / rad : 1.0f, ey = rad > 0.0f ? Y / rad : 0.0f;
+  const float ir = fast_rcp(rad);
+  const float ex = rad > 0.0f ? X * ir : 1.0f, ey = rad > 0.0f ? Y * ir : 0.0f;
   D[0] = fmaf(fs.fx, m * ex, fs.cx);
   D[1] = fmaf(fs.fy, m * ey, fs.cy);
   rho = h * fmaxf(fs.fx, fs.fy);
@@ -784,7 +788,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
           // the solid is the convex hull of its two cap discs
           const float r1 = typ == HT_CONE ? s2 : s0;
           for (int i = 0; i < 3; ++i) {
-            const float sn = sqrtf(fmaxf(0.0f, 1.0f - uf[i] * uf[i]));
+            const float sn = fast_sqrt(fmaxf(0.0f, 1.0f - uf[i] * uf[i]));
             const float c1 = fmaf(s1, uf[i], cf[i]);
             lo3[i] = fminf(cf[i] - s0 * sn, c1 - r1 * sn);
             hi3[i] = fmaxf(cf[i] + s0 * sn, c1 + r1 * sn);
@@ -795,7 +799,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
             const float f0 = (float)F[i * 4 + 0] * s0;
             const float f1 = (float)F[i * 4 + 1] * (ecyl ? s2 : s1);
             const float f2 = ecyl ? 0.0f : (float)F[i * 4 + 2] * s2;
-            const float e = sqrtf(fmaf(f0, f0, fmaf(f1, f1, f2 * f2)));
+            const float e = fast_sqrt(fmaf(f0, f0, fmaf(f1, f1, f2 * f2)));
             const float c1 = ecyl ? fmaf(s1, uf[i], cf[i]) : cf[i];
             lo3[i] = fminf(cf[i], c1) - e;
             hi3[i] = fmaxf(cf[i], c1) + e;
@@ -808,7 +812,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
       } else if (fs.bg > 0.0f && lo3[2] >= fs.bg) {
         box = make_int4(1, 0, 1, 0);   // entirely behind the background plane
       } else {
-        const float izl = 1.0f / lo3[2], izh = 1.0f / hi3[2];
+        const float izl = fast_rcp(lo3[2]), izh = fast_rcp(hi3[2]);
         const float xmin = fminf(lo3[0] * izl, lo3[0] * izh);
         const float xmax = fmaxf(hi3[0] * izl, hi3[0] * izh);
         const float ymin = fminf(lo3[1] * izl, lo3[1] * izh);
@@ -880,7 +884,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
           const float dx = D1[0] - D0[0], dy = D1[1] - D0[1];
           const float vv = fmaf(dx, dx, dy * dy);
           cap = make_float4(D0[0], D0[1], dx, dy);
-          capr = make_float2(vv > 0.0f ? 1.0f / vv : 0.0f, reach * reach);
+          capr = make_float2(vv > 0.0f ? fast_rcp(vv) : 0.0f, reach * reach);
         }
       }
       ws.caps[(size_t)p * n_prim + k] = cap;
