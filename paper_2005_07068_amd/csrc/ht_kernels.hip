@@ -24,6 +24,14 @@ namespace ht {
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// A pointer read from memory (a FrameSlot field) is generic to the compiler, and generic
+// loads count against the LDS counter too, so every LDS wait would also wait for them; these
+// buffers are device memory, so their loads are issued as global loads.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -502,21 +510,6 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   __shared__ double s_T[kWavesPerBlock][HT_MAX_SEG][12];
   __shared__ double s_h[kWavesPerBlock][HT_MAX_DOF];
   __shared__ double s_sin[kWavesPerBlock][HT_MAX_DOF], s_cos[kWavesPerBlock][HT_MAX_DOF];
-  // the kinematic tables (everything before the primitive tables), staged by one coalesced
-  // copy: the tree walk would otherwise wait on long chains of dependent global loads.  The
-  // primitive tables are read from global memory by the lane that sets a primitive up,
-  // issued at the start so that their latency overlaps the trigonometry and the tree walk.
-  constexpr int kSegBytes = ((int)offsetof(DevModel, prim_type) + 15) / 16 * 16;
-  static_assert(kSegBytes <= (int)sizeof(DevModel), "copy stays inside the model");
-  __shared__ __align__(16) unsigned char s_model[kSegBytes];
-  {
-    const uint4* src4 = reinterpret_cast<const uint4*>(a.model);
-    uint4* dst4 = reinterpret_cast<uint4*>(s_model);
-    for (int i = threadIdx.x; i < kSegBytes / 16; i += kBlock) dst4[i] = src4[i];
-  }
-  // only the members before prim_type may be read through M
-  const DevModel& M = *reinterpret_cast<const DevModel*>(s_model);
-  const DevModel* __restrict__ G = a.model;
   // the wavefront index as a scalar, so that everything per particle below is wave-uniform
   // (scalar instructions and branches)
   const int lane = threadIdx.x & (kWave - 1);
@@ -527,46 +520,79 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   const int p = blockIdx.x * kPpb + pb;
   const bool active = p < n_total;
   const int n_dof = a.n_dof, n_seg = a.n_seg, n_prim = a.n_prim;
+  const DevModel* __restrict__ G = a.model;
+  // Every load that depends on the particle alone is issued first, together and with clamped
+  // indices (a load behind a branch, or issued after another whose result is awaited, adds a
+  // memory latency to this latency-bound kernel): this lane's pose parameter, the frame's
+  // slot and stop flag, the candidate's active flag and this lane's collision pair.
+  const int pc = min(p, n_total - 1);
+  const int f = pc / a.n_particles;
+  const float x_lane = a.poses[(size_t)pc * n_dof + min(lane, n_dof - 1)];
+  const int slot_raw = a.frame_slots[f];
+  const int stop_raw = a.frame_stop ? a.frame_stop[f] : 0;
+  const int act_raw = a.active ? a.active[pc / a.active_div] : 1;
+  const int kc_i = max(lane - (kWave - HT_MAX_KC), 0);
+  const int kc_a = G->kc_a[kc_i], kc_b = G->kc_b[kc_i];
+  // the kinematic tables (everything before the primitive tables), staged by one coalesced
+  // copy with all its loads in flight at once: the tree walk would otherwise wait on long
+  // chains of dependent global loads.  The primitive tables are read from global memory by the
+  // lane that sets a primitive up, issued here so that their latency overlaps the
+  // trigonometry and the tree walk.
+  constexpr int kSegBytes = ((int)offsetof(DevModel, prim_type) + 15) / 16 * 16;
+  static_assert(kSegBytes <= (int)sizeof(DevModel), "copy stays inside the model");
+  __shared__ __align__(16) unsigned char s_model[kSegBytes];
+  {
+    constexpr int kN = kSegBytes / 16, kIt = (kN + kBlock - 1) / kBlock;
+    const uint4* src4 = reinterpret_cast<const uint4*>(a.model);
+    uint4* dst4 = reinterpret_cast<uint4*>(s_model);
+    uint4 v[kIt];
+#pragma unroll
+    for (int j = 0; j < kIt; ++j) v[j] = src4[min((int)threadIdx.x + j * kBlock, kN - 1)];
+#pragma unroll
+    for (int j = 0; j < kIt; ++j)
+      if ((int)threadIdx.x + j * kBlock < kN) dst4[threadIdx.x + j * kBlock] = v[j];
+  }
+  // only the members before prim_type may be read through M
+  const DevModel& M = *reinterpret_cast<const DevModel*>(s_model);
   __shared__ int s_fin[kWavesPerBlock];
   PrimIn pin0;
   if (active && lane + h * kWave < n_prim) load_prim(G, lane + h * kWave, pin0);
 
-  // every angle's sine and cosine at once (one lane per pose parameter), so the tree walk
-  // below is trigonometry-free
+  // every angle's sine and cosine at once (one lane per pose parameter, n_dof <= 64), so the
+  // tree walk below is trigonometry-free
+  static_assert(HT_MAX_DOF <= kWave, "one lane per pose parameter");
   bool finite = true;
-  if (active && h == 0) {
-    for (int i = lane; i < n_dof; i += kWave) {
-      const float x = a.poses[(size_t)p * n_dof + i];
-      s_h[pb][i] = (double)x;
-      finite = finite && isfinite(x);
-      double sv = 0.0, cv = 1.0;
-      if (isfinite(x)) sincos((double)x, &sv, &cv);
-      s_sin[pb][i] = sv;
-      s_cos[pb][i] = cv;
-    }
+  if (active && h == 0 && lane < n_dof) {
+    const float x = x_lane;
+    s_h[pb][lane] = (double)x;
+    finite = isfinite(x);
+    double sv = 0.0, cv = 1.0;
+    if (finite) sincos((double)x, &sv, &cv);
+    s_sin[pb][lane] = sv;
+    s_cos[pb][lane] = cv;
   }
   finite = __ballot(!finite) == 0ull;
   if (h == 0 && lane == 0) s_fin[pb] = finite ? 1 : 0;
-  int slot = -1;
-  if (active) slot = a.frame_slots[p / a.n_particles];
+  const int slot = active ? slot_raw : -1;
   const bool slot_ok = active && slot >= 0 && slot < HT_MAX_SLOTS && a.slots[slot].set;
   if (active && !slot_ok && h == 0 && lane == 0 && a.dev_errors)
     atomicOr(a.dev_errors, HT_DEVERR_UNSET_SLOT);
   // a particle of a stopped frame (tracking stop rule), or a candidate of a refined particle
   // that has stopped refining, is neither cast nor written
-  const bool skip = active && ((a.frame_stop && a.frame_stop[p / a.n_particles] != 0) ||
-                               (a.active && a.active[p / a.active_div] == 0));
-  // the slot's background sums, needed only by the record written at the end
-  double bg_td = 0.0, bg_or = 0.0;
-  if (slot_ok && h == 0) {
-    const double* tot = a.slots[slot].totals;
-    bg_td = tot[0];
-    bg_or = tot[1];
-  }
+  const bool skip = active && (stop_raw != 0 || act_raw == 0);
   __syncthreads();
   // the first wavefront's finiteness test, for every wavefront of the particle
   if (WPP > 1) finite = __builtin_amdgcn_readfirstlane(s_fin[pb]) != 0;
   const bool valid = slot_ok && finite && !skip;
+  // the slot's background sums, needed only by the record written at the end: loaded after
+  // the barrier as global loads (which no barrier waits for), so that their two dependent
+  // latencies overlap the tree walk
+  double bg_td = 0.0, bg_or = 0.0;
+  if (slot_ok && h == 0) {
+    const double* tot = a.slots[slot].totals;
+    bg_td = global_ptr(tot)[0];
+    bg_or = global_ptr(tot)[1];
+  }
 
   // segment transforms, T_s = W L_root ... L_parent(s) L_s with L_s = Off_s Rot(a1, q1)
   // Rot(a2, q2) and W the wrist of s's tree: every lane forms its own L_s once and stages it
@@ -678,7 +704,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   __shared__ double s_kc[kWavesPerBlock][HT_MAX_KC];
   if (valid && h == 0 && lane >= kWave - HT_MAX_KC && lane - (kWave - HT_MAX_KC) < M.n_kc) {
     const int i = lane - (kWave - HT_MAX_KC);
-    s_kc[pb][i] = fmax(-(s_h[pb][G->kc_a[i]] - s_h[pb][G->kc_b[i]]), 0.0);
+    s_kc[pb][i] = fmax(-(s_h[pb][kc_a] - s_h[pb][kc_b]), 0.0);
   }
   __syncthreads();
 
@@ -1345,14 +1371,6 @@ __device__ __forceinline__ FrameSlot uni(const FrameSlot& f) {
   u.totals = uni(f.totals);
   u.grad_mask = uni(f.grad_mask);
   return u;
-}
-
-// A pointer read from memory (a FrameSlot field) is generic to the compiler, and generic
-// loads count against the LDS counter too, so every LDS wait would also wait for them; these
-// buffers are device memory, so their loads are issued as global loads.
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
-  return (const __attribute__((address_space(1))) T*)p;
 }
 
 // Walks a particle's tiles (the union of its rectangles, each row-major) in steps of the
