@@ -2028,19 +2028,22 @@ __device__ bool assemble_wave(const EvalArgs& a, const Workspace& ws, int p, boo
   }
   cost = cost_from_sums(S_d, S_and, S_or, pi.kc);
   if (!grad) return true;
-  // wrench rows summed in item order (lane l: values l, l + 64, l + 128), four items' loads in
-  // flight at a time (indices clamped into the particle's items; past the end adds zero)
+  // wrench rows summed in item order (lane l: values l, l + 64, l + 128), kAsmItems items'
+  // loads in flight at a time (indices clamped into the particle's items; past the end adds
+  // zero): each round is one memory latency, and small gradient launches give a particle
+  // some 30 items
+  constexpr int kAsmItems = 16;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int i0 = b; i0 < e; i0 += 4) {
-    float v[4][3];
+  for (int i0 = b; i0 < e; i0 += kAsmItems) {
+    float v[kAsmItems][3];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kAsmItems; ++u) {
       const float* src = ws.wrench + (size_t)min(i0 + u, e - 1) * nv;
 #pragma unroll
       for (int k = 0; k < 3; ++k) v[u][k] = src[min(lane + k * kWave, nv - 1)];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kAsmItems; ++u)
 #pragma unroll
       for (int k = 0; k < 3; ++k)
         acc[k] += (i0 + u < e && lane + k * kWave < nv) ? (double)v[u][k] : 0.0;
