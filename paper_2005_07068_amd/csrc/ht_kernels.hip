@@ -1889,33 +1889,31 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
   const float org_v = t < n_seg * 4 ? ws.seg_org[(size_t)ps * n_seg * 4 + t] : 0.0f;
   const int kc_i = t < HT_MAX_KC ? t : 0;
   const int kca_v = a.model->kc_a[kc_i], kcb_v = a.model->kc_b[kc_i];
-  // wave q sums items b+q, b+q+4, ... (two at a time, loads first); lane l sums values l,
-  // l+64, l+128; then the four partial sums are added in a fixed order
+  // wave q sums items b+q, b+q+4, ... (kFinItems at a time, loads first); lane l sums values
+  // l, l+64, l+128; then the four partial sums are added in a fixed order
   const int nv = n_seg * 6, lane = t & (kWave - 1);
   const int q = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform
   // the first partials, for the second wavefront's cost sums below; loaded by every wavefront
   // (unconditionally, so that no branch waits on them), issued with the wrench loads
   const Partial pr0 = first_partial(ws, b, e, lane);
+  constexpr int kFinItems = 4;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int i = b + q; i < e; i += 2 * kWavesPerBlock) {
-    const bool two = i + kWavesPerBlock < e;
-    const float* s0 = ws.wrench + (size_t)i * nv;
-    const float* s1 = two ? s0 + (size_t)kWavesPerBlock * nv : s0;
-    // the six loads are unconditional (offsets clamped into the item), so they are in flight
-    // together; lanes past nv add zero
-    float v0[3], v1[3];
+  for (int i = b + q; i < e; i += kFinItems * kWavesPerBlock) {
+    // the loads are unconditional (items and offsets clamped into the particle's), so they are
+    // in flight together; items past the end and lanes past nv add zero
+    float v[kFinItems][3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int o = min(lane + k * kWave, nv - 1);
-      v0[k] = s0[o];
-      v1[k] = s1[o];
+    for (int u = 0; u < kFinItems; ++u) {
+      const float* src = ws.wrench + (size_t)min(i + u * kWavesPerBlock, e - 1) * nv;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[u][k] = src[min(lane + k * kWave, nv - 1)];
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const bool in = lane + k * kWave < nv;
-      acc[k] += in ? (double)v0[k] : 0.0;
-      if (two) acc[k] += in ? (double)v1[k] : 0.0;
-    }
+    for (int u = 0; u < kFinItems; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (i + u * kWavesPerBlock < e)
+          acc[k] += lane + k * kWave < nv ? (double)v[u][k] : 0.0;
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k)
