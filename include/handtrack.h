@@ -319,7 +319,8 @@ ht_status ht_set_launch_config(ht_ctx* ctx, const ht_launch_config* cfg);
 /* Autotune the launch shape on the given workload (timed with HIP events on hip_stream,
  * synchronising it), keep the fastest in the context and return it in *out.
  * The candidates are tiles_per_item in {4..64} x groups_per_cu in {1..8} (powers of two) x
- * cull in {0, 1}. */
+ * cull in {0, 1}, tried from cull 1, 64 tiles and 8 workgroups down; a candidate must be more
+ * than 1 % faster than the best before it to replace it. */
 ht_status ht_autotune(ht_ctx* ctx, int n_frames, const int32_t* frame_slots, int n_particles,
                       const float* poses, float* cost, int repeats, ht_launch_config* out,
                       void* hip_stream);
