@@ -1949,21 +1949,32 @@ __global__ __launch_bounds__(kBlock) void finalize_grad_kernel(EvalArgs a, Works
     const bool trans = f[0] != 0.0f;
     const double ax = f[1], ay = f[2], az = f[3];
     double g = 0.0;
-    // the segments this parameter moves, in increasing order
-    for (uint32_t m = desc; m; m &= m - 1) {
-      const int s = __builtin_ctz(m);
-      const double* W = s_W + s * 6;
-      if (trans) {
-        g += ax * W[3] + ay * W[4] + az * W[5];
-      } else {
-        const double lx = (double)org[s * 4 + 0] - f[4];
-        const double ly = (double)org[s * 4 + 1] - f[5];
-        const double lz = (double)org[s * 4 + 2] - f[6];
+    // the segments this parameter moves, in increasing order, four per round (their LDS reads
+    // issued together)
+    for (uint32_t m = desc; m;) {
+      int sg[4];
+      bool has[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        has[q] = m != 0u;
+        sg[q] = has[q] ? __builtin_ctz(m) : 0;
+        m &= m - 1u;
+      }
+      double t[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double* W = s_W + sg[q] * 6;
+        const double lx = (double)org[sg[q] * 4 + 0] - f[4];
+        const double ly = (double)org[sg[q] * 4 + 1] - f[5];
+        const double lz = (double)org[sg[q] * 4 + 2] - f[6];
         const double mx = W[0] + (ly * W[5] - lz * W[4]);
         const double my = W[1] + (lz * W[3] - lx * W[5]);
         const double mz = W[2] + (lx * W[4] - ly * W[3]);
-        g += ax * mx + ay * my + az * mz;
+        t[q] = trans ? ax * W[3] + ay * W[4] + az * W[5] : ax * mx + ay * my + az * mz;
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (has[q]) g += t[q];
     }
     g *= s_inv_or;
     // collision term of Eq. 5: the pairs whose term is positive (recorded by the kinematics)
@@ -2061,20 +2072,34 @@ __device__ bool assemble_wave(const EvalArgs& a, const Workspace& ws, int p, boo
     const bool trans = f0.x != 0.0f;
     const double ax = f0.y, ay = f0.z, az = f0.w;
     double acc_g = 0.0;
-    for (uint32_t m = desc; m; m &= m - 1) {
-      const int sg = __builtin_ctz(m);
-      const double* Ws = W + sg * 6;
-      if (trans) {
-        acc_g += ax * Ws[3] + ay * Ws[4] + az * Ws[5];
-      } else {
-        const double lx = (double)org[sg * 4 + 0] - f1.x;
-        const double ly = (double)org[sg * 4 + 1] - f1.y;
-        const double lz = (double)org[sg * 4 + 2] - f1.z;
+    // the segments this parameter moves, in increasing order, kAdjRound per round: their LDS
+    // reads are issued together (one segment per round waited on the reads of each in turn;
+    // eight per round measured no faster than four)
+    constexpr int kAdjRound = 4;
+    for (uint32_t m = desc; m;) {
+      int sg[kAdjRound];
+      bool has[kAdjRound];
+#pragma unroll
+      for (int q = 0; q < kAdjRound; ++q) {
+        has[q] = m != 0u;
+        sg[q] = has[q] ? __builtin_ctz(m) : 0;
+        m &= m - 1u;
+      }
+      double t[kAdjRound];
+#pragma unroll
+      for (int q = 0; q < kAdjRound; ++q) {
+        const double* Ws = W + sg[q] * 6;
+        const double lx = (double)org[sg[q] * 4 + 0] - f1.x;
+        const double ly = (double)org[sg[q] * 4 + 1] - f1.y;
+        const double lz = (double)org[sg[q] * 4 + 2] - f1.z;
         const double mx = Ws[0] + (ly * Ws[5] - lz * Ws[4]);
         const double my = Ws[1] + (lz * Ws[3] - lx * Ws[5]);
         const double mz = Ws[2] + (lx * Ws[4] - ly * Ws[3]);
-        acc_g += ax * mx + ay * my + az * mz;
+        t[q] = trans ? ax * Ws[3] + ay * Ws[4] + az * Ws[5] : ax * mx + ay * my + az * mz;
       }
+#pragma unroll
+      for (int q = 0; q < kAdjRound; ++q)
+        if (has[q]) acc_g += t[q];
     }
     acc_g *= inv_or;
     for (int m = pi.kc_mask; m; m &= m - 1) {
@@ -2097,6 +2122,19 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(EvalArgs a, Works
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = blockIdx.x;                       // refined particle (frame * K + rank)
   const int n_dof = ra.n_dof;
+  const bool on = lane < n_dof;
+  const int d = on ? lane : 0;
+  const size_t xi = (size_t)r * n_dof + d;
+  // the inputs of wavefront 0's decisions below, loaded before the assembly so that their
+  // latency overlaps it (no kernel writes them meanwhile; this one writes them only after
+  // reading them); buffers a mode does not use are allocated, their values unused
+  const int act_in = ra.active[r];
+  const float x_in = ra.rx[xi], c_in = ra.rcost[r], g_in = ra.grad[xi];
+  float cx_in[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) cx_in[j] = ra.cand[((size_t)r * 4 + j) * n_dof + d];
+  const int trans_in = a.model->dof_trans[d];
+  const float lo_in = a.model->lo[d], hi_in = a.model->hi[d];
   // 1. the preceding evaluation: the particle itself (propose only), else its candidates
   const bool mine = ra.op.accept ? true : w == 0;
   if (mine) {
@@ -2108,11 +2146,8 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(EvalArgs a, Works
   }
   __syncthreads();
   if (w != 0) return;
-  const bool on = lane < n_dof;
-  const int d = on ? lane : 0;
-  const size_t xi = (size_t)r * n_dof + d;
-  bool act = ra.active[r] != 0;
-  float x = ra.rx[xi];
+  bool act = act_in != 0;
+  float x = x_in;
   float c, gd;
   if (!ra.op.accept) {
     // the gradient evaluation of the selected particle: its cost and gradient
@@ -2121,8 +2156,8 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(EvalArgs a, Works
     if (on) ra.grad[xi] = gd;
     if (lane == 0) ra.rcost[r] = c;
   } else {
-    c = ra.rcost[r];
-    gd = ra.grad[xi];
+    c = c_in;
+    gd = g_in;
   }
   if (ra.op.accept && act) {
     // the four candidates' costs (a skipped one counts as +inf) and positions
@@ -2130,7 +2165,7 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(EvalArgs a, Works
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       cc[j] = s_cost[j];
-      cx[j] = ra.cand[((size_t)r * 4 + j) * n_dof + d];
+      cx[j] = cx_in[j];
     }
     int pick = -1;
 #pragma unroll
@@ -2160,7 +2195,7 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(EvalArgs a, Works
     }
   }
   if (ra.op.propose) {
-    const float eta = a.model->dof_trans[d] ? ra.eta_trans : ra.eta_rot;
+    const float eta = trans_in ? ra.eta_trans : ra.eta_rot;
     const float gs = on ? eta * gd : 0.0f;
     float gmax = fabsf(gs);
     bool fin = isfinite(gs);
@@ -2175,7 +2210,7 @@ __global__ __launch_bounds__(kBlock) void refine_update_kernel(EvalArgs a, Works
         float xn = x;
         if (ok) {
           const float step = eta * (gs / gmax) * ldexpf(1.0f, -j);
-          xn = fminf(fmaxf(x - step, a.model->lo[d]), a.model->hi[d]);
+          xn = fminf(fmaxf(x - step, lo_in), hi_in);
         }
         ra.cand[((size_t)r * 4 + j) * n_dof + d] = xn;
       }
