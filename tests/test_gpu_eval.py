@@ -232,6 +232,42 @@ def test_launch_shapes_and_autotuner_keep_costs_bit_identical():
     ctx.close()
 
 
+def test_work_lists_built_in_the_ray_cast_and_by_the_work_list_kernel_agree():
+    """Launches of at most 256 particles build their work list inside the ray cast (items in a
+    static stride, at most six workgroups per CU); larger ones take the work-list kernel's list
+    and the dequeue counter.  The same particles evaluated in one launch of 300, in launches of
+    256 + 44 and of 150 + 150 (and with debug images, which always take the work-list kernel)
+    get bit-identical costs, and the device counts every evaluation once; gradients (FP32
+    wrench rows summed per item, items cut differently) agree to 1e-5 of the largest
+    component."""
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(4)
+    P = 300
+    poses = particles_for(model, fr, P, seed=21)
+    ctx = make_ctx(model, [fr])
+    dev = torch.device("cuda:0")
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    x = torch.tensor(poses, device=dev)
+    ctx.eval_counts(reset=True)
+    whole = ctx.eval(x, slots).cpu().numpy()
+    for cut in (256, 150):
+        parts = np.concatenate([ctx.eval(x[:cut], slots).cpu().numpy(),
+                                ctx.eval(x[cut:], slots).cpu().numpy()])
+        assert np.array_equal(parts, whole), cut
+    assert ctx.eval_counts(reset=True) == (3 * P, 0)
+    H, W = fr["depth"].shape
+    c_dbg, _ = eval_debug(ctx, poses[:40], 0, W, H)
+    assert np.array_equal(c_dbg, whole[:40])
+    c_all, g_all = ctx.eval_grad(x, slots)
+    c_cut = torch.cat([ctx.eval_grad(x[:256], slots)[0], ctx.eval_grad(x[256:], slots)[0]])
+    g_cut = torch.cat([ctx.eval_grad(x[:256], slots)[1], ctx.eval_grad(x[256:], slots)[1]])
+    assert np.array_equal(c_all.cpu().numpy(), whole) and torch.equal(c_cut, c_all)
+    g_all, g_cut = g_all.cpu().numpy(), g_cut.cpu().numpy()
+    scale = np.max(np.abs(g_all), axis=1, keepdims=True)
+    assert np.all(np.abs(g_cut - g_all) <= 1e-5 * scale)
+    ctx.close()
+
+
 def test_depth_error_against_the_ray_surface_margin():
     """The worst GPU depth error on hit pixels, binned by the oracle's margin of the winning
     primitive (m; dimensionless, 0 at the silhouette): FP32 conditioning grows like
