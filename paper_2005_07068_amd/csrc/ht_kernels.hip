@@ -702,9 +702,13 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
   }
   // collision terms of Eq. 5, one per spare lane (summed in order below)
   __shared__ double s_kc[kWavesPerBlock][HT_MAX_KC];
-  if (valid && h == 0 && lane >= kWave - HT_MAX_KC && lane - (kWave - HT_MAX_KC) < M.n_kc) {
+  // (every pair slot is written, zero past the model's pairs, so the record below sums all of
+  // them without a branch per slot)
+  if (valid && h == 0 && lane >= kWave - HT_MAX_KC) {
     const int i = lane - (kWave - HT_MAX_KC);
-    s_kc[pb][i] = fmax(-(s_h[pb][kc_a] - s_h[pb][kc_b]), 0.0);
+    double v = 0.0;
+    if (i < M.n_kc) v = fmax(-(s_h[pb][kc_a] - s_h[pb][kc_b]), 0.0);
+    s_kc[pb][i] = v;
   }
   __syncthreads();
 
@@ -938,10 +942,9 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
     int kc_mask = 0;
     if (valid) {
       // the terms are differences of FP32 values: their FP64 sum is exact in any order
-      const int n_kc = __builtin_amdgcn_readfirstlane(M.n_kc);
 #pragma unroll
       for (int i = 0; i < HT_MAX_KC; ++i) {
-        const double v = i < n_kc ? s_kc[pb][i] : 0.0;
+        const double v = s_kc[pb][i];
         kc += v;
         kc_mask |= v > 0.0 ? 1 << i : 0;
       }
