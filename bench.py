@@ -37,8 +37,8 @@ METRIC = "particle evals/s (render+cost, +adjoint) and ms/frame vs plain PSO at 
 # FP32 operations (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes).  Keyed by the SHA-256 of the kernel
 # sources they were measured on: any later change of the kernel reports null.
 MEASURED_COUNTERS = {
-    "1c3f5732e5091253a3d8aeb66f6b0ab11a4267a5de2b9a52ee9ddaa8e4476f8b": {
-        "config": 4, "fetch_kib": 9473.339, "write_kib": 237.107, "fetch_scale": 2.0,
+    "dbc5592a0807ff31e24c771a061b596160d5772da431205603ffab1e88a172d5": {
+        "config": 4, "fetch_kib": 9473.201, "write_kib": 237.068, "fetch_scale": 2.0,
         "write_scale": 1.0, "fp32_flop": 2.232e9},
 }
 KERNEL_SOURCES = ("paper_2005_07068_amd/csrc/ht_kernels.hip",
