@@ -1468,7 +1468,10 @@ __device__ void self_schedule(const EvalArgs& a, const Workspace& ws, int* s_off
   if (t == 0) s_off[0] = 0;
   __syncthreads();
   total = total_items;
-  interleave = a.grad && total_items <= 2 * a.grid;
+  // items in a static stride, about one per workgroup: interleaved tiles, so that every item
+  // samples the whole hand (runs of consecutive tiles left the launch waiting on the items
+  // from the hand's middle: 128 forward candidates 26.7 -> 24.1 us)
+  interleave = total_items <= 2 * a.grid;
   if (blockIdx.x == 0) {
     // n_total + 1 offsets: one per thread, the end offset by thread 0
     if (t < n_total) ws.item_off[t] = s_off[t];
