@@ -1550,7 +1550,11 @@ __global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace w
       item = xcd_major_item(blockIdx.x, gridDim.x);
       first = false;
     } else if constexpr (SELF) {
+      // the next item in the static stride; the barrier keeps its per-wavefront LDS sums
+      // clear of the previous item's (whose readers may still be at work when both items
+      // belong to one particle and so no staging barrier follows)
       item += gridDim.x;
+      __syncthreads();
     } else {
       if (tid == 0) s_item = (int)gridDim.x + atomicAdd(&ws.counters[0], 1);
       __syncthreads();

@@ -268,6 +268,45 @@ def test_work_lists_built_in_the_ray_cast_and_by_the_work_list_kernel_agree():
     ctx.close()
 
 
+def test_self_scheduled_workgroup_with_two_items_of_one_particle():
+    """A self-scheduled launch gives workgroup g the items g, g + grid, ...; with one workgroup
+    per CU, four tiles per item and a hand that covers more than four tiles per CU (a three
+    times upsampled 1920x1440 observation, focal lengths tripled) a workgroup takes two items of the
+    same particle back to back, with no staging between them.  Its cost equals, bit for bit,
+    the one the work-list kernel's launch (300 copies of the particle) and the debug launch
+    give; the gradient agrees to 1e-5 of its largest component."""
+    torch = torch_cuda()
+    cfg, model, fr = frame_for(4)
+    pose = particles_for(model, fr, 1, seed=21)
+    up = 3
+    depth = np.repeat(np.repeat(fr["depth"], up, axis=0), up, axis=1)
+    skin = np.repeat(np.repeat(fr["skin"], up, axis=0), up, axis=1)
+    fx, fy, cx, cy = (float(c) for c in fr["cam"])
+    # pixel u of the source image is pixels up u .. up u + up - 1 here (centre up u + 1)
+    cam = (up * fx, up * fy, up * cx + (up - 1) / 2, up * cy + (up - 1) / 2)
+    ctx = make_ctx(model, [dict(fr, depth=depth, skin=skin, cam=cam)])
+    ctx.set_launch_config(4, 1, 1)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    H, W = depth.shape
+    c_dbg, dbg = eval_debug(ctx, pose, 0, W, H)
+    hit = dbg["hit"][0] == 1
+    hit_tiles = hit[:H // 8 * 8, :W // 8 * 8].reshape(H // 8, 8, W // 8, 8).any(axis=(1, 3))
+    # more than 4 n_cu tiles in the hand's region: more items of 4 tiles than workgroups
+    assert hit_tiles.sum() > 4 * n_cu, (hit_tiles.sum(), n_cu)
+    dev = torch.device("cuda:0")
+    slots = torch.zeros(1, dtype=torch.int32, device=dev)
+    x1 = torch.tensor(pose, device=dev)
+    x300 = x1.expand(300, -1).contiguous()
+    one = ctx.eval(x1, slots).cpu().numpy()
+    many = ctx.eval(x300, slots).cpu().numpy()
+    assert np.array_equal(one, c_dbg) and np.all(many == one[0])
+    g1 = ctx.eval_grad(x1, slots)[1].cpu().numpy()
+    g300 = ctx.eval_grad(x300, slots)[1].cpu().numpy()
+    scale = np.max(np.abs(g300[0]))
+    assert scale > 0 and np.all(np.abs(g300 - g1[0]) <= 1e-5 * scale)
+    ctx.close()
+
+
 def test_depth_error_against_the_ray_surface_margin():
     """The worst GPU depth error on hit pixels, binned by the oracle's margin of the winning
     primitive (m; dimensionless, 0 at the silhouette): FP32 conditioning grows like
