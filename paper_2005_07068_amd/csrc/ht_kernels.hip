@@ -1039,6 +1039,9 @@ __global__ __launch_bounds__(kBlock) void debug_fill_kernel(ht_debug dbg, size_t
 // centre, which is accurate because d is exact and the centre is a double-float pair; the
 // hit decision and the half-chord then come from small, well-conditioned quantities.
 
+// A test may report a miss as ok with a NaN entry (the half-chord of a ray that misses is the
+// square root of a negative number): the caller compares entries as unsigned integers, and a
+// NaN's bit pattern exceeds +inf's, so such an entry is never taken.
 struct Hit {
   float t;        // ray parameter of the entry point
   bool ok;
@@ -1071,8 +1074,8 @@ __device__ __forceinline__ void sphere_test(const float* r, float dx, float dy, 
   const float vz = fmaf(t0, dz, -r[2]) - r[6];
   const float rho2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
   const float h2 = r[3] - rho2;
-  h.ok = h2 >= 0.0f;
-  const float hs = fast_sqrt(fmaxf(h2, 0.0f) * inv_dd);
+  h.ok = true;   // a miss (h2 < 0) has a NaN entry
+  const float hs = fast_sqrt(h2 * inv_dd);
   h.t = t0 - hs;
   if (MRG) h.m = h2 / r[3];
   if (GRAD) {
@@ -1107,8 +1110,8 @@ __device__ __forceinline__ void ellipsoid_test(const float* r, float dx, float d
   const float B = fmaf(vx, qdx, fmaf(vy, qdy, vz * qdz));
   const float cc = -B * inv;
   const float m = fmaf(B, B * inv, 1.0f - fmaf(vx, qvx, fmaf(vy, qvy, vz * qvz)));
-  h.ok = m >= 0.0f;
-  const float tin = cc - fast_sqrt(fmaxf(m, 0.0f) * inv);
+  h.ok = true;   // a miss (m < 0) has a NaN entry
+  const float tin = cc - fast_sqrt(m * inv);
   h.t = t0 + tin;
   if (MRG) h.m = m;
   if (GRAD) {
@@ -1124,6 +1127,25 @@ __device__ __forceinline__ void ellipsoid_test(const float* r, float dx, float d
 // Closed cylinder as the intersection of the infinite cylinder and the slab 0 <= s <= L:
 // both intervals are expressed as offsets from the reference parameter t_r (the closest
 // approach to the axis), so the hit test compares small accurate numbers.
+//
+// Margin of the cylinder at one pixel (debug images): offsets tau from t_r, radius^2 at tau
+// is rho2 + 2 tau B + tau^2 A, axial coordinate a3 + tau da.
+__device__ __forceinline__ float cylinder_margin(const float* r, bool par, float A, float B,
+                                                 float rho2, float h2, float invA, float cc,
+                                                 float a3, float da, float inv_da) {
+  const float L = r[7];
+  const float ir2 = 1.0f / r[3];
+  const float hsf = fast_sqrt(fmaxf(h2, 0.0f) * invA);
+  const float sa = fmaf(cc - hsf, da, a3), sb = fmaf(cc + hsf, da, a3);
+  const float c0 = -a3 * inv_da, c1 = (L - a3) * inv_da;
+  const float q0 = fmaf(c0, fmaf(c0, A, 2.0f * B), rho2);
+  const float q1 = fmaf(c1, fmaf(c1, A, 2.0f * B), rho2);
+  const bool axial = da != 0.0f;
+  return capped_margin(par ? -INFINITY : h2 * ir2, !par && h2 >= 0.0f, sa, sb, L,
+                       axial ? (r[3] - q0) * ir2 : -INFINITY,
+                       axial ? (r[3] - q1) * ir2 : -INFINITY);
+}
+
 template <bool GRAD, bool MRG = false>
 __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy, float dz,
                                               float dd, Hit& h) {
@@ -1135,6 +1157,49 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   const float inv_da = fast_rcp(da);
   const float invA = fast_rcp(A);
   const float t_side = fmaf(px, r[0], fmaf(py, r[1], pz * r[2])) * invA;
+  {
+    // every lane first as if its ray were not near-parallel to the axis: the side-centred
+    // reference, and a miss of the side surface (h2 < 0) gives a NaN half-chord, which fails
+    // both interval comparisons.  The values equal the general path's for such lanes.
+    const float tr = t_side;
+    const float vx = fmaf(tr, dx, -r[0]) - r[4];
+    const float vy = fmaf(tr, dy, -r[1]) - r[5];
+    const float vz = fmaf(tr, dz, -r[2]) - r[6];
+    const float a3 = fmaf(vx, ux, fmaf(vy, uy, vz * uz));
+    const float wx = fmaf(-a3, ux, vx), wy = fmaf(-a3, uy, vy), wz = fmaf(-a3, uz, vz);
+    const float rho2 = fmaf(wx, wx, fmaf(wy, wy, wz * wz));
+    const float B = fmaf(wx, px, fmaf(wy, py, wz * pz));
+    const float cc = -B * invA;
+    const float h2 = fmaf(B, B * invA, r[3] - rho2);
+    const float hs = fast_sqrt(h2 * invA);
+    const float d0 = -a3 * inv_da, d1 = (L - a3) * inv_da;
+    const float din = fminf(d0, d1), dout = fmaxf(d0, d1);
+    const float s_in = cc - hs, s_out = cc + hs;
+    h.ok = (s_in <= dout) & (din <= s_out);
+    const float tin = fmaxf(s_in, din);
+    {
+      // a plain sum, as on the general path (where t_r is a select): not fused with t_r's
+      // product
+#pragma clang fp contract(off)
+      h.t = tr + tin;
+    }
+    if (MRG) h.m = cylinder_margin(r, false, A, B, rho2, h2, invA, cc, a3, da, inv_da);
+    if (GRAD) {
+      const bool cap = din > s_in;
+      h.rx = fmaf(tin, dx, vx);
+      h.ry = fmaf(tin, dy, vy);
+      h.rz = fmaf(tin, dz, vz);
+      const float sgn = da > 0.0f ? -1.0f : 1.0f;
+      h.nx = cap ? sgn * ux : fmaf(tin, px, wx);
+      h.ny = cap ? sgn * uy : fmaf(tin, py, wy);
+      h.nz = cap ? sgn * uz : fmaf(tin, pz, wz);
+    }
+  }
+  // a near-parallel ray (its pixel lies within about half a pixel of the image of the axis's
+  // vanishing point, so few wavefronts ever have one) sends the wavefront down the general
+  // path, which recomputes every lane
+  if (__builtin_expect(__ballot(par) == 0ull, 1)) return;
+  // general path: near-parallel rays take the reference at the slab's middle
   const float t_mid = r[17] * inv_da;                    // r[17] = r[11] + L / 2
   const float tr = par ? t_mid : t_side;
   const float vx = fmaf(tr, dx, -r[0]) - r[4];
@@ -1161,19 +1226,7 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   const float tin = fmaxf(cc - hs, din), tout = fminf(cc + hs, dout);
   h.ok = (h2 >= 0.0f) & (tin <= tout);
   h.t = tr + tin;
-  if (MRG) {
-    // offsets tau from t_r: radius^2 at tau is rho2 + 2 tau B + tau^2 A, axial s = a3 + tau da
-    const float ir2 = 1.0f / r[3];
-    const float hsf = fast_sqrt(fmaxf(h2, 0.0f) * invA);
-    const float sa = fmaf(cc - hsf, da, a3), sb = fmaf(cc + hsf, da, a3);
-    const float c0 = -a3 * inv_da, c1 = (L - a3) * inv_da;
-    const float q0 = fmaf(c0, fmaf(c0, A, 2.0f * B), rho2);
-    const float q1 = fmaf(c1, fmaf(c1, A, 2.0f * B), rho2);
-    const bool axial = da != 0.0f;
-    h.m = capped_margin(par ? -INFINITY : h2 * ir2, !par && h2 >= 0.0f, sa, sb, L,
-                        axial ? (r[3] - q0) * ir2 : -INFINITY,
-                        axial ? (r[3] - q1) * ir2 : -INFINITY);
-  }
+  if (MRG) h.m = cylinder_margin(r, par, A, B, rho2, h2, invA, cc, a3, da, inv_da);
   if (GRAD) {
     // entry point relative to p0 and the outward normal of the entry surface
     const bool cap = din > cc - hs;

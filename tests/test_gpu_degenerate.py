@@ -121,3 +121,49 @@ def test_gradient_of_a_hypothesis_that_renders_nothing():
     assert np.array_equal(g, ref.astype(np.float32))
     E = ocost.objective(model, h.astype(np.float64), fr)
     assert abs(c.cpu().numpy()[0] - E) <= 1e-5 * E
+
+
+@pytest.mark.parametrize("tilt", [0.0, 4e-4, -7e-4])
+def test_cylinder_seen_along_its_axis(tilt):
+    """A cylinder whose axis runs along the optical axis, 2-3 mm off it, so that the principal
+    point's ray (and, tilted by a fraction of a milliradian, a ray next to it) lies within
+    1e-3 rad of the axis: such rays take the slab-centred reference and the side test at the
+    slab's middle, and their wavefront takes the general path.  Depths, masks and costs
+    against the FP64 oracle; the principal point's pixel hits the near cap."""
+    from oracle import fk, raycast
+    from workload import CYLINDER, make_hand_model, seed_sequence
+    torch_cuda()
+    m = make_hand_model(seed_sequence(0, 4243), 1)
+    m = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in m.items()}
+    m["n_prim"] = 1
+    m["prim_type"] = np.array([CYLINDER], np.int32)
+    m["prim_seg"] = np.zeros(1, np.int32)
+    frame = np.zeros((1, 3, 4))
+    frame[0, :, :3] = np.eye(3)
+    frame[0, :, 3] = (2.0, -3.0, 0.0)
+    m["prim_frame"] = frame
+    m["prim_size"] = np.array([[9.0, 30.0, 0.0]])
+    W, H = 96, 64
+    # pixel (48, 32) looks along the optical axis, its neighbours 1e-3 rad off it; the
+    # cylinder's image is a disc of about 950 pixels
+    cam = (1000.0, 1000.0, 48.0, 32.0)
+    h = np.zeros(26)
+    h[22] = 520.0
+    h[23] = tilt
+    rng = np.random.default_rng(6)
+    res = raycast.render(m, h, W, H, cam, 1500.0)
+    depth, skin = synth.observe(res, rng)
+    fr = {"depth": depth, "skin": skin, "cam": cam, "bg": 1500.0, "h_true": h}
+    # what the test exercises: hit pixels whose rays lie within 1e-3 rad of the axis
+    cyl = fk.camera_primitives(m, h)[0]
+    d = raycast.pixel_directions(W, H, cam)
+    cos = (d @ cyl["R"][:, 2]) / np.linalg.norm(d, axis=-1)
+    near = res["hit"] & (np.sqrt(np.maximum(1.0 - cos ** 2, 0.0)) < 1e-3)
+    assert near[32, 48] and near.sum() >= 1
+    poses = [h.astype(np.float32), _away(m, h, dx=1.0), _away(m, h, dz=-40.0)]
+    ctx = make_ctx(m, [fr])
+    cost, dbg = eval_debug(ctx, poses, 0, W, H)
+    ctx.close()
+    for i in range(len(poses)):
+        check_particle(m, fr, poses[i], cost[i], dbg, i)
+    assert dbg["hit"][0][32, 48] == 1
