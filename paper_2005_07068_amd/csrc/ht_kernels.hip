@@ -1553,13 +1553,20 @@ __device__ __forceinline__ int self_item_particle(const int* s_off, int n_total,
 
 // NT: primitive types the model uses (3: spheres, cylinders, ellipsoids; kNumTypes: also
 // cones and elliptic cylinders), so a model without the latter keeps the smaller register
-// footprint.  (Forcing more wavefronts per SIMD than the natural register count allows
-// spills registers and measured slower.)  SELF: the launch builds its own work list (at most
+// footprint.  (Forcing more wavefronts per SIMD than the vector register count allows
+// spills vector registers and measured slower.)  SELF: the launch builds its own work list (at most
 // kSelfSched particles, no debug images); a variant of its own, so the larger launches keep
 // the dequeue loop without the self-scheduling code (which cost them about 5%).
+//
+// The work-list launches of the plain forward cast ask for eight wavefronts per SIMD: left to
+// itself the compiler needs more scalar registers than eight allow (seven fit), and the few
+// it then keeps in vector-register lanes are reloaded per item, outside the tile loop
+// (1.2 % off the two-hand frame; the self-scheduled launches, at most six workgroups per
+// CU, measured slower with the same request).
 template <bool GRAD, bool DEBUG, int NT, bool SELF>
-__global__ __launch_bounds__(kBlock) void raycast_kernel(EvalArgs a, Workspace ws,
-                                                      TypeMasks tm) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kBlock),
+                          amdgpu_waves_per_eu((GRAD || DEBUG || SELF) ? 1 : 8)))
+void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
   __shared__ float4 s_rec[HT_MAX_PRIM * (kRec / 4)];
   __shared__ int4 s_box[HT_MAX_PRIM];
   __shared__ float4 s_cap[HT_MAX_PRIM];
