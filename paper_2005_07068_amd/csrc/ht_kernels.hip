@@ -913,7 +913,9 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
           const float reach = fmaxf(r0, r1) * 1.0001f + kTileHalfDiag + 0.5f;
           const float dx = D1[0] - D0[0], dy = D1[1] - D0[1];
           const float vv = fmaf(dx, dx, dy * dy);
-          cap = make_float4(D0[0], D0[1], dx, dy);
+          // (the first disc's centre stored less the tile-centre offset 3.5 px, so the ray
+          // cast measures from a tile's corner pixel index)
+          cap = make_float4(D0[0] - 3.5f, D0[1] - 3.5f, dx, dy);
           capr = make_float2(vv > 0.0f ? fast_rcp(vv) : 0.0f, reach * reach);
         }
       }
@@ -1678,15 +1680,25 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
         const int4 b = s_box[kk];
         const float4 cp = s_cap[kk];
         const float2 cq = s_capr[kk];
-        bool ov = (k < n_prim) & (b.x <= x0 + kTile - 1) & (b.y >= x0) &
-                  (b.z <= y0 + kTile - 1) & (b.w >= y0);
-        if (ov) {
-          const float wx = (float)x0 + 3.5f - cp.x, wy = (float)y0 + 3.5f - cp.y;
+        // one ballot per comparison, combined on the scalar unit with the half's primitive
+        // lanes (a ballot of the combined condition routes its lane mask through a vector
+        // register and back)
+        const int left = n_prim - half * kWave;
+        uint64_t m = (left >= kWave ? ~0ull : (1ull << left) - 1ull) &
+                     __builtin_amdgcn_ballot_w64(b.x <= x0 + kTile - 1) &
+                     __builtin_amdgcn_ballot_w64(b.y >= x0) &
+                     __builtin_amdgcn_ballot_w64(b.z <= y0 + kTile - 1) &
+                     __builtin_amdgcn_ballot_w64(b.w >= y0);
+        if (m) {
+          // on every lane (a uniform branch), the result a lane mask combined on the scalar
+          // unit: no per-lane branch whose outcome would go through a vector register
+          // tile centre (x0 + 3.5, y0 + 3.5) minus the first disc's centre (cp: less 3.5)
+          const float wx = (float)x0 - cp.x, wy = (float)y0 - cp.y;
           const float sp = fminf(fmaxf(fmaf(wx, cp.z, wy * cp.w) * cq.x, 0.0f), 1.0f);
           const float ex = fmaf(-sp, cp.z, wx), ey = fmaf(-sp, cp.w, wy);
-          ov = fmaf(ex, ex, ey * ey) <= cq.y;
+          m &= __builtin_amdgcn_ballot_w64(fmaf(ex, ex, ey * ey) <= cq.y);
         }
-        mk[half] = __ballot(ov);
+        mk[half] = m;
       }
       if ((mk[0] | mk[1]) == 0ull) continue;
 
