@@ -1036,9 +1036,10 @@ __global__ __launch_bounds__(kBlock) void debug_fill_kernel(ht_debug dbg, size_t
 // ------------------------------------------------------------------------------------
 // ray-primitive intersections (FP32; centres carried as hi + lo pairs)
 //
-// The ray is x = t d with d = ((u - cx) sx, (v - cy) sy, sz) exact in FP32; depth = t sz.
-// Every test first forms the offset of the ray's closest-approach point from the primitive
-// centre, which is accurate because d is exact and the centre is a double-float pair; the
+// The ray is x = t d with d = ((u - cx) sx, (v - cy) sy, sz), formed in FP32 (to within a
+// rounding of its components) and then taken as exact; depth = t sz.  Every test first forms
+// the offset of the ray's closest-approach point from the primitive centre, which is accurate
+// because the tests use that same FP32 d and the centre is a double-float pair; the
 // hit decision and the half-chord then come from small, well-conditioned quantities.
 
 // A test may report a miss as ok with a NaN entry (the half-chord of a ray that misses is the
@@ -1600,6 +1601,9 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
   const int n_eval = a.n_frames * a.n_particles;
   int cur_p = -1;
   FrameSlot fs{};
+  // the lane's pixel offset within a tile as a ray component: ((lane & 7) - cx) sx and
+  // ((lane >> 3) - cy) sy, so that a tile's rays cost one multiply-add per component
+  float lane_dx = 0.0f, lane_dy = 0.0f;
   const PInfo& pi = s_pi;
 
   // the first item of every workgroup is its own index; later ones come from the dequeue
@@ -1639,6 +1643,8 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
       cur_p = p;
       __syncthreads();
       fs = uni(a.slots[uni(s_pi.slot)]);
+      lane_dx = ((float)(lane & 7) - fs.cx) * fs.sx;
+      lane_dy = ((float)(lane >> 3) - fs.cy) * fs.sy;
     }
     if (GRAD) {
       float* wr = &s_wr[wave][0][0][0];
@@ -1666,6 +1672,7 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
     for (int t = first + wave * gap; t < t_end; t += stride, walk.step(stride)) {
       const int tx = walk.tx(), ty = walk.ty();
       const int x0 = tx * kTile, y0 = ty * kTile;
+      const float x0f = (float)x0, y0f = (float)y0;
       // culling, one lane per primitive: screen box overlap, then the distance of the tile's
       // centre from the primitive's image segment
       // (the three loads are issued together, the index clamped, so no branch waits on LDS;
@@ -1693,7 +1700,7 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
           // on every lane (a uniform branch), the result a lane mask combined on the scalar
           // unit: no per-lane branch whose outcome would go through a vector register
           // tile centre (x0 + 3.5, y0 + 3.5) minus the first disc's centre (cp: less 3.5)
-          const float wx = (float)x0 - cp.x, wy = (float)y0 - cp.y;
+          const float wx = x0f - cp.x, wy = y0f - cp.y;
           const float sp = fminf(fmaxf(fmaf(wx, cp.z, wy * cp.w) * cq.x, 0.0f), 1.0f);
           const float ex = fmaf(-sp, cp.z, wx), ey = fmaf(-sp, cp.w, wy);
           m &= __builtin_amdgcn_ballot_w64(fmaf(ex, ex, ey * ey) <= cq.y);
@@ -1705,19 +1712,15 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
       const int tile_idx = ty * fs.TW + tx;
       const int u = x0 + (lane & 7), v = y0 + (lane >> 3);
       const uint32_t word = global_ptr(fs.words)[(size_t)tile_idx * kTilePx + lane];
-      // the tile's background sums, loaded with the words (by lane 0, which subtracts them
-      // after the tests) so that their latency overlaps the tests
-      float bg_td = 0.0f;
-      int bg_sk = 0;
-      if (lane == 0) {
-        bg_td = global_ptr(fs.tile_td)[tile_idx];
-        bg_sk = global_ptr(fs.tile_skin)[tile_idx];
-      }
+      // the tile's background sums, loaded with the words (one address for every lane) so
+      // that their latency overlaps the tests; lane 0 subtracts them after the tests
+      const float bg_td = global_ptr(fs.tile_td)[tile_idx];
+      const int bg_sk = global_ptr(fs.tile_skin)[tile_idx];
       const bool valid = (word & kValidBit) != 0;
       const float od = (float)(word & 0xFFFFu);
       const bool os = (word & kSkinBit) != 0;
-      const float dx = ((float)u - fs.cx) * fs.sx;
-      const float dy = ((float)v - fs.cy) * fs.sy;
+      const float dx = fmaf(x0f, fs.sx, lane_dx);
+      const float dy = fmaf(y0f, fs.sy, lane_dy);
       const float dz = fs.sz;
       const float dd = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
       const float inv_dd = fast_rcp(dd);
