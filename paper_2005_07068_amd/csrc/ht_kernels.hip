@@ -1664,7 +1664,8 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
     const int t_end = interleave ? n_tiles : min((c + 1) * tpi, n_tiles);
     const int stride = gap * kWavesPerBlock;
     double acc_td = 0.0;   // exact: the FP32 terms are multiples of 2^-15 mm
-    int acc_a = 0, acc_o = 0;
+    double acc_bg = 0.0;   // the tiles' background depth sums (the same on every lane)
+    int acc_a = 0, acc_o = 0;   // wavefront totals: popcounts of lane masks (scalar unit)
     const float* recs = reinterpret_cast<const float*>(s_rec);
 
     TileWalk walk;
@@ -1775,20 +1776,21 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
       const float diff = fabsf(od - rd);
       const float td = fminf(diff, kDClamp);
       const bool rm = hit && (diff < kDMatch || od == 0.0f);
-      if (valid) {
-        acc_td += (double)td;
-        acc_a += (os && rm) ? 1 : 0;
-        acc_o += (os || rm) ? 1 : 0;
+      acc_td += (double)(valid ? td : 0.0f);
+      {
+        // one ballot per condition, combined on the scalar unit
+        const uint64_t m_valid = __builtin_amdgcn_ballot_w64(valid);
+        const uint64_t m_os = __builtin_amdgcn_ballot_w64(os);
+        const uint64_t m_rm = __builtin_amdgcn_ballot_w64(rm);
+        acc_a += __builtin_popcountll(m_valid & m_os & m_rm);
+        acc_o += __builtin_popcountll(m_valid & (m_os | m_rm));
       }
       {
-        // read back from lane 0 only here (a convergent read, so the wait for the loads stays
-        // after the tests)
+        // read back here (a convergent read, so the wait for the loads stays after the tests)
         const float bgt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(bg_td)));
         const int bgs = __builtin_amdgcn_readfirstlane(bg_sk);
-        if (lane == 0) {
-          acc_td -= (double)bgt;
-          acc_o -= bgs;
-        }
+        acc_bg += (double)bgt;
+        acc_o -= bgs;
       }
       // the debug images have the host's W x H of the debug slot; a frame slot of another
       // size would write past them, so stores outside that extent are dropped
@@ -1846,9 +1848,7 @@ void raycast_kernel(EvalArgs a, Workspace ws, TypeMasks tm) {
       }
     }
 
-    acc_td = wave_sum(acc_td);
-    acc_a = wave_sum(acc_a);
-    acc_o = wave_sum(acc_o);
+    acc_td = wave_sum(acc_td) - acc_bg;
     if (lane == 0) {
       s_td[wave] = acc_td;
       s_a[wave] = acc_a;
