@@ -747,7 +747,7 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
       const double u[3] = {F[2], F[6], F[10]};
       // terms of the ray tests that do not depend on the pixel are formed here once, as the
       // same FP32 operations the tests would perform (so the tests' results are unchanged):
-      // products with the ray's z component sz, and the cylinder's mid-axis parameter
+      // products with the ray's z component sz
       if (typ == HT_SPHERE) {
         rec[3] = (float)(sz[0] * sz[0]);
         rec[7] = fs.sz * rec[2];
@@ -762,8 +762,13 @@ __global__ __launch_bounds__(kBlock, 4) void fk_kernel(EvalArgs a, Workspace ws)
         rec[11] = typ == HT_CONE ? (float)((r1 - r0) / L)
                                  : (float)(c[0] * u[0] + c[1] * u[1] + c[2] * u[2]);
         if (typ == HT_CYLINDER) {
+          // sz uz, then the part of the cap centre perpendicular to the axis (q = c - (c.u) u:
+          // q_z sz, q_x, q_y), whose product with d is the side reference's numerator
+          const double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
           rec[16] = fs.sz * rec[10];
-          rec[17] = fmaf(0.5f, rec[7], rec[11]);
+          rec[17] = fs.sz * (float)(c[2] - cu * u[2]);
+          rec[18] = (float)(c[0] - cu * u[0]);
+          rec[19] = (float)(c[1] - cu * u[1]);
         }
       } else {
         // ellipsoid: Q = R diag(1/s^2) R^T with R the rotation part of F; elliptic cylinder:
@@ -1159,7 +1164,8 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   const bool par = A < 1.0e-6f * dd;          // ray within ~1e-3 rad of the axis
   const float inv_da = fast_rcp(da);
   const float invA = fast_rcp(A);
-  const float t_side = fmaf(px, r[0], fmaf(py, r[1], pz * r[2])) * invA;
+  // (p . c = d . q: q, the cap centre's part perpendicular to the axis, is in r[17..19])
+  const float t_side = fmaf(dx, r[18], fmaf(dy, r[19], r[17])) * invA;
   {
     // every lane first as if its ray were not near-parallel to the axis: the side-centred
     // reference, and a miss of the side surface (h2 < 0) gives a NaN half-chord, which fails
@@ -1203,7 +1209,7 @@ __device__ __forceinline__ void cylinder_test(const float* r, float dx, float dy
   // path, which recomputes every lane
   if (__builtin_expect(__ballot(par) == 0ull, 1)) return;
   // general path: near-parallel rays take the reference at the slab's middle
-  const float t_mid = r[17] * inv_da;                    // r[17] = r[11] + L / 2
+  const float t_mid = fmaf(0.5f, L, r[11]) * inv_da;    // r[11] = c . u
   const float tr = par ? t_mid : t_side;
   const float vx = fmaf(tr, dx, -r[0]) - r[4];
   const float vy = fmaf(tr, dy, -r[1]) - r[5];
